@@ -1,0 +1,191 @@
+/*
+ * stf.h - C ABI of the MI355X (gfx950) stochastic texture filtering library.
+ *
+ * Implements stochastic texture filtering (STF) with sample reuse under
+ * magnification from Wronski, Pharr and Akenine-Moeller, "Improved
+ * Stochastic Texture Filtering Through Sample Reuse" (2025):
+ *   - one-tap STF: each pixel picks one texel with probability equal to its
+ *     filter weight and returns it unweighted (Sec. 2.2, Sec. S1);
+ *   - sample reuse: pixels of one 8x8 screen tile (one 64-lane wavefront)
+ *     exchange their picked texels and combine them with the weighted
+ *     importance sampling estimator of Eq. (14) (Sec. 4.2, Sec. 4.5);
+ *   - the deterministic filter of Eq. (3) as ground truth;
+ *   - the adjoint of Eq. (14) with respect to the texels.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers named "device" are HIP device pointers owned by the caller;
+ *     the library never frees or retains them. Descriptor structs and the
+ *     arrays of output pointers are host memory read during the call only.
+ *   - Every call validates its arguments on the host before anything is
+ *     enqueued; on error nothing is launched, the return value is negative
+ *     and stf_last_error() describes the problem.
+ *   - Work is enqueued asynchronously on `hip_stream` (a hipStream_t; NULL
+ *     means the default stream). No call synchronises or allocates.
+ *   - The forward outputs are a pure function of the inputs, seed, frame and
+ *     texture slot index.
+ *   - Screen layout: UV is FP32 [height][width][2] row-major (u then v);
+ *     outputs are FP32 [height][width][C] row-major, C = channels of the
+ *     texture format; pixel (px, py) has its centre at (px+1/2, py+1/2).
+ *   - Texture layout: row y starts at data + y * pitch_bytes; texels are
+ *     tightly packed within a row. Texel (0,0) is the first texel.
+ *   - Texel-space coordinate of a texture coordinate u on a texture of
+ *     size W: x = u * W - 0.5 in FP32 (Sec. 4.5 listing); the sub-texel
+ *     fraction is quantised to 16 bits.
+ *   - Addressing: STF_WRAP on power-of-two textures of 4..32768 texels per
+ *     axis; texel identity is the index modulo the texture size.
+ */
+#ifndef STF_H
+#define STF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STF_VERSION 1
+#define STF_MAX_TEXTURES 4
+#define STF_MAX_SCREEN 32768
+
+typedef enum stf_status {
+    STF_OK = 0,
+    STF_EINVAL = -1,        /* bad pointer, size, enum value or layout */
+    STF_EUNSUPPORTED = -2,  /* valid request this build does not implement */
+    STF_EHIP = -3           /* the HIP runtime reported an error at launch */
+} stf_status;
+
+typedef enum stf_filter_kind {
+    STF_BILINEAR = 0,        /* tent filter, 2x2 support (Sec. S6) */
+    STF_BICUBIC_BSPLINE = 1  /* uniform cubic B-spline, 4x4 support (Sec. 5.4) */
+} stf_filter_kind;
+
+typedef enum stf_format {      /* channels, bytes per texel, decode */
+    STF_RGBA8_UNORM = 0,       /* 4, 4,  byte / 255 (linear, no sRGB) */
+    STF_RGBA16F = 1,           /* 4, 8,  IEEE half, exact */
+    STF_RG16F = 2,             /* 2, 4,  IEEE half, exact */
+    STF_R8_UNORM = 3,          /* 1, 1,  byte / 255 */
+    STF_RGBA32F = 4,           /* 4, 16, exact */
+    STF_R32F = 5               /* 1, 4,  exact */
+} stf_format;
+
+typedef enum stf_address {
+    STF_WRAP = 0
+} stf_address;
+
+/* Sharing footprints S(c) on the tile pixel coordinates (lx, ly) in [0,8)^2
+ * of the 8x8 screen tile that one wavefront processes (Sec. 4.3). Every
+ * footprint contains the pixel itself. Windows keep their size at tile edges
+ * by shifting inward. Pixels outside the screen take part in no footprint. */
+typedef enum stf_footprint {
+    STF_FP_SELF = 0,        /* {c}: reduces exactly to one-tap STF */
+    STF_FP_QUAD2X2 = 1,     /* 2x2 quad with even origin (Sec. 2.3, "2x2q") */
+    STF_FP_WAVE2X2 = 2,     /* 2x2 window, origin l - ((l' + (l >> 1)) & 1) per axis ("2x2w") */
+    STF_FP_SQUARE3X3 = 3,   /* origin clamp(l - 1, 0, 5) per axis */
+    STF_FP_SQUARE4X4 = 4,   /* origin clamp(l - 1, 0, 4) per axis */
+    STF_FP_TILE8X8 = 5,     /* all 64 pixels of the tile (the whole wavefront) */
+    STF_FP_LUT = 6          /* caller table, see stf_reuse */
+} stf_footprint;
+
+typedef struct stf_texture {
+    const void* data;       /* device, texel payload */
+    int32_t width;          /* texels */
+    int32_t height;         /* texels */
+    int64_t pitch_bytes;    /* >= width * bytes per texel, multiple of it */
+    int32_t format;         /* stf_format */
+    int32_t reserved;       /* must be 0 */
+} stf_texture;
+
+typedef struct stf_screen {
+    const float* uv;        /* device, FP32 [height][width][2] */
+    int32_t width;          /* pixels, 1..STF_MAX_SCREEN */
+    int32_t height;         /* pixels, 1..STF_MAX_SCREEN */
+} stf_screen;
+
+typedef struct stf_params {
+    int32_t filter;         /* stf_filter_kind */
+    int32_t address;        /* stf_address */
+    uint32_t seed;          /* random stream: pcg4d(px, py, frame, seed + (slot>>1)*0x9E3779B9) */
+    uint32_t frame;
+} stf_params;
+
+typedef struct stf_reuse {
+    int32_t footprint;      /* stf_footprint */
+    int32_t lut_k;          /* STF_FP_LUT only: entries per pixel, 1..64 */
+    const uint8_t* lut;     /* STF_FP_LUT only: device [64][lut_k] row-major tile
+                               pixel ids (ly*8+lx, low 6 bits used); an entry
+                               equal to the pixel itself is ignored, the pixel
+                               is always a member; repeated entries count
+                               repeatedly. NULL for other footprints. */
+} stf_reuse;
+
+/*
+ * One-tap STF (Sec. 2.2; Sec. S1 shows the importance-sampling estimator
+ * reduces to returning the picked texel). For each texture slot t each pixel
+ * picks one texel of its filter support with probability equal to the filter
+ * weight, using two uniforms from the hash of (px, py, frame, seed, t), and
+ * writes the decoded texel.
+ *   tex    host array of ntex descriptors (1 <= ntex <= STF_MAX_TEXTURES)
+ *   out    host array of ntex device pointers, out[t] FP32 [H][W][C_t]
+ *   sel    optional device int32 [ntex][H][W][2]: picked texel (x, y),
+ *          wrapped into [0, size); NULL to skip
+ * Returns STF_OK or a negative stf_status.
+ */
+int stf_filter(const stf_texture* tex, int32_t ntex, const stf_screen* scr,
+               const stf_params* p, float* const* out, int32_t* sel, void* hip_stream);
+
+/*
+ * STF with sample reuse (Sec. 4). Each pixel c picks its texel exactly as
+ * stf_filter does (same `sel`), then combines the picks of the members i of
+ * its footprint with Eq. (14):
+ *     out_c = sum_i w_i T_i / sum_i w_i,   w_i = f_c(x_i) / p_i(x_i),
+ * where f_c is c's filter weight at texel x_i and p_i the probability with
+ * which i picked it; w_i = 0 for texels outside c's support (skipped, never
+ * multiplied) and w_c = 1, so with no useful neighbour out_c equals the
+ * one-tap STF value (Sec. 4.5). The result always lies within the range of
+ * the texels under c's own filter (Eq. (5)).
+ *   r      host descriptor of the footprint (and device LUT for STF_FP_LUT)
+ * Other arguments as stf_filter.
+ */
+int stf_filter_reuse(const stf_texture* tex, int32_t ntex, const stf_screen* scr,
+                     const stf_params* p, const stf_reuse* r, float* const* out,
+                     int32_t* sel, void* hip_stream);
+
+/*
+ * Deterministic filtered value, Eq. (3): sum over the filter support of
+ * weight * texel, with the same coordinates and 16-bit fractions as the
+ * stochastic paths (ground truth for PSNR; the full-filter cost).
+ * p->seed and p->frame are ignored.
+ */
+int stf_filter_reference(const stf_texture* tex, int32_t ntex, const stf_screen* scr,
+                         const stf_params* p, float* const* out, void* hip_stream);
+
+/*
+ * Adjoint of stf_filter_reuse with respect to the texels. The weights of
+ * Eq. (14) depend only on UVs and random numbers, so the output is linear in
+ * the texels: out_c = sum_i a_ci T[x_i], a_ci = w_i / sum_j w_j, and
+ *     dL/dT[x] += sum_c sum_{i in S(c), x_i = x} a_ci dL/dout_c.
+ *   tex    descriptors of the forward textures (data may be NULL: only size
+ *          and format are used)
+ *   dout   host array of ntex device pointers, FP32 [H][W][C_t]
+ *   dtex   host array of ntex device pointers, FP32 [tex height][tex width][C_t],
+ *          dense (pitch = width * C_t * 4); ACCUMULATED into (+=), so clear
+ *          it first for a plain gradient. Summation order is not fixed
+ *          (floating-point atomics): results agree to rounding, not bits.
+ * Same p and r as the forward call being differentiated.
+ */
+int stf_backward(const stf_texture* tex, int32_t ntex, const stf_screen* scr,
+                 const stf_params* p, const stf_reuse* r, const float* const* dout,
+                 float* const* dtex, void* hip_stream);
+
+/* Message for the last non-OK status returned on this thread ("" if none).
+ * The pointer stays valid until the next call on this thread. */
+const char* stf_last_error(void);
+
+/* STF_VERSION of the built library. */
+int stf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STF_H */

@@ -1,0 +1,262 @@
+"""Python binding of libstf.so: stochastic texture filtering with sample reuse
+on MI355X (gfx950).
+
+Argument marshalling only: every step of the filtering runs in the HIP
+kernels behind the C ABI of include/stf.h. PyTorch provides device memory and
+the stream; there is no CPU fallback. Importing works without a GPU; calling
+anything without the built library raises.
+
+Textures are torch tensors [H, W, C] on the GPU: uint8 with C=4 (RGBA8 UNORM)
+or C=1 (R8 UNORM), float16 with C=4 (RGBA16F) or C=2 (RG16F), float32 with
+C=4 (RGBA32F) or C=1 (R32F). UV is float32 [H, W, 2]. Outputs are float32
+[H, W, C] per texture.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+__all__ = [
+    "BILINEAR", "BICUBIC", "FOOTPRINTS", "FORMATS", "library", "lib_path", "version",
+    "filter", "filter_reuse", "filter_reference", "backward", "StfError",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(HERE, "libstf.so")
+
+BILINEAR = 0
+BICUBIC = 1
+FILTERS = {"bilinear": BILINEAR, "bicubic": BICUBIC}
+FOOTPRINTS = {"self": 0, "quad2x2": 1, "wave2x2": 2, "square3x3": 3, "square4x4": 4, "tile8x8": 5, "lut": 6}
+# (torch dtype name, channels) -> (stf_format, bytes per texel)
+FORMATS = {
+    ("uint8", 4): (0, 4), ("float16", 4): (1, 8), ("float16", 2): (2, 4),
+    ("uint8", 1): (3, 1), ("float32", 4): (4, 16), ("float32", 1): (5, 4),
+}
+STF_MAX_TEXTURES = 4
+
+
+class StfError(RuntimeError):
+    pass
+
+
+class Texture(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("pitch_bytes", ctypes.c_int64), ("format", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Screen(ctypes.Structure):
+    _fields_ = [("uv", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("filter", ctypes.c_int32), ("address", ctypes.c_int32),
+                ("seed", ctypes.c_uint32), ("frame", ctypes.c_uint32)]
+
+
+class Reuse(ctypes.Structure):
+    _fields_ = [("footprint", ctypes.c_int32), ("lut_k", ctypes.c_int32), ("lut", ctypes.c_void_p)]
+
+
+_lib = None
+_SYMBOLS = ("stf_filter", "stf_filter_reuse", "stf_filter_reference", "stf_backward",
+            "stf_last_error", "stf_version")
+
+
+def library() -> ctypes.CDLL:
+    """Load libstf.so (built in-tree by build.py). Raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(lib_path):
+            raise StfError(f"{lib_path} is missing: build it with paper_2504_05562_amd/build.py")
+        lib = ctypes.CDLL(lib_path)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        tex_args = [P(Texture), ctypes.c_int32, P(Screen), P(Params)]
+        lib.stf_filter.argtypes = tex_args + [P(vp), vp, vp]
+        lib.stf_filter_reuse.argtypes = tex_args + [P(Reuse), P(vp), vp, vp]
+        lib.stf_filter_reference.argtypes = tex_args + [P(vp), vp]
+        lib.stf_backward.argtypes = tex_args + [P(Reuse), P(vp), P(vp), vp]
+        for name in ("stf_filter", "stf_filter_reuse", "stf_filter_reference", "stf_backward", "stf_version"):
+            getattr(lib, name).restype = ctypes.c_int
+        lib.stf_last_error.restype = ctypes.c_char_p
+        lib.stf_last_error.argtypes = []
+        _lib = lib
+    return _lib
+
+
+def version() -> int:
+    return library().stf_version()
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        msg = library().stf_last_error().decode()
+        raise StfError(f"stf status {rc}: {msg}")
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _texture_descs(textures: Sequence, need_data: bool = True):
+    if not 1 <= len(textures) <= STF_MAX_TEXTURES:
+        raise ValueError(f"1..{STF_MAX_TEXTURES} textures expected")
+    arr = (Texture * len(textures))()
+    chans = []
+    for i, t in enumerate(textures):
+        if t.dim() != 3:
+            raise ValueError("texture tensors are [H, W, C]")
+        key = (str(t.dtype).replace("torch.", ""), int(t.shape[2]))
+        if key not in FORMATS:
+            raise ValueError(f"unsupported texture dtype/channels {key}")
+        fmt, bpp = FORMATS[key]
+        if need_data:
+            if not t.is_cuda:
+                raise ValueError("textures must be GPU tensors")
+            C, W = int(t.shape[2]), int(t.shape[1])
+            if (C > 1 and t.stride(2) != 1) or (W > 1 and t.stride(1) != C):
+                raise ValueError("texels must be packed within a row")
+        arr[i].data = t.data_ptr() if need_data else None
+        arr[i].width = int(t.shape[1])
+        arr[i].height = int(t.shape[0])
+        arr[i].pitch_bytes = int(t.stride(0)) * t.element_size()
+        arr[i].format = fmt
+        arr[i].reserved = 0
+        chans.append(int(t.shape[2]))
+    return arr, chans
+
+
+def _screen(uv):
+    import torch
+    if uv.dtype != torch.float32 or uv.dim() != 3 or uv.shape[2] != 2 or not uv.is_cuda or not uv.is_contiguous():
+        raise ValueError("uv must be a contiguous float32 GPU tensor [H, W, 2]")
+    return Screen(uv.data_ptr(), int(uv.shape[1]), int(uv.shape[0]))
+
+
+def _params(filter, seed, frame):
+    f = FILTERS[filter] if isinstance(filter, str) else int(filter)
+    return Params(f, 0, int(seed) & 0xFFFFFFFF, int(frame) & 0xFFFFFFFF)
+
+
+def _outputs(uv, chans, out=None):
+    import torch
+    H, W = int(uv.shape[0]), int(uv.shape[1])
+    if out is None:
+        out = [torch.empty((H, W, c), dtype=torch.float32, device=uv.device) for c in chans]
+    ptrs = (ctypes.c_void_p * len(out))(*[o.data_ptr() for o in out])
+    return out, ptrs
+
+
+def _reuse(footprint, lut):
+    fp = FOOTPRINTS[footprint] if isinstance(footprint, str) else int(footprint)
+    if lut is None:
+        return Reuse(fp, 0, None)
+    return Reuse(fp, int(lut.shape[1]), lut.data_ptr())
+
+
+def filter(textures, uv, filter="bicubic", seed=0, frame=0, sel=False, out=None, stream=None):
+    """One-tap STF (stf_filter). Returns a list of outputs, plus the int32
+    selection tensor [ntex, H, W, 2] if sel=True."""
+    import torch
+    lib = library()
+    descs, chans = _texture_descs(textures)
+    scr = _screen(uv)
+    prm = _params(filter, seed, frame)
+    out, ptrs = _outputs(uv, chans, out)
+    s = torch.empty((len(textures),) + tuple(uv.shape[:2]) + (2,), dtype=torch.int32, device=uv.device) if sel else None
+    _check(lib.stf_filter(descs, len(textures), ctypes.byref(scr), ctypes.byref(prm), ptrs,
+                          ctypes.c_void_p(s.data_ptr() if s is not None else None), _stream_handle(stream)))
+    return (out, s) if sel else out
+
+
+def filter_reuse(textures, uv, footprint="tile8x8", filter="bicubic", seed=0, frame=0, lut=None,
+                 sel=False, out=None, stream=None):
+    """STF with sample reuse (stf_filter_reuse). `lut` is a uint8 GPU tensor
+    [64, K] of tile pixel ids for footprint='lut'."""
+    import torch
+    lib = library()
+    descs, chans = _texture_descs(textures)
+    scr = _screen(uv)
+    prm = _params(filter, seed, frame)
+    r = _reuse(footprint, lut)
+    out, ptrs = _outputs(uv, chans, out)
+    s = torch.empty((len(textures),) + tuple(uv.shape[:2]) + (2,), dtype=torch.int32, device=uv.device) if sel else None
+    _check(lib.stf_filter_reuse(descs, len(textures), ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(r), ptrs,
+                                ctypes.c_void_p(s.data_ptr() if s is not None else None), _stream_handle(stream)))
+    return (out, s) if sel else out
+
+
+def filter_reference(textures, uv, filter="bicubic", out=None, stream=None):
+    """Deterministic filter of Eq. (3) (stf_filter_reference)."""
+    lib = library()
+    descs, chans = _texture_descs(textures)
+    scr = _screen(uv)
+    prm = _params(filter, 0, 0)
+    out, ptrs = _outputs(uv, chans, out)
+    _check(lib.stf_filter_reference(descs, len(textures), ctypes.byref(scr), ctypes.byref(prm), ptrs,
+                                    _stream_handle(stream)))
+    return out
+
+
+def backward(textures, uv, grads, footprint="tile8x8", filter="bicubic", seed=0, frame=0, lut=None,
+             dtex=None, stream=None):
+    """Adjoint of filter_reuse (stf_backward): accumulates dL/dT into `dtex`
+    (float32 [H_t, W_t, C] per texture; zero-initialised if not given)."""
+    import torch
+    lib = library()
+    descs, chans = _texture_descs(textures)
+    scr = _screen(uv)
+    prm = _params(filter, seed, frame)
+    r = _reuse(footprint, lut)
+    if dtex is None:
+        dtex = [torch.zeros((int(t.shape[0]), int(t.shape[1]), c), dtype=torch.float32, device=uv.device)
+                for t, c in zip(textures, chans)]
+    for g in grads:
+        if g.dtype != torch.float32 or not g.is_contiguous():
+            raise ValueError("grads must be contiguous float32")
+    gp = (ctypes.c_void_p * len(grads))(*[g.data_ptr() for g in grads])
+    dp = (ctypes.c_void_p * len(dtex))(*[d.data_ptr() for d in dtex])
+    _check(lib.stf_backward(descs, len(textures), ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(r), gp, dp,
+                            _stream_handle(stream)))
+    return dtex
+
+
+def _autograd_function():
+    import torch
+
+    class STFReuse(torch.autograd.Function):
+        """Differentiable reuse STF of one texture (float32 [H, W, C], C in
+        {1, 4}): forward = stf_filter_reuse, backward = stf_backward. The
+        weights depend only on UV and random numbers, so the gradient with
+        respect to UV is not defined (returned as None)."""
+
+        @staticmethod
+        def forward(ctx, texture, uv, footprint, filter, seed, frame):
+            ctx.save_for_backward(texture, uv)
+            ctx.cfg = (footprint, filter, seed, frame)
+            return filter_reuse([texture.detach()], uv.detach(), footprint, filter, seed, frame)[0]
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            texture, uv = ctx.saved_tensors
+            footprint, filt, seed, frame = ctx.cfg
+            g = backward([texture], uv, [grad_out.contiguous().float()], footprint, filt, seed, frame)[0]
+            return g.view_as(texture), None, None, None, None, None
+
+    return STFReuse
+
+
+_STFReuse = None
+
+
+def stf_reuse_autograd(texture, uv, footprint="tile8x8", filter="bicubic", seed=0, frame=0):
+    """torch.autograd entry: reuse STF of a float32 texture, differentiable
+    with respect to the texels."""
+    global _STFReuse
+    if _STFReuse is None:
+        _STFReuse = _autograd_function()
+    return _STFReuse.apply(texture, uv, footprint, filter, seed, frame)

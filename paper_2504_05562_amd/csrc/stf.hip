@@ -1,0 +1,755 @@
+// STF with sample reuse on gfx950: forward, reference and adjoint kernels
+// plus the host side of the C ABI declared in include/stf.h.
+//
+// One wavefront processes one 8x8 screen tile; a 256-thread workgroup holds
+// four tiles side by side (32x8 pixels), so every UV row segment a group
+// reads is 256 contiguous bytes. Per pixel and texture slot a kernel:
+//   1. loads UV once (shared by all slots),
+//   2. splits the texel-space coordinate and forms per-axis weights,
+//   3. draws two uniforms from the pcg4d hash and picks one texel per axis
+//      by exact integer CDF inversion (one-tap STF),
+//   4. fetches and decodes that single texel,
+//   5. (reuse) exchanges picks inside the tile and evaluates Eq. (14) in the
+//      difference form  out = T_c + sum_i w_i (T_i - T_c) / sum_i w_i,
+//      which equals Eq. (14) and keeps constant regions and the no-overlap
+//      fallback exact in FP32,
+//   6. stores FP32 colours with non-temporal stores.
+// Exchange strategies:
+//   quad2x2  DPP quad_perm moves, no LDS;
+//   tile8x8  texel bins in LDS: every lane adds its 1/p to the bin of its
+//            texel (N_j = sum over picks of texel j of 1/p_i), then each
+//            pixel visits only the N x N bins of its own support:
+//            sum_i w_i (T_i - T_c) = sum_j f_c(j) N_j (T_j - T_c);
+//   others   per-lane records in LDS read through the footprint member
+//            table (windows computed, or the caller's LUT).
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "stf_device.h"
+
+namespace stf {
+
+enum Mode { kModeStf = 0, kModeQuad = 1, kModeRecords = 2, kModeBins = 3 };
+
+// LDS per wavefront: bins (kBins floats of N + kBins * 4 floats of texels)
+// or records (64 x {s, r} + 64 x 4 floats); the larger one sets the size.
+constexpr int kLdsFloatsPerWave = kBins * 5;
+
+struct Pixel {
+    int px, py;          // screen pixel
+    int lx, ly;          // pixel inside the tile
+    int q;               // row-major tile pixel id ly*8+lx
+    bool valid;          // inside the screen
+    float u, v;
+};
+
+// Footprint member m of tile pixel (lx, ly) as a row-major tile pixel id.
+__device__ __forceinline__ int member_id(int fp, int lx, int ly, int m, const uint8_t* lut, int lut_k, int q) {
+    switch (fp) {
+    case STF_FP_QUAD2X2:
+        return ((ly & ~1) + (m >> 1)) * 8 + (lx & ~1) + (m & 1);
+    case STF_FP_WAVE2X2: {
+        const int ox = min(max(lx - ((ly + (lx >> 1)) & 1), 0), 6);
+        const int oy = min(max(ly - ((lx + (ly >> 1)) & 1), 0), 6);
+        return (oy + (m >> 1)) * 8 + ox + (m & 1);
+    }
+    case STF_FP_SQUARE3X3: {
+        const int ox = min(max(lx - 1, 0), 5), oy = min(max(ly - 1, 0), 5);
+        const int my = m / 3;
+        return (oy + my) * 8 + ox + (m - 3 * my);
+    }
+    case STF_FP_SQUARE4X4: {
+        const int ox = min(max(lx - 1, 0), 4), oy = min(max(ly - 1, 0), 4);
+        return (oy + (m >> 2)) * 8 + ox + (m & 3);
+    }
+    case STF_FP_LUT:
+        return lut[q * lut_k + m] & 63;
+    default:  // STF_FP_TILE8X8
+        return m;
+    }
+}
+
+__device__ __forceinline__ int footprint_size(int fp, int lut_k) {
+    switch (fp) {
+    case STF_FP_QUAD2X2: case STF_FP_WAVE2X2: return 4;
+    case STF_FP_SQUARE3X3: return 9;
+    case STF_FP_SQUARE4X4: return 16;
+    case STF_FP_LUT: return lut_k;
+    default: return 64;
+    }
+}
+
+// Accumulate the contribution of one shared pick (canonical texel (sx, sy)
+// packed as sx | sy << 16, reciprocal PMF r, texel Ti) into pixel c's sums.
+template <int N, int C>
+__device__ __forceinline__ void accumulate(uint32_t s, float r, const float* Ti, int bx, int by,
+                                           uint32_t mx, uint32_t my, const float* wx, const float* wy,
+                                           const float* Tc, float& B, float* acc) {
+    const uint32_t dx = ((s & 0xFFFFu) - (uint32_t)bx) & mx;
+    const uint32_t dy = ((s >> 16) - (uint32_t)by) & my;
+    if (dx < (uint32_t)N && dy < (uint32_t)N) {      // outside the own support: skipped
+        float fx = wx[0], fy = wy[0];
+#pragma unroll
+        for (int k = 1; k < N; ++k) {
+            fx = (dx == (uint32_t)k) ? wx[k] : fx;
+            fy = (dy == (uint32_t)k) ? wy[k] : fy;
+        }
+        const float w = fx * fy * r;
+        B += w;
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = fmaf(w, Ti[c] - Tc[c], acc[c]);
+    }
+}
+
+// Receive the pick of quad partner lane^X through DPP and accumulate it.
+template <int X, int N, int C>
+__device__ __forceinline__ void quad_step(uint32_t s, float r, const float* Tv, int bx, int by, uint32_t mx,
+                                          uint32_t my, const float* wx, const float* wy, float& B, float* acc) {
+    float Ti[C];
+    const uint32_t si = quad_xor<X>(s);
+    const float ri = quad_xor<X>(r);
+#pragma unroll
+    for (int c = 0; c < C; ++c) Ti[c] = quad_xor<X>(Tv[c]);
+    accumulate<N, C>(si, ri, Ti, bx, by, mx, my, wx, wy, Tv, B, acc);
+}
+
+template <int FILT, int MODE, int C>
+__device__ __forceinline__ void slot_pass(const Args& a, int slot, const Pixel& P, float* lds) {
+    using Fl = Filter<FILT>;
+    constexpr int N = Fl::N;
+    const TexArg t = a.tex[slot];
+    const int lane = lane_id();
+
+    int i0x, Fx, i0y, Fy;
+    texel_split(P.u, t.w, i0x, Fx);
+    texel_split(P.v, t.h, i0y, Fy);
+    const uint2 h = slot_hash((uint32_t)P.px, (uint32_t)P.py, slot, a.seed, a.frame);
+    float wx[N], wy[N];
+    const int kx = Fl::pick(h.x, Fx, wx);
+    const int ky = Fl::pick(h.y, Fy, wy);
+    const int bx = i0x - Fl::DELTA, by = i0y - Fl::DELTA;    // first texel of the support
+    const uint32_t mx = (uint32_t)t.w - 1u, my = (uint32_t)t.h - 1u;
+    const uint32_t sx = (uint32_t)(bx + kx) & mx;
+    const uint32_t sy = (uint32_t)(by + ky) & my;
+    const Texel<C> T = fetch<C>(t, sx, sy);
+    const int64_t pix = (int64_t)P.py * a.sw + P.px;
+
+    if (a.sel != nullptr && P.valid) {
+        int2* sp = reinterpret_cast<int2*>(a.sel) + ((int64_t)slot * a.sh * a.sw + pix);
+        *sp = make_int2((int)sx, (int)sy);
+    }
+    if constexpr (MODE == kModeStf) {
+        if (P.valid) store_out<C>(a.out[slot], pix, T.v);
+        return;
+    } else {
+        float pk_x = wx[0], pk_y = wy[0];
+#pragma unroll
+        for (int k = 1; k < N; ++k) {
+            pk_x = (kx == k) ? wx[k] : pk_x;
+            pk_y = (ky == k) ? wy[k] : pk_y;
+        }
+        // invalid pixels share a pick of weight zero
+        const float r = P.valid ? __frcp_rn(pk_x * pk_y) : 0.0f;
+        float Tv[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) Tv[c] = P.valid ? T.v[c] : 0.0f;
+        const uint32_t s = sx | (sy << 16);
+
+        float B = 1.0f;            // own pick: w_c = f_c / p_c = 1 (Sec. 4.5)
+        float acc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+
+        if constexpr (MODE == kModeQuad) {
+            quad_step<1, N, C>(s, r, Tv, bx, by, mx, my, wx, wy, B, acc);
+            quad_step<2, N, C>(s, r, Tv, bx, by, mx, my, wx, wy, B, acc);
+            quad_step<3, N, C>(s, r, Tv, bx, by, mx, my, wx, wy, B, acc);
+        } else {
+            bool use_bins = false;
+            if constexpr (MODE == kModeBins) {
+                // Bin window: kBinG x kBinG texels around the support of lane 0.
+                constexpr int margin = (kBinG - N) / 2;
+                const int base_x = __builtin_amdgcn_readfirstlane(bx) - margin;
+                const int base_y = __builtin_amdgcn_readfirstlane(by) - margin;
+                const uint32_t rx = (uint32_t)(bx - base_x) & mx;
+                const uint32_t ry = (uint32_t)(by - base_y) & my;
+                const bool fits = !P.valid || (rx <= (uint32_t)(kBinG - N) && ry <= (uint32_t)(kBinG - N));
+                use_bins = (t.w >= kBinG) && (t.h >= kBinG) && (__builtin_amdgcn_ballot_w64(!fits) == 0);
+                if (use_bins) {
+                    float* Nb = lds;                 // [kBins] sum of 1/p per texel
+                    float* Tb = lds + kBins;         // [kBins][C] texel values
+                    // clear: each lane zeroes 4 bins of N and 4 bins of T
+                    reinterpret_cast<float4*>(Nb)[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                    for (int i = 0; i < C; ++i)
+                        reinterpret_cast<float4*>(Tb)[lane * C + i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    wave_lds_sync();
+                    if (P.valid) {
+                        const int bin = (int)(ry + ky) * kBinG + (int)(rx + kx);
+                        atomicAdd(&Nb[bin], r);
+#pragma unroll
+                        for (int c = 0; c < C; ++c) Tb[bin * C + c] = Tv[c];
+                    }
+                    wave_lds_sync();
+                    B = 0.0f;                        // the own pick is in the bins
+#pragma unroll
+                    for (int b = 0; b < N; ++b) {
+#pragma unroll
+                        for (int aa = 0; aa < N; ++aa) {
+                            const int idx = (int)(ry + b) * kBinG + (int)rx + aa;
+                            const float w = wx[aa] * wy[b] * Nb[idx];
+                            B += w;
+#pragma unroll
+                            for (int c = 0; c < C; ++c) acc[c] = fmaf(w, Tb[idx * C + c] - Tv[c], acc[c]);
+                        }
+                    }
+                    wave_lds_sync();                 // reads done before the next slot reuses LDS
+                }
+            }
+            if (!use_bins) {
+                uint2* meta = reinterpret_cast<uint2*>(lds);        // [64] {s, r}
+                float4* val = reinterpret_cast<float4*>(lds + 128);  // [64] texel
+                meta[P.q] = make_uint2(s, __float_as_uint(r));
+                float pad[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int c = 0; c < C; ++c) pad[c] = Tv[c];
+                val[P.q] = make_float4(pad[0], pad[1], pad[2], pad[3]);
+                wave_lds_sync();
+                const int fp = (MODE == kModeBins) ? (int)STF_FP_TILE8X8 : a.footprint;
+                const int K = footprint_size(fp, a.lut_k);
+                for (int m = 0; m < K; ++m) {
+                    const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
+                    if (j == P.q) continue;          // the own pick is already counted
+                    const uint2 mj = meta[j];
+                    const float4 vj = val[j];
+                    const float Ti[4] = {vj.x, vj.y, vj.z, vj.w};
+                    accumulate<N, C>(mj.x, __uint_as_float(mj.y), Ti, bx, by, mx, my, wx, wy, Tv, B, acc);
+                }
+                wave_lds_sync();
+            }
+        }
+        if (P.valid) {
+            float o[C];
+            const float inv = 1.0f / B;
+#pragma unroll
+            for (int c = 0; c < C; ++c) o[c] = fmaf(acc[c], inv, Tv[c]);
+            store_out<C>(a.out[slot], pix, o);
+        }
+    }
+}
+
+__device__ __forceinline__ bool setup_pixel(const Args& a, Pixel& P) {
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    lane_pixel(lane, P.lx, P.ly);
+    P.q = P.ly * 8 + P.lx;
+    const int tx = blockIdx.x * kWavesPerGroup + wave;
+    if (tx * kTile >= a.sw) return false;                    // whole tile off screen
+    P.px = tx * kTile + P.lx;
+    P.py = blockIdx.y * kTile + P.ly;
+    P.valid = (P.px < a.sw) && (P.py < a.sh);
+    const int cx = min(P.px, a.sw - 1), cy = min(P.py, a.sh - 1);
+    const v2f uv = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(a.uv) + ((int64_t)cy * a.sw + cx));
+    P.u = uv.x;
+    P.v = uv.y;
+    return true;
+}
+
+template <int FILT, int MODE>
+__global__ __launch_bounds__(kThreads) void forward_kernel(Args a) {
+    __shared__ __align__(16) float lds_all[kWavesPerGroup * kLdsFloatsPerWave];
+    Pixel P;
+    if (!setup_pixel(a, P)) return;
+    float* lds = lds_all + (threadIdx.x >> 6) * kLdsFloatsPerWave;
+    for (int slot = 0; slot < a.ntex; ++slot) {
+        const int ch = a.tex[slot].ch;
+        if (ch == 4) slot_pass<FILT, MODE, 4>(a, slot, P, lds);
+        else if (ch == 2) slot_pass<FILT, MODE, 2>(a, slot, P, lds);
+        else slot_pass<FILT, MODE, 1>(a, slot, P, lds);
+    }
+}
+
+// Deterministic filter, Eq. (3): sum over the support of f_c * T.
+template <int FILT, int C>
+__device__ __forceinline__ void reference_slot(const Args& a, int slot, const Pixel& P) {
+    using Fl = Filter<FILT>;
+    constexpr int N = Fl::N;
+    const TexArg t = a.tex[slot];
+    int i0x, Fx, i0y, Fy;
+    texel_split(P.u, t.w, i0x, Fx);
+    texel_split(P.v, t.h, i0y, Fy);
+    float wx[N], wy[N];
+    (void)Fl::pick(0u, Fx, wx);
+    (void)Fl::pick(0u, Fy, wy);
+    const uint32_t mx = (uint32_t)t.w - 1u, my = (uint32_t)t.h - 1u;
+    float acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        const uint32_t y = (uint32_t)(i0y - Fl::DELTA + b) & my;
+#pragma unroll
+        for (int aa = 0; aa < N; ++aa) {
+            const uint32_t x = (uint32_t)(i0x - Fl::DELTA + aa) & mx;
+            const Texel<C> T = fetch<C>(t, x, y);
+            const float w = wx[aa] * wy[b];
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] = fmaf(w, T.v[c], acc[c]);
+        }
+    }
+    if (P.valid) store_out<C>(a.out[slot], (int64_t)P.py * a.sw + P.px, acc);
+}
+
+template <int FILT>
+__global__ __launch_bounds__(kThreads) void reference_kernel(Args a) {
+    Pixel P;
+    if (!setup_pixel(a, P)) return;
+    for (int slot = 0; slot < a.ntex; ++slot) {
+        const int ch = a.tex[slot].ch;
+        if (ch == 4) reference_slot<FILT, 4>(a, slot, P);
+        else if (ch == 2) reference_slot<FILT, 2>(a, slot, P);
+        else reference_slot<FILT, 1>(a, slot, P);
+    }
+}
+
+// ============================================================================
+// adjoint of Eq. (14)
+// ============================================================================
+//
+// out_c = sum_i a_ci T[x_i] with a_ci = w_ci / B_c, w_ci = f_c(x_i) r_i and
+// B_c = sum_i w_ci; the weights depend on UVs and random numbers only, so
+// dL/dT[x] += sum_c sum_{i in S(c), x_i = x} a_ci dL/dout_c. The kernel
+// recomputes every pick exactly as the forward pass does, recomputes B_c,
+// and scatters. For the whole tile the sum over i collapses per texel:
+// dL/dT[x] = N_x sum_c f_c(x) q_c with N_x = sum_{i: x_i = x} r_i and
+// q_c = dL/dout_c / B_c, which is accumulated in LDS bins and flushed with
+// one global atomic per populated bin and channel.
+
+// f_c at texel (sx, sy) and whether it is inside c's support.
+template <int N>
+__device__ __forceinline__ bool own_weight(uint32_t s, int bx, int by, uint32_t mx, uint32_t my,
+                                           const float* wx, const float* wy, float& f) {
+    const uint32_t dx = ((s & 0xFFFFu) - (uint32_t)bx) & mx;
+    const uint32_t dy = ((s >> 16) - (uint32_t)by) & my;
+    float fx = wx[0], fy = wy[0];
+#pragma unroll
+    for (int k = 1; k < N; ++k) {
+        fx = (dx == (uint32_t)k) ? wx[k] : fx;
+        fy = (dy == (uint32_t)k) ? wy[k] : fy;
+    }
+    f = fx * fy;
+    return dx < (uint32_t)N && dy < (uint32_t)N;
+}
+
+template <int C>
+__device__ __forceinline__ void atomic_texel(float* g, int tw, uint32_t s, const float* v, float scale) {
+    float* p = g + ((int64_t)(s >> 16) * tw + (s & 0xFFFFu)) * C;
+#pragma unroll
+    for (int c = 0; c < C; ++c) unsafeAtomicAdd(p + c, v[c] * scale);
+}
+
+template <int FILT, int MODE, int C>
+__device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pixel& P, float* lds) {
+    using Fl = Filter<FILT>;
+    constexpr int N = Fl::N;
+    const TexArg t = a.tex[slot];
+    const int lane = lane_id();
+    int i0x, Fx, i0y, Fy;
+    texel_split(P.u, t.w, i0x, Fx);
+    texel_split(P.v, t.h, i0y, Fy);
+    const uint2 h = slot_hash((uint32_t)P.px, (uint32_t)P.py, slot, a.seed, a.frame);
+    float wx[N], wy[N];
+    const int kx = Fl::pick(h.x, Fx, wx);
+    const int ky = Fl::pick(h.y, Fy, wy);
+    const int bx = i0x - Fl::DELTA, by = i0y - Fl::DELTA;
+    const uint32_t mx = (uint32_t)t.w - 1u, my = (uint32_t)t.h - 1u;
+    const uint32_t sx = (uint32_t)(bx + kx) & mx;
+    const uint32_t sy = (uint32_t)(by + ky) & my;
+    const uint32_t s = sx | (sy << 16);
+    float* grad = const_cast<float*>(a.out[slot]);           // dL/dT, [th][tw][C]
+    const int64_t pix = (int64_t)P.py * a.sw + P.px;
+    float g[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) g[c] = P.valid ? a.dout[slot][pix * C + c] : 0.0f;
+
+    if constexpr (MODE == kModeStf) {
+        if (P.valid) atomic_texel<C>(grad, t.w, s, g, 1.0f);
+        return;
+    } else {
+        float pk_x = wx[0], pk_y = wy[0];
+#pragma unroll
+        for (int k = 1; k < N; ++k) {
+            pk_x = (kx == k) ? wx[k] : pk_x;
+            pk_y = (ky == k) ? wy[k] : pk_y;
+        }
+        const float r = P.valid ? __frcp_rn(pk_x * pk_y) : 0.0f;
+
+        if constexpr (MODE == kModeQuad) {
+            uint32_t si[3];
+            float ri[3];
+            si[0] = quad_xor<1>(s); ri[0] = quad_xor<1>(r);
+            si[1] = quad_xor<2>(s); ri[1] = quad_xor<2>(r);
+            si[2] = quad_xor<3>(s); ri[2] = quad_xor<3>(r);
+            float B = 1.0f, f[3];
+            bool in[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                in[m] = own_weight<N>(si[m], bx, by, mx, my, wx, wy, f[m]);
+                if (in[m]) B += f[m] * ri[m];
+            }
+            if (P.valid) {
+                const float inv = 1.0f / B;
+                atomic_texel<C>(grad, t.w, s, g, inv);
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    if (in[m] && ri[m] != 0.0f) atomic_texel<C>(grad, t.w, si[m], g, f[m] * ri[m] * inv);
+            }
+        } else {
+            bool use_bins = false;
+            if constexpr (MODE == kModeBins) {
+                constexpr int margin = (kBinG - N) / 2;
+                const int base_x = __builtin_amdgcn_readfirstlane(bx) - margin;
+                const int base_y = __builtin_amdgcn_readfirstlane(by) - margin;
+                const uint32_t rx = (uint32_t)(bx - base_x) & mx;
+                const uint32_t ry = (uint32_t)(by - base_y) & my;
+                const bool fits = !P.valid || (rx <= (uint32_t)(kBinG - N) && ry <= (uint32_t)(kBinG - N));
+                use_bins = (t.w >= kBinG) && (t.h >= kBinG) && (__builtin_amdgcn_ballot_w64(!fits) == 0);
+                if (use_bins) {
+                    float* Nb = lds;
+                    float* Qb = lds + kBins;
+                    reinterpret_cast<float4*>(Nb)[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                    for (int i = 0; i < C; ++i)
+                        reinterpret_cast<float4*>(Qb)[lane * C + i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    wave_lds_sync();
+                    if (P.valid) atomicAdd(&Nb[(int)(ry + ky) * kBinG + (int)(rx + kx)], r);
+                    wave_lds_sync();
+                    float B = 0.0f;
+#pragma unroll
+                    for (int b = 0; b < N; ++b)
+#pragma unroll
+                        for (int aa = 0; aa < N; ++aa)
+                            B += wx[aa] * wy[b] * Nb[(int)(ry + b) * kBinG + (int)rx + aa];
+                    if (P.valid) {
+                        const float inv = 1.0f / B;
+#pragma unroll
+                        for (int b = 0; b < N; ++b)
+#pragma unroll
+                            for (int aa = 0; aa < N; ++aa) {
+                                const int idx = (int)(ry + b) * kBinG + (int)rx + aa;
+                                if (Nb[idx] != 0.0f) {
+                                    const float f = wx[aa] * wy[b] * inv;
+#pragma unroll
+                                    for (int c = 0; c < C; ++c) atomicAdd(&Qb[idx * C + c], f * g[c]);
+                                }
+                            }
+                    }
+                    wave_lds_sync();
+                    // flush: lane handles bins lane, lane+64, lane+128, lane+192
+#pragma unroll
+                    for (int k = 0; k < kBins / 64; ++k) {
+                        const int idx = lane + 64 * k;
+                        const float nx = Nb[idx];
+                        if (nx != 0.0f) {
+                            const uint32_t tx = (uint32_t)(base_x + (idx % kBinG)) & mx;
+                            const uint32_t ty = (uint32_t)(base_y + (idx / kBinG)) & my;
+                            float q[C];
+#pragma unroll
+                            for (int c = 0; c < C; ++c) q[c] = Qb[idx * C + c];
+                            atomic_texel<C>(grad, t.w, tx | (ty << 16), q, nx);
+                        }
+                    }
+                    wave_lds_sync();
+                }
+            }
+            if (!use_bins) {
+                uint2* meta = reinterpret_cast<uint2*>(lds);
+                meta[P.q] = make_uint2(s, __float_as_uint(r));
+                wave_lds_sync();
+                const int fp = (MODE == kModeBins) ? (int)STF_FP_TILE8X8 : a.footprint;
+                const int K = footprint_size(fp, a.lut_k);
+                float B = 1.0f;
+                for (int m = 0; m < K; ++m) {
+                    const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
+                    if (j == P.q) continue;
+                    const uint2 mj = meta[j];
+                    float f;
+                    if (own_weight<N>(mj.x, bx, by, mx, my, wx, wy, f)) B += f * __uint_as_float(mj.y);
+                }
+                if (P.valid) {
+                    const float inv = 1.0f / B;
+                    atomic_texel<C>(grad, t.w, s, g, inv);
+                    for (int m = 0; m < K; ++m) {
+                        const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
+                        if (j == P.q) continue;
+                        const uint2 mj = meta[j];
+                        const float rj = __uint_as_float(mj.y);
+                        float f;
+                        if (own_weight<N>(mj.x, bx, by, mx, my, wx, wy, f) && rj != 0.0f)
+                            atomic_texel<C>(grad, t.w, mj.x, g, f * rj * inv);
+                    }
+                }
+                wave_lds_sync();
+            }
+        }
+    }
+}
+
+template <int FILT, int MODE>
+__global__ __launch_bounds__(kThreads) void backward_kernel(Args a) {
+    __shared__ __align__(16) float lds_all[kWavesPerGroup * kLdsFloatsPerWave];
+    Pixel P;
+    if (!setup_pixel(a, P)) return;
+    float* lds = lds_all + (threadIdx.x >> 6) * kLdsFloatsPerWave;
+    for (int slot = 0; slot < a.ntex; ++slot) {
+        const int ch = a.tex[slot].ch;
+        if (ch == 4) backward_slot<FILT, MODE, 4>(a, slot, P, lds);
+        else if (ch == 2) backward_slot<FILT, MODE, 2>(a, slot, P, lds);
+        else backward_slot<FILT, MODE, 1>(a, slot, P, lds);
+    }
+}
+
+}  // namespace stf
+
+// ============================================================================
+// host side of the C ABI
+// ============================================================================
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int format_channels(int fmt) {
+    switch (fmt) {
+    case STF_RGBA8_UNORM: case STF_RGBA16F: case STF_RGBA32F: return 4;
+    case STF_RG16F: return 2;
+    case STF_R8_UNORM: case STF_R32F: return 1;
+    default: return 0;
+    }
+}
+
+int format_bytes(int fmt) {
+    switch (fmt) {
+    case STF_RGBA8_UNORM: return 4;
+    case STF_RGBA16F: return 8;
+    case STF_RGBA32F: return 16;
+    case STF_RG16F: return 4;
+    case STF_R8_UNORM: return 1;
+    case STF_R32F: return 4;
+    default: return 0;
+    }
+}
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Validates everything the kernels assume and fills the kernel arguments.
+int prepare(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
+            bool need_data, stf::Args& a) {
+    std::memset(&a, 0, sizeof a);
+    if (tex == nullptr || scr == nullptr || p == nullptr)
+        return fail(STF_EINVAL, "null descriptor pointer");
+    if (ntex < 1 || ntex > STF_MAX_TEXTURES)
+        return fail(STF_EINVAL, "ntex=%d outside 1..%d", ntex, STF_MAX_TEXTURES);
+    if (scr->uv == nullptr) return fail(STF_EINVAL, "screen uv is null");
+    if (scr->width < 1 || scr->height < 1 || scr->width > STF_MAX_SCREEN || scr->height > STF_MAX_SCREEN)
+        return fail(STF_EINVAL, "screen %dx%d outside 1..%d", scr->width, scr->height, STF_MAX_SCREEN);
+    if ((reinterpret_cast<uintptr_t>(scr->uv) & 7) != 0) return fail(STF_EINVAL, "uv not 8-byte aligned");
+    if (p->filter != STF_BILINEAR && p->filter != STF_BICUBIC_BSPLINE)
+        return fail(STF_EINVAL, "unknown filter %d", p->filter);
+    if (p->address != STF_WRAP) return fail(STF_EUNSUPPORTED, "address mode %d not supported (WRAP only)", p->address);
+    for (int i = 0; i < ntex; ++i) {
+        const stf_texture& t = tex[i];
+        const int ch = format_channels(t.format);
+        const int bpp = format_bytes(t.format);
+        if (ch == 0) return fail(STF_EINVAL, "texture %d: unknown format %d", i, t.format);
+        if (t.reserved != 0) return fail(STF_EINVAL, "texture %d: reserved field must be 0", i);
+        if (need_data && t.data == nullptr) return fail(STF_EINVAL, "texture %d: data is null", i);
+        if (!pow2(t.width) || !pow2(t.height) || t.width < 4 || t.height < 4 || t.width > 32768 || t.height > 32768)
+            return fail(STF_EINVAL, "texture %d: %dx%d must be powers of two in 4..32768 for WRAP", i, t.width, t.height);
+        if (need_data) {
+            if (t.pitch_bytes < (int64_t)t.width * bpp || t.pitch_bytes % bpp != 0)
+                return fail(STF_EINVAL, "texture %d: pitch %lld invalid for width %d x %d bytes", i,
+                            (long long)t.pitch_bytes, t.width, bpp);
+            if ((reinterpret_cast<uintptr_t>(t.data) % bpp) != 0)
+                return fail(STF_EINVAL, "texture %d: data not aligned to %d bytes", i, bpp);
+        }
+        a.tex[i].data = static_cast<const uint8_t*>(t.data);
+        a.tex[i].pitch = t.pitch_bytes;
+        a.tex[i].w = t.width;
+        a.tex[i].h = t.height;
+        a.tex[i].fmt = t.format;
+        a.tex[i].ch = ch;
+    }
+    a.uv = scr->uv;
+    a.ntex = ntex;
+    a.sw = scr->width;
+    a.sh = scr->height;
+    a.seed = p->seed;
+    a.frame = p->frame;
+    return STF_OK;
+}
+
+int check_outputs(float* const* out, int32_t ntex) {
+    if (out == nullptr) return fail(STF_EINVAL, "out array is null");
+    for (int i = 0; i < ntex; ++i) {
+        if (out[i] == nullptr) return fail(STF_EINVAL, "out[%d] is null", i);
+        if ((reinterpret_cast<uintptr_t>(out[i]) & 15) != 0) return fail(STF_EINVAL, "out[%d] not 16-byte aligned", i);
+    }
+    return STF_OK;
+}
+
+int check_reuse(const stf_reuse* r) {
+    if (r == nullptr) return fail(STF_EINVAL, "reuse descriptor is null");
+    if (r->footprint < STF_FP_SELF || r->footprint > STF_FP_LUT)
+        return fail(STF_EINVAL, "unknown footprint %d", r->footprint);
+    if (r->footprint == STF_FP_LUT) {
+        if (r->lut == nullptr) return fail(STF_EINVAL, "footprint LUT requires a lut pointer");
+        if (r->lut_k < 1 || r->lut_k > 64) return fail(STF_EINVAL, "lut_k=%d outside 1..64", r->lut_k);
+    }
+    return STF_OK;
+}
+
+dim3 grid_of(const stf::Args& a) {
+    return dim3((unsigned)((a.sw + stf::kTile * stf::kWavesPerGroup - 1) / (stf::kTile * stf::kWavesPerGroup)),
+                (unsigned)((a.sh + stf::kTile - 1) / stf::kTile));
+}
+
+int finish_launch(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(STF_EHIP, "%s launch failed: %s", what, hipGetErrorString(e));
+    return STF_OK;
+}
+
+template <int FILT, int MODE>
+void launch_forward(const stf::Args& a, hipStream_t s) {
+    hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE>), grid_of(a), dim3(stf::kThreads), 0, s, a);
+}
+
+int forward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
+            const stf_reuse* r, float* const* out, int32_t* sel, void* hip_stream) {
+    g_last_error.clear();
+    stf::Args a;
+    int rc = prepare(tex, ntex, scr, p, true, a);
+    if (rc != STF_OK) return rc;
+    if ((rc = check_outputs(out, ntex)) != STF_OK) return rc;
+    if (sel != nullptr && (reinterpret_cast<uintptr_t>(sel) & 7) != 0) return fail(STF_EINVAL, "sel not 8-byte aligned");
+    int mode = stf::kModeStf;
+    if (r != nullptr) {
+        if ((rc = check_reuse(r)) != STF_OK) return rc;
+        a.footprint = r->footprint;
+        a.lut = r->lut;
+        a.lut_k = r->lut_k;
+        switch (r->footprint) {
+        case STF_FP_SELF: mode = stf::kModeStf; break;
+        case STF_FP_QUAD2X2: mode = stf::kModeQuad; break;
+        case STF_FP_TILE8X8: mode = stf::kModeBins; break;
+        default: mode = stf::kModeRecords; break;
+        }
+    }
+    for (int i = 0; i < ntex; ++i) a.out[i] = out[i];
+    a.sel = sel;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const bool cubic = p->filter == STF_BICUBIC_BSPLINE;
+    switch (mode) {
+    case stf::kModeStf: cubic ? launch_forward<1, stf::kModeStf>(a, s) : launch_forward<0, stf::kModeStf>(a, s); break;
+    case stf::kModeQuad: cubic ? launch_forward<1, stf::kModeQuad>(a, s) : launch_forward<0, stf::kModeQuad>(a, s); break;
+    case stf::kModeRecords: cubic ? launch_forward<1, stf::kModeRecords>(a, s) : launch_forward<0, stf::kModeRecords>(a, s); break;
+    default: cubic ? launch_forward<1, stf::kModeBins>(a, s) : launch_forward<0, stf::kModeBins>(a, s); break;
+    }
+    return finish_launch("forward");
+}
+
+}  // namespace
+
+extern "C" {
+
+int stf_filter(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
+               float* const* out, int32_t* sel, void* hip_stream) {
+    return forward(tex, ntex, scr, p, nullptr, out, sel, hip_stream);
+}
+
+int stf_filter_reuse(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
+                     const stf_reuse* r, float* const* out, int32_t* sel, void* hip_stream) {
+    if (r == nullptr) {
+        g_last_error.clear();
+        return fail(STF_EINVAL, "reuse descriptor is null");
+    }
+    return forward(tex, ntex, scr, p, r, out, sel, hip_stream);
+}
+
+int stf_filter_reference(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
+                         float* const* out, void* hip_stream) {
+    g_last_error.clear();
+    stf::Args a;
+    int rc = prepare(tex, ntex, scr, p, true, a);
+    if (rc != STF_OK) return rc;
+    if ((rc = check_outputs(out, ntex)) != STF_OK) return rc;
+    for (int i = 0; i < ntex; ++i) a.out[i] = out[i];
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (p->filter == STF_BICUBIC_BSPLINE)
+        hipLaunchKernelGGL((stf::reference_kernel<1>), grid_of(a), dim3(stf::kThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((stf::reference_kernel<0>), grid_of(a), dim3(stf::kThreads), 0, s, a);
+    return finish_launch("reference");
+}
+
+int stf_backward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
+                 const stf_reuse* r, const float* const* dout, float* const* dtex, void* hip_stream) {
+    g_last_error.clear();
+    stf::Args a;
+    int rc = prepare(tex, ntex, scr, p, false, a);
+    if (rc != STF_OK) return rc;
+    if ((rc = check_reuse(r)) != STF_OK) return rc;
+    if (dout == nullptr || dtex == nullptr) return fail(STF_EINVAL, "dout/dtex arrays are null");
+    for (int i = 0; i < ntex; ++i) {
+        if (dout[i] == nullptr || dtex[i] == nullptr) return fail(STF_EINVAL, "dout[%d]/dtex[%d] is null", i, i);
+        if ((reinterpret_cast<uintptr_t>(dout[i]) & 3) || (reinterpret_cast<uintptr_t>(dtex[i]) & 3))
+            return fail(STF_EINVAL, "dout[%d]/dtex[%d] not 4-byte aligned", i, i);
+        a.out[i] = dtex[i];
+        a.dout[i] = dout[i];
+    }
+    a.footprint = r->footprint;
+    a.lut = r->lut;
+    a.lut_k = r->lut_k;
+    int mode;
+    switch (r->footprint) {
+    case STF_FP_SELF: mode = stf::kModeStf; break;
+    case STF_FP_QUAD2X2: mode = stf::kModeQuad; break;
+    case STF_FP_TILE8X8: mode = stf::kModeBins; break;
+    default: mode = stf::kModeRecords; break;
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const bool cubic = p->filter == STF_BICUBIC_BSPLINE;
+    const dim3 g = grid_of(a), b(stf::kThreads);
+#define STF_BW(F, M) hipLaunchKernelGGL((stf::backward_kernel<F, M>), g, b, 0, s, a)
+    switch (mode) {
+    case stf::kModeStf: if (cubic) STF_BW(1, stf::kModeStf); else STF_BW(0, stf::kModeStf); break;
+    case stf::kModeQuad: if (cubic) STF_BW(1, stf::kModeQuad); else STF_BW(0, stf::kModeQuad); break;
+    case stf::kModeRecords: if (cubic) STF_BW(1, stf::kModeRecords); else STF_BW(0, stf::kModeRecords); break;
+    default: if (cubic) STF_BW(1, stf::kModeBins); else STF_BW(0, stf::kModeBins); break;
+    }
+#undef STF_BW
+    return finish_launch("backward");
+}
+
+const char* stf_last_error(void) { return g_last_error.c_str(); }
+
+int stf_version(void) { return STF_VERSION; }
+
+}  // extern "C"

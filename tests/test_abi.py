@@ -1,0 +1,81 @@
+"""The C-ABI library loads and exports every symbol include/stf.h declares;
+argument validation rejects bad calls on the host before any launch (no GPU
+compute is run here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2504_05562_amd as stf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "stf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(stf_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = stf.library()
+    names = declared_functions()
+    assert {"stf_filter", "stf_filter_reuse", "stf_filter_reference", "stf_backward",
+            "stf_last_error", "stf_version"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert stf.version() == 1
+
+
+def _call_filter(tex, ntex, scr, prm):
+    lib = stf.library()
+    out = (ctypes.c_void_p * 4)(16, 32, 48, 64)
+    return lib.stf_filter(tex, ntex, scr, prm, out, None, None)
+
+
+def _good():
+    tex = (stf.Texture * 1)()
+    tex[0].data = 256
+    tex[0].width = 64
+    tex[0].height = 64
+    tex[0].pitch_bytes = 64 * 4
+    tex[0].format = 0
+    scr = stf.Screen(4096, 16, 16)
+    prm = stf.Params(1, 0, 0, 0)
+    return tex, scr, prm
+
+
+@pytest.mark.parametrize("mutate,code,needle", [
+    (lambda t, s, p: setattr(s, "uv", None), -1, "uv"),
+    (lambda t, s, p: setattr(s, "width", 0), -1, "screen"),
+    (lambda t, s, p: setattr(p, "filter", 7), -1, "filter"),
+    (lambda t, s, p: setattr(p, "address", 1), -2, "address"),
+    (lambda t, s, p: setattr(t[0], "format", 99), -1, "format"),
+    (lambda t, s, p: setattr(t[0], "width", 48), -1, "powers of two"),
+    (lambda t, s, p: setattr(t[0], "height", 2), -1, "powers of two"),
+    (lambda t, s, p: setattr(t[0], "pitch_bytes", 100), -1, "pitch"),
+    (lambda t, s, p: setattr(t[0], "data", None), -1, "data"),
+    (lambda t, s, p: setattr(t[0], "reserved", 1), -1, "reserved"),
+])
+def test_validation_errors(mutate, code, needle):
+    tex, scr, prm = _good()
+    mutate(tex, scr, prm)
+    rc = _call_filter(tex, 1, ctypes.byref(scr), ctypes.byref(prm))
+    assert rc == code
+    assert needle in stf.library().stf_last_error().decode()
+
+
+def test_validation_counts_and_nulls():
+    lib = stf.library()
+    tex, scr, prm = _good()
+    assert _call_filter(tex, 0, ctypes.byref(scr), ctypes.byref(prm)) == -1
+    assert _call_filter(tex, 5, ctypes.byref(scr), ctypes.byref(prm)) == -1
+    assert lib.stf_filter(None, 1, ctypes.byref(scr), ctypes.byref(prm), None, None, None) == -1
+    assert lib.stf_filter_reuse(tex, 1, ctypes.byref(scr), ctypes.byref(prm), None, None, None, None) == -1
+    bad_fp = stf.Reuse(42, 0, None)
+    out = (ctypes.c_void_p * 1)(4096)
+    assert lib.stf_filter_reuse(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(bad_fp), out, None, None) == -1
+    lut_missing = stf.Reuse(6, 4, None)
+    assert lib.stf_filter_reuse(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(lut_missing), out, None, None) == -1
+    assert b"lut" in lib.stf_last_error()

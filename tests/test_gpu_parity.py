@@ -1,0 +1,238 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bar: texel selection bit-exact; colours within 1e-5 relative to the larger
+of |oracle| and the largest texel magnitude under the pixel's own filter
+(the FP32 convex combination has no cancellation, so its error scales with
+the texels it mixes). Inputs are seeded and synthetic.
+"""
+import numpy as np
+import pytest
+
+import oracle as o
+import workloads as w
+
+torch = pytest.importorskip("torch")
+stf = pytest.importorskip("paper_2504_05562_amd")
+
+pytestmark = pytest.mark.gpu
+REL = 1e-5
+FILTERS = {"bilinear": o.BILINEAR, "bicubic": o.BICUBIC}
+ALL_FP = ["self", "quad2x2", "wave2x2", "square3x3", "square4x4", "tile8x8"]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def support_scale(tex, uv, filt):
+    """Per pixel and channel: max |T| over the pixel's own filter support."""
+    T = np.abs(o.decode_texels(tex))
+    th, tw = tex.shape[:2]
+    n, d = (4, 1) if filt == o.BICUBIC else (2, 0)
+    i0x, _ = o.split_coord(o.texel_float_coord(uv[..., 0], tw))
+    i0y, _ = o.split_coord(o.texel_float_coord(uv[..., 1], th))
+    m = np.zeros(uv.shape[:2] + (tex.shape[2],))
+    for b in range(n):
+        for a in range(n):
+            m = np.maximum(m, T[(i0y - d + b) % th, (i0x - d + a) % tw])
+    return m
+
+
+def assert_close(gpu, ref, scale, what=""):
+    tol = REL * np.maximum(np.abs(ref), scale) + 1e-30
+    err = np.abs(gpu.astype(np.float64) - ref)
+    bad = err > tol
+    assert not bad.any(), f"{what}: {bad.sum()} values beyond tolerance, worst {np.max(err / tol):.3g}x"
+
+
+def oracle_image(vals, uv, tiles=None):
+    if tiles is None:
+        tiles = o.all_tiles(uv.shape[1], uv.shape[0])
+    return o.tiles_to_image(vals, tiles, uv.shape[1], uv.shape[0])
+
+
+def run_case(texs, uv, filt, fp, seed=0, frame=0, lut=None):
+    """Full-image parity of stf_filter_reuse (or stf_filter for fp=None)."""
+    ftag = FILTERS[filt]
+    dt = [dev(t) for t in texs]
+    duv = dev(uv)
+    if fp is None:
+        outs, sel = stf.filter(dt, duv, filt, seed, frame, sel=True)
+        ref = o.stf_filter(texs, uv, ftag, seed, frame)
+    else:
+        lut_t = dev(lut.astype(np.uint8)) if lut is not None else None
+        outs, sel = stf.filter_reuse(dt, duv, fp, filt, seed, frame, lut=lut_t, sel=True)
+        ref = o.stf_filter_reuse(texs, uv, ftag, seed, frame, fp, lut=lut)
+    sel = host(sel)
+    for slot, (tex, (rv, rs)) in enumerate(zip(texs, ref)):
+        want_sel = oracle_image(rs, uv)
+        assert np.array_equal(sel[slot], want_sel), f"slot {slot}: selection differs"
+        gv = host(outs[slot])
+        assert_close(gv, oracle_image(rv, uv), support_scale(tex, uv, ftag), f"slot {slot} {fp}")
+    return outs, sel
+
+
+def small_textures(seed=0):
+    return [w.small_texture(seed)]
+
+
+# --------------------------------------------------------------- small workload
+
+@pytest.mark.parametrize("fp", [None, "self", "quad2x2"])
+def test_small_workload_full(fp):
+    """256^2 RGBA8, 512x512 fronto-parallel quad at 8x, bilinear, seed 0."""
+    run_case(small_textures(), w.small_screen(), "bilinear", fp)
+
+
+@pytest.mark.parametrize("filt", ["bilinear", "bicubic"])
+@pytest.mark.parametrize("fp", ALL_FP)
+def test_all_footprints_ragged_screen(filt, fp):
+    # 61x37: partial tiles on both axes; rotated quad at 3.3x
+    tex = w.tile_texture_rgba8(3, 64)
+    uv = w.small_screen(61, 37, 64, 3.3, offset_seed=4)
+    run_case([tex], uv, filt, fp, seed=7, frame=3)
+
+
+@pytest.mark.parametrize("fp", ["square3x3", "tile8x8"])
+def test_multi_texture_formats(fp):
+    texs = [w.plane_albedo(1, 64), w.plane_normal(1, 64), w.r8_texture(2, 32),
+            np.random.default_rng(0).random((16, 16, 4)).astype(np.float32)]
+    uv = w.small_screen(40, 24, 64, 5.0, offset_seed=1)
+    run_case(texs, uv, "bicubic", fp, seed=11)
+
+
+def test_lut_footprint():
+    rng = np.random.default_rng(5)
+    lut = rng.integers(0, 64, (64, 9))
+    lut[::3, 0] = np.arange(64)[::3]          # some rows name the pixel itself
+    uv = w.small_screen(48, 32, 64, 4.0, offset_seed=2)
+    run_case([w.tile_texture_rgba8(1, 64)], uv, "bicubic", "lut", seed=2, lut=lut)
+
+
+def test_tile_bins_fallback_under_minification():
+    # texels 1.5 apart per pixel: the tile's texels exceed the bin window and
+    # the kernel takes the per-record path; results must not change
+    uv = w.small_screen(64, 64, 256, 1 / 1.5, offset_seed=3)
+    run_case([w.small_texture(1)], uv, "bicubic", "tile8x8", seed=1)
+
+
+def test_tiny_inputs():
+    run_case([w.tile_texture_rgba8(1, 4)], w.small_screen(1, 1, 4, 2.0), "bicubic", "tile8x8")
+    run_case([w.tile_texture_rgba8(1, 4)], w.small_screen(3, 9, 4, 2.0), "bilinear", "quad2x2")
+
+
+# --------------------------------------------------------------- plane workload
+
+@pytest.fixture(scope="module")
+def plane():
+    uv, _, _, info = w.perspective_plane()
+    return [w.plane_albedo(), w.plane_normal()], uv
+
+
+def test_plane_selection_full_and_sampled_colours(plane):
+    """1920x1080 perspective plane, 2048^2 RGBA16F + RG16F, bicubic, whole-tile
+    reuse (the benchmarked launch): selection bit-exact on every pixel,
+    colours on 400 sampled tiles."""
+    texs, uv = plane
+    dt = [dev(t) for t in texs]
+    duv = dev(uv)
+    outs, sel = stf.filter_reuse(dt, duv, "tile8x8", "bicubic", 0, 0, sel=True)
+    sel = host(sel)
+    tiles_all = o.all_tiles(1920, 1080)
+    for slot, tex in enumerate(texs):
+        s = o.stf_samples(tex, uv, tiles_all, slot, o.BICUBIC, 0, 0)
+        want = o.tiles_to_image(np.stack([s["sx"], s["sy"]], -1), tiles_all, 1920, 1080)
+        assert np.array_equal(sel[slot], want), f"slot {slot} selection"
+    rng = np.random.default_rng(0)
+    tiles = tiles_all[rng.choice(len(tiles_all), 400, replace=False)]
+    ref = o.stf_filter_reuse(texs, uv, o.BICUBIC, 0, 0, "tile8x8", tiles=tiles)
+    px = tiles[:, 0:1] * 8 + (np.arange(64) % 8)[None]
+    py = tiles[:, 1:2] * 8 + (np.arange(64) // 8)[None]
+    for slot, tex in enumerate(texs):
+        g = host(outs[slot])[py, px]
+        sc = support_scale(tex, uv, o.BICUBIC)[py, px]
+        assert_close(g, ref[slot][0], sc, f"plane slot {slot}")
+
+
+def test_plane_reference_and_stf(plane):
+    texs, uv = plane
+    dt = [dev(t) for t in texs]
+    duv = dev(uv)
+    ref_g = [host(x) for x in stf.filter_reference(dt, duv, "bicubic")]
+    stf_g = [host(x) for x in stf.filter(dt, duv, "bicubic", 0, 0)]
+    rng = np.random.default_rng(1)
+    tiles_all = o.all_tiles(1920, 1080)
+    tiles = tiles_all[rng.choice(len(tiles_all), 300, replace=False)]
+    px = tiles[:, 0:1] * 8 + (np.arange(64) % 8)[None]
+    py = tiles[:, 1:2] * 8 + (np.arange(64) // 8)[None]
+    mu = o.reference_filter(texs, uv, o.BICUBIC, tiles=tiles)
+    st = o.stf_filter(texs, uv, o.BICUBIC, 0, 0, tiles=tiles)
+    for slot, tex in enumerate(texs):
+        sc = support_scale(tex, uv, o.BICUBIC)[py, px]
+        assert_close(ref_g[slot][py, px], mu[slot], sc, "reference")
+        assert np.array_equal(stf_g[slot][py, px], st[slot][0].astype(np.float32)), "stf texels exact"
+
+
+# --------------------------------------------------------------- properties
+
+def test_constant_texture_exact_on_gpu():
+    tex = np.full((64, 64, 4), 0.375, np.float16)
+    uv = w.small_screen(64, 64, 64, 3.0, offset_seed=0)
+    for fp in ALL_FP:
+        out = host(stf.filter_reuse([dev(tex)], dev(uv), fp, "bicubic", 3)[0])
+        assert np.all(out == np.float32(0.375)), fp
+
+
+def test_self_and_disjoint_equal_stf_bit_exact():
+    tex = w.tile_texture_rgba8(2, 256)
+    uv_far = w.small_screen(64, 64, 256, 1 / 8)        # supports never overlap
+    uv_mag = w.small_screen(64, 64, 256, 6.0, offset_seed=5)
+    a = host(stf.filter([dev(tex)], dev(uv_mag), "bicubic", 4)[0])
+    b = host(stf.filter_reuse([dev(tex)], dev(uv_mag), "self", "bicubic", 4)[0])
+    assert np.array_equal(a, b)
+    a = host(stf.filter([dev(tex)], dev(uv_far), "bicubic", 4)[0])
+    for fp in ALL_FP:
+        b = host(stf.filter_reuse([dev(tex)], dev(uv_far), fp, "bicubic", 4)[0])
+        assert np.array_equal(a, b), fp
+
+
+def test_convex_hull_on_gpu():
+    tex = w.tile_texture_rgba8(6, 64)
+    uv = w.small_screen(128, 64, 64, 4.0, offset_seed=6)
+    T = o.decode_texels(tex)
+    i0x, _ = o.split_coord(o.texel_float_coord(uv[..., 0], 64))
+    i0y, _ = o.split_coord(o.texel_float_coord(uv[..., 1], 64))
+    vals = np.stack([T[(i0y - 1 + b) % 64, (i0x - 1 + a) % 64] for a in range(4) for b in range(4)], 0)
+    lo, hi = vals.min(0), vals.max(0)
+    for fp in ALL_FP:
+        out = host(stf.filter_reuse([dev(tex)], dev(uv), fp, "bicubic", 8)[0]).astype(np.float64)
+        slack = 4 * np.finfo(np.float32).eps
+        assert np.all(out >= lo - slack) and np.all(out <= hi + slack), fp
+
+
+def test_deterministic_bits(plane):
+    texs, uv = plane
+    dt = [dev(t) for t in texs]
+    duv = dev(uv)
+    a = [host(x) for x in stf.filter_reuse(dt, duv, "tile8x8", "bicubic", 9)]
+    b = [host(x) for x in stf.filter_reuse(dt, duv, "tile8x8", "bicubic", 9)]
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_reuse_psnr_gain_on_plane(plane):
+    """Whole-tile reuse improves PSNR over one-tap STF by >= 10 dB on the
+    1080p bicubic plane (the quality half of the headline metric)."""
+    texs, uv = plane
+    dt = [dev(texs[0])]
+    duv = dev(uv)
+    ref = host(stf.filter_reference(dt, duv, "bicubic")[0])
+    s = host(stf.filter(dt, duv, "bicubic", 0)[0])
+    r = host(stf.filter_reuse(dt, duv, "tile8x8", "bicubic", 0)[0])
+    gain = o.psnr(r[..., :3], ref[..., :3]) - o.psnr(s[..., :3], ref[..., :3])
+    assert gain >= 10.0, gain
