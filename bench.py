@@ -53,6 +53,25 @@ def measured_traffic():
     return d.get("bytes_per_launch")
 
 
+def copy_probe(torch, dev, nbytes=512 << 20, reps=5):
+    """Device-to-device copy of a buffer larger than the last-level cache:
+    the achievable HBM rate (read + write bytes / time) and the reference
+    kernel for calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3 / reps
+    return {"bytes_per_copy": nbytes, "gbs": round(2 * nbytes / dt / 1e9, 1)}
+
+
 def cpu_baseline(texs, uv, n_tiles=2400, seed=0):
     """The FP64 oracle as it stands, on a bounded random sample of the frame's
     tiles (both textures), single-threaded numpy."""
@@ -154,6 +173,7 @@ def main():
         return float(10 * torch.log10(1.0 / torch.mean(d * d)))
 
     p_r, p_s = psnr(out_r, ref), psnr(out_s, ref)
+    probe = copy_probe(torch, dev)
 
     res = {
         "metric": METRIC,
@@ -179,6 +199,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
             "kernel": "forward_kernel<bicubic, bins>", "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_us": round(launch_s * 1e6, 3),
+            "frac_of_copy_probe": round(achieved / probe["gbs"], 4), "copy_probe_gbs": probe["gbs"],
         },
         "stf_1sample": {
             "value": round(px * args.steps / wall_s / 1e6, 1), "unit": "Mpixel/s",

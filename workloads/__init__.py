@@ -43,6 +43,7 @@ def _smoothstep(t: np.ndarray) -> np.ndarray:
 def value_noise(rng: np.random.Generator, size: int, period: int, channels: int) -> np.ndarray:
     """Tileable value noise: random lattice values every `period` texels,
     smoothstep-interpolated. Returns float64 [size, size, channels] in [0, 1]."""
+    period = min(period, size)
     assert size % period == 0
     n = size // period
     lat = rng.random((n, n, channels))
