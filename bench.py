@@ -72,7 +72,7 @@ def copy_probe(torch, dev, nbytes=512 << 20, reps=5):
     return {"bytes_per_copy": nbytes, "gbs": round(2 * nbytes / dt / 1e9, 1)}
 
 
-def cpu_baseline(texs, uv, n_tiles=2400, seed=0):
+def cpu_baseline(texs, uv, n_tiles=12000, seed=0):
     """The FP64 oracle as it stands, on a bounded random sample of the frame's
     tiles (both textures), single-threaded numpy."""
     import oracle
