@@ -27,7 +27,10 @@
  *     outputs are FP32 [height][width][C] row-major, C = channels of the
  *     texture format; pixel (px, py) has its centre at (px+1/2, py+1/2).
  *   - Texture layout: row y starts at data + y * pitch_bytes; texels are
- *     tightly packed within a row. Texel (0,0) is the first texel.
+ *     tightly packed within a row. Texel (0,0) is the first texel. The base
+ *     address and pitch_bytes are multiples of 16 and the allocation holds
+ *     height * pitch_bytes bytes (kernels read aligned 16-byte blocks inside
+ *     a row).
  *   - Texel-space coordinate of a texture coordinate u on a texture of
  *     size W: x = u * W - 0.5 in FP32 (Sec. 4.5 listing); the sub-texel
  *     fraction is quantised to 16 bits.
@@ -90,7 +93,7 @@ typedef struct stf_texture {
     const void* data;       /* device, texel payload */
     int32_t width;          /* texels */
     int32_t height;         /* texels */
-    int64_t pitch_bytes;    /* >= width * bytes per texel, multiple of it */
+    int64_t pitch_bytes;    /* >= width * bytes per texel, multiple of 16 */
     int32_t format;         /* stf_format */
     int32_t reserved;       /* must be 0 */
 } stf_texture;

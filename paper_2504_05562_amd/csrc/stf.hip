@@ -36,8 +36,16 @@ namespace stf {
 
 enum Mode { kModeStf = 0, kModeQuad = 1, kModeRecords = 2, kModeBins = 3 };
 
-// LDS per wavefront: bins (kBins floats of N + kBins * 4 floats of texels)
-// or records (64 x {s, r} + 64 x 4 floats); the larger one sets the size.
+// Whole-tile gather arithmetic: true accumulates w_j (T_j - T_c) (exact zero
+// for constant regions and the one-tap fallback in FP32); false accumulates
+// w_j T_j (one operation less per channel and bin; within a few ulp).
+#ifndef STF_EXACT_DIFF
+#define STF_EXACT_DIFF 1
+#endif
+constexpr bool kExactDiff = STF_EXACT_DIFF != 0;
+
+// LDS per wavefront: bins (kBins x 16 B records, or kBins floats of N plus
+// kBins x 16 B of decoded texels) or records (64 x {s, r} + 64 x 16 B).
 constexpr int kLdsFloatsPerWave = kBins * 5;
 
 struct Pixel {
@@ -46,6 +54,27 @@ struct Pixel {
     int q;               // row-major tile pixel id ly*8+lx
     bool valid;          // inside the screen
     float u, v;
+};
+
+// Per-pixel selection state for one texture size: both axes plus the
+// products of their weights (the 2D filter weights f_c over the support).
+template <int FILT>
+struct SelCtx {
+    static constexpr int N = AxisCtx<FILT>::N;
+    AxisCtx<FILT> x, y;
+    float wxy[N * N];
+    int tw = 0, th = 0;
+    __device__ __forceinline__ void update(const Pixel& P, int w, int h) {
+        if (w == tw && h == th) return;                  // wave-uniform
+        if (w != tw) x.init(P.u, w);
+        if (h != th) y.init(P.v, h);
+        tw = w;
+        th = h;
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+#pragma unroll
+            for (int a = 0; a < N; ++a) wxy[b * N + a] = x.w(a) * y.w(b);
+    }
 };
 
 // Footprint member m of tile pixel (lx, ly) as a row-major tile pixel id.
@@ -84,129 +113,241 @@ __device__ __forceinline__ int footprint_size(int fp, int lut_k) {
     }
 }
 
-// Accumulate the contribution of one shared pick (canonical texel (sx, sy)
-// packed as sx | sy << 16, reciprocal PMF r, texel Ti) into pixel c's sums.
-template <int N, int C>
-__device__ __forceinline__ void accumulate(uint32_t s, float r, const float* Ti, int bx, int by,
-                                           uint32_t mx, uint32_t my, const float* wx, const float* wy,
-                                           const float* Tc, float& B, float* acc) {
-    const uint32_t dx = ((s & 0xFFFFu) - (uint32_t)bx) & mx;
-    const uint32_t dy = ((s >> 16) - (uint32_t)by) & my;
-    if (dx < (uint32_t)N && dy < (uint32_t)N) {      // outside the own support: skipped
-        float fx = wx[0], fy = wy[0];
-#pragma unroll
-        for (int k = 1; k < N; ++k) {
-            fx = (dx == (uint32_t)k) ? wx[k] : fx;
-            fy = (dy == (uint32_t)k) ? wy[k] : fy;
-        }
-        const float w = fx * fy * r;
+// Offset of texel s (packed sx | sy << 16) inside the support starting at
+// (bx, by), modulo the texture size; inside iff both offsets are < N.
+template <int N>
+__device__ __forceinline__ bool support_offset(uint32_t s, int bx, int by, uint32_t mx, uint32_t my,
+                                               uint32_t& dx, uint32_t& dy) {
+    dx = ((s & 0xFFFFu) - (uint32_t)bx) & mx;
+    dy = ((s >> 16) - (uint32_t)by) & my;
+    return dx < (uint32_t)N && dy < (uint32_t)N;
+}
+
+// Accumulate one shared pick (texel s, reciprocal PMF r, decoded texel Ti)
+// into pixel c's sums; picks outside c's support are skipped.
+template <int FILT, int C>
+__device__ __forceinline__ void accumulate(const SelCtx<FILT>& ctx, uint32_t s, float r, const float* Ti,
+                                           uint32_t mx, uint32_t my, const float* Tc, float& B, float* acc) {
+    constexpr int N = SelCtx<FILT>::N;
+    uint32_t dx, dy;
+    if (support_offset<N>(s, ctx.x.base, ctx.y.base, mx, my, dx, dy)) {
+        const float w = ctx.x.wsel(dx) * ctx.y.wsel(dy) * r;
         B += w;
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = fmaf(w, Ti[c] - Tc[c], acc[c]);
     }
 }
 
+// ---------------------------------------------------------------- texel bins
+
+// One bin per texel of a kBinG x kBinG window: N = sum of 1/p over the picks
+// of that texel, plus the texel itself (raw half bits or decoded floats).
+// gather() adds one bin's term of  sum_j f_c(j) N_j (T_j - T_c)  (EXACT) or
+// of  sum_j f_c(j) N_j T_j , and f_c(j) N_j to B.
+template <int P> struct Bins;
+
+template <> struct Bins<kF16x4> {             // record {raw.x, raw.y, N, 0}
+    __device__ static void clear(float* l, int lane) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) reinterpret_cast<uint4*>(l)[lane + 64 * i] = make_uint4(0, 0, 0, 0);
+    }
+    __device__ static void put(float* l, int bin, float r, const Texel<kF16x4>& T) {
+        atomicAdd(&l[bin * 4 + 2], r);
+        *reinterpret_cast<uint2*>(&l[bin * 4]) = T.raw;
+    }
+    template <bool EXACT>
+    __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
+        const uint4 q = reinterpret_cast<const uint4*>(l)[bin];
+        const float w = f * __uint_as_float(q.z);
+        B += w;
+        if constexpr (EXACT) {
+            acc[0] = fmaf(w, half_minus<0>(q.x, nTc[0]), acc[0]);
+            acc[1] = fmaf(w, half_minus<1>(q.x, nTc[1]), acc[1]);
+            acc[2] = fmaf(w, half_minus<0>(q.y, nTc[2]), acc[2]);
+            acc[3] = fmaf(w, half_minus<1>(q.y, nTc[3]), acc[3]);
+        } else {
+            acc[0] = fmaf(h2f(q.x), w, acc[0]);
+            acc[1] = fmaf(h2f(q.x >> 16), w, acc[1]);
+            acc[2] = fmaf(h2f(q.y), w, acc[2]);
+            acc[3] = fmaf(h2f(q.y >> 16), w, acc[3]);
+        }
+    }
+};
+
+template <> struct Bins<kF16x2> {             // record {raw, N}
+    __device__ static void clear(float* l, int lane) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) reinterpret_cast<uint4*>(l)[lane + 64 * i] = make_uint4(0, 0, 0, 0);
+    }
+    __device__ static void put(float* l, int bin, float r, const Texel<kF16x2>& T) {
+        atomicAdd(&l[bin * 2 + 1], r);
+        reinterpret_cast<uint32_t*>(l)[bin * 2] = T.raw;
+    }
+    template <bool EXACT>
+    __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
+        const uint2 q = reinterpret_cast<const uint2*>(l)[bin];
+        const float w = f * __uint_as_float(q.y);
+        B += w;
+        if constexpr (EXACT) {
+            acc[0] = fmaf(w, half_minus<0>(q.x, nTc[0]), acc[0]);
+            acc[1] = fmaf(w, half_minus<1>(q.x, nTc[1]), acc[1]);
+        } else {
+            acc[0] = fmaf(h2f(q.x), w, acc[0]);
+            acc[1] = fmaf(h2f(q.x >> 16), w, acc[1]);
+        }
+    }
+};
+
+template <> struct Bins<kF32x1> {             // record {T, N}
+    __device__ static void clear(float* l, int lane) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) reinterpret_cast<uint4*>(l)[lane + 64 * i] = make_uint4(0, 0, 0, 0);
+    }
+    __device__ static void put(float* l, int bin, float r, const Texel<kF32x1>& T) {
+        atomicAdd(&l[bin * 2 + 1], r);
+        l[bin * 2] = T.v[0];
+    }
+    template <bool EXACT>
+    __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
+        const float2 q = reinterpret_cast<const float2*>(l)[bin];
+        const float w = f * q.y;
+        B += w;
+        acc[0] = EXACT ? fmaf(w, q.x + nTc[0], acc[0]) : fmaf(q.x, w, acc[0]);
+    }
+};
+
+template <> struct Bins<kF32x4> {             // float4 T[kBins], then float N[kBins]
+    __device__ static void clear(float* l, int lane) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) reinterpret_cast<uint4*>(l)[lane + 64 * i] = make_uint4(0, 0, 0, 0);
+    }
+    __device__ static void put(float* l, int bin, float r, const Texel<kF32x4>& T) {
+        atomicAdd(&l[4 * kBins + bin], r);
+        reinterpret_cast<float4*>(l)[bin] = make_float4(T.v[0], T.v[1], T.v[2], T.v[3]);
+    }
+    template <bool EXACT>
+    __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
+        const float4 q = reinterpret_cast<const float4*>(l)[bin];
+        const float w = f * l[4 * kBins + bin];
+        B += w;
+        const float T[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = EXACT ? fmaf(w, T[c] + nTc[c], acc[c]) : fmaf(T[c], w, acc[c]);
+    }
+};
+
+// Bin window of the wave: kBinG x kBinG texels whose corner sits `margin`
+// texels before lane 0's support. Returns false (wave-uniformly) when some
+// on-screen pixel's support leaves the window.
+template <int N>
+__device__ __forceinline__ bool bin_window(const Pixel& P, int bx, int by, uint32_t mx, uint32_t my, int tw, int th,
+                                           int& base_x, int& base_y, uint32_t& rx, uint32_t& ry) {
+    constexpr int margin = (kBinG - N) / 2;
+    base_x = __builtin_amdgcn_readfirstlane(bx) - margin;
+    base_y = __builtin_amdgcn_readfirstlane(by) - margin;
+    rx = (uint32_t)(bx - base_x) & mx;
+    ry = (uint32_t)(by - base_y) & my;
+    const bool fits = !P.valid || (rx <= (uint32_t)(kBinG - N) && ry <= (uint32_t)(kBinG - N));
+    return (tw >= kBinG) && (th >= kBinG) && (__builtin_amdgcn_ballot_w64(!fits) == 0);
+}
+
 // Receive the pick of quad partner lane^X through DPP and accumulate it.
-template <int X, int N, int C>
-__device__ __forceinline__ void quad_step(uint32_t s, float r, const float* Tv, int bx, int by, uint32_t mx,
-                                          uint32_t my, const float* wx, const float* wy, float& B, float* acc) {
+template <int X, int FILT, int C>
+__device__ __forceinline__ void quad_step(const SelCtx<FILT>& ctx, uint32_t s, float r, const float* Tv, uint32_t mx,
+                                          uint32_t my, float& B, float* acc) {
     float Ti[C];
     const uint32_t si = quad_xor<X>(s);
     const float ri = quad_xor<X>(r);
 #pragma unroll
     for (int c = 0; c < C; ++c) Ti[c] = quad_xor<X>(Tv[c]);
-    accumulate<N, C>(si, ri, Ti, bx, by, mx, my, wx, wy, Tv, B, acc);
+    accumulate<FILT, C>(ctx, si, ri, Ti, mx, my, Tv, B, acc);
 }
 
-template <int FILT, int MODE, int C>
-__device__ __forceinline__ void slot_pass(const Args& a, int slot, const Pixel& P, float* lds) {
-    using Fl = Filter<FILT>;
-    constexpr int N = Fl::N;
-    const TexArg t = a.tex[slot];
-    const int lane = lane_id();
+// The one-tap pick of one texture slot: per-axis offsets, texel, and the
+// 16-byte block holding the texel (extracted after every load is issued).
+struct SlotPick {
+    int kx, ky;
+    uint32_t sx, sy;
+    uint4 raw;
+};
 
-    int i0x, Fx, i0y, Fy;
-    texel_split(P.u, t.w, i0x, Fx);
-    texel_split(P.v, t.h, i0y, Fy);
-    const uint2 h = slot_hash((uint32_t)P.px, (uint32_t)P.py, slot, a.seed, a.frame);
-    float wx[N], wy[N];
-    const int kx = Fl::pick(h.x, Fx, wx);
-    const int ky = Fl::pick(h.y, Fy, wy);
-    const int bx = i0x - Fl::DELTA, by = i0y - Fl::DELTA;    // first texel of the support
+template <int FILT>
+__device__ __forceinline__ SlotPick pick_slot(const TexArg& t, const SelCtx<FILT>& ctx, uint32_t hx, uint32_t hy) {
+    SlotPick k;
+    k.kx = ctx.x.pick(hx);
+    k.ky = ctx.y.pick(hy);
+    k.sx = (uint32_t)(ctx.x.base + k.kx) & ((uint32_t)t.w - 1u);
+    k.sy = (uint32_t)(ctx.y.base + k.ky) & ((uint32_t)t.h - 1u);
+    k.raw = fetch_block(t, k.sx, k.sy, format_bytes(t.fmt));
+    return k;
+}
+
+// Exchange and estimator for one texture slot of one pixel.
+template <int FILT, int MODE, int PL>
+__device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int slot, const Pixel& P,
+                                          const SelCtx<FILT>& ctx, const SlotPick& pk, float* lds) {
+    constexpr int N = SelCtx<FILT>::N;
+    constexpr int C = Texel<PL>::C;
+    const int lane = lane_id();
+    const int kx = pk.kx, ky = pk.ky;
     const uint32_t mx = (uint32_t)t.w - 1u, my = (uint32_t)t.h - 1u;
-    const uint32_t sx = (uint32_t)(bx + kx) & mx;
-    const uint32_t sy = (uint32_t)(by + ky) & my;
-    const Texel<C> T = fetch<C>(t, sx, sy);
+    const uint32_t sx = pk.sx, sy = pk.sy;
+    const Texel<PL> T = decode<PL>(block_texel(pk.raw, sx, format_bytes(t.fmt)), t.fmt);
     const int64_t pix = (int64_t)P.py * a.sw + P.px;
 
     if (a.sel != nullptr && P.valid) {
         int2* sp = reinterpret_cast<int2*>(a.sel) + ((int64_t)slot * a.sh * a.sw + pix);
         *sp = make_int2((int)sx, (int)sy);
     }
+    float Tv[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) Tv[c] = T.ch(c);
     if constexpr (MODE == kModeStf) {
-        if (P.valid) store_out<C>(a.out[slot], pix, T.v);
+        if (P.valid) store_out<C>(a.out[slot], pix, Tv);
         return;
     } else {
-        float pk_x = wx[0], pk_y = wy[0];
+        // 1/p of the own pick; off-screen pixels share a pick of weight zero
+        const float r = P.valid ? fast_rcp(ctx.x.wsel(kx) * ctx.y.wsel(ky)) : 0.0f;
+        if (!P.valid) {
 #pragma unroll
-        for (int k = 1; k < N; ++k) {
-            pk_x = (kx == k) ? wx[k] : pk_x;
-            pk_y = (ky == k) ? wy[k] : pk_y;
+            for (int c = 0; c < C; ++c) Tv[c] = 0.0f;
         }
-        // invalid pixels share a pick of weight zero
-        const float r = P.valid ? __frcp_rn(pk_x * pk_y) : 0.0f;
-        float Tv[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) Tv[c] = P.valid ? T.v[c] : 0.0f;
         const uint32_t s = sx | (sy << 16);
-
         float B = 1.0f;            // own pick: w_c = f_c / p_c = 1 (Sec. 4.5)
         float acc[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = 0.0f;
 
         if constexpr (MODE == kModeQuad) {
-            quad_step<1, N, C>(s, r, Tv, bx, by, mx, my, wx, wy, B, acc);
-            quad_step<2, N, C>(s, r, Tv, bx, by, mx, my, wx, wy, B, acc);
-            quad_step<3, N, C>(s, r, Tv, bx, by, mx, my, wx, wy, B, acc);
+            quad_step<1, FILT, C>(ctx, s, r, Tv, mx, my, B, acc);
+            quad_step<2, FILT, C>(ctx, s, r, Tv, mx, my, B, acc);
+            quad_step<3, FILT, C>(ctx, s, r, Tv, mx, my, B, acc);
         } else {
             bool use_bins = false;
             if constexpr (MODE == kModeBins) {
-                // Bin window: kBinG x kBinG texels around the support of lane 0.
-                constexpr int margin = (kBinG - N) / 2;
-                const int base_x = __builtin_amdgcn_readfirstlane(bx) - margin;
-                const int base_y = __builtin_amdgcn_readfirstlane(by) - margin;
-                const uint32_t rx = (uint32_t)(bx - base_x) & mx;
-                const uint32_t ry = (uint32_t)(by - base_y) & my;
-                const bool fits = !P.valid || (rx <= (uint32_t)(kBinG - N) && ry <= (uint32_t)(kBinG - N));
-                use_bins = (t.w >= kBinG) && (t.h >= kBinG) && (__builtin_amdgcn_ballot_w64(!fits) == 0);
+                int base_x, base_y;
+                uint32_t rx, ry;
+                use_bins = bin_window<N>(P, ctx.x.base, ctx.y.base, mx, my, t.w, t.h, base_x, base_y, rx, ry);
                 if (use_bins) {
-                    float* Nb = lds;                 // [kBins] sum of 1/p per texel
-                    float* Tb = lds + kBins;         // [kBins][C] texel values
-                    // clear: each lane zeroes 4 bins of N and 4 bins of T
-                    reinterpret_cast<float4*>(Nb)[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-                    for (int i = 0; i < C; ++i)
-                        reinterpret_cast<float4*>(Tb)[lane * C + i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    Bins<PL>::clear(lds, lane);
                     wave_lds_sync();
-                    if (P.valid) {
-                        const int bin = (int)(ry + ky) * kBinG + (int)(rx + kx);
-                        atomicAdd(&Nb[bin], r);
-#pragma unroll
-                        for (int c = 0; c < C; ++c) Tb[bin * C + c] = Tv[c];
-                    }
+                    if (P.valid) Bins<PL>::put(lds, (int)(ry + ky) * kBinG + (int)(rx + kx), r, T);
                     wave_lds_sync();
                     B = 0.0f;                        // the own pick is in the bins
+                    const int bin0 = (int)ry * kBinG + (int)rx;
+                    float nTc[C];
 #pragma unroll
-                    for (int b = 0; b < N; ++b) {
+                    for (int c = 0; c < C; ++c) nTc[c] = -Tv[c];
 #pragma unroll
-                        for (int aa = 0; aa < N; ++aa) {
-                            const int idx = (int)(ry + b) * kBinG + (int)rx + aa;
-                            const float w = wx[aa] * wy[b] * Nb[idx];
-                            B += w;
+                    for (int b = 0; b < N; ++b)
 #pragma unroll
-                            for (int c = 0; c < C; ++c) acc[c] = fmaf(w, Tb[idx * C + c] - Tv[c], acc[c]);
-                        }
+                        for (int aa = 0; aa < N; ++aa)
+                            Bins<PL>::template gather<kExactDiff>(lds, bin0 + b * kBinG + aa, ctx.wxy[b * N + aa], nTc,
+                                                                  B, acc);
+                    if constexpr (!kExactDiff) {
+                        // sum_j w_j T_j  ->  sum_j w_j (T_j - T_c), the form the final step expects
+#pragma unroll
+                        for (int c = 0; c < C; ++c) acc[c] = fmaf(-B, Tv[c], acc[c]);
                     }
                     wave_lds_sync();                 // reads done before the next slot reuses LDS
                 }
@@ -228,14 +369,14 @@ __device__ __forceinline__ void slot_pass(const Args& a, int slot, const Pixel& 
                     const uint2 mj = meta[j];
                     const float4 vj = val[j];
                     const float Ti[4] = {vj.x, vj.y, vj.z, vj.w};
-                    accumulate<N, C>(mj.x, __uint_as_float(mj.y), Ti, bx, by, mx, my, wx, wy, Tv, B, acc);
+                    accumulate<FILT, C>(ctx, mj.x, __uint_as_float(mj.y), Ti, mx, my, Tv, B, acc);
                 }
                 wave_lds_sync();
             }
         }
         if (P.valid) {
             float o[C];
-            const float inv = 1.0f / B;
+            const float inv = fast_rcp(B);
 #pragma unroll
             for (int c = 0; c < C; ++c) o[c] = fmaf(acc[c], inv, Tv[c]);
             store_out<C>(a.out[slot], pix, o);
@@ -260,46 +401,79 @@ __device__ __forceinline__ bool setup_pixel(const Args& a, Pixel& P) {
     return true;
 }
 
-template <int FILT, int MODE>
+// Random numbers of texture slot `slot`: slots 2q and 2q+1 share one pcg4d
+// evaluation keyed with seed + q * golden (first / last two outputs).
+__device__ __forceinline__ void slot_uniforms(const Args& a, const Pixel& P, int slot, uint4& hq, uint32_t& hx,
+                                              uint32_t& hy) {
+    if ((slot & 1) == 0)
+        hq = pcg4d(make_uint4((uint32_t)P.px, (uint32_t)P.py, a.frame, a.seed + (uint32_t)(slot >> 1) * kGolden));
+    hx = (slot & 1) ? hq.z : hq.x;
+    hy = (slot & 1) ? hq.w : hq.y;
+}
+
+__device__ __forceinline__ int payload_of(int fmt) {
+    switch (fmt) {
+    case STF_RGBA16F: return kF16x4;
+    case STF_RG16F: return kF16x2;
+    case STF_R8_UNORM: case STF_R32F: return kF32x1;
+    default: return kF32x4;
+    }
+}
+
+// NT textures, unrolled: descriptors are loaded once, and every pick and
+// texel fetch is issued before the first exchange so their latencies overlap.
+template <int FILT, int MODE, int NT>
 __global__ __launch_bounds__(kThreads) void forward_kernel(Args a) {
-    __shared__ __align__(16) float lds_all[kWavesPerGroup * kLdsFloatsPerWave];
+    __shared__ __align__(16) float lds_all[(MODE == kModeRecords || MODE == kModeBins) ? kWavesPerGroup * kLdsFloatsPerWave : 4];
     Pixel P;
     if (!setup_pixel(a, P)) return;
-    float* lds = lds_all + (threadIdx.x >> 6) * kLdsFloatsPerWave;
-    for (int slot = 0; slot < a.ntex; ++slot) {
-        const int ch = a.tex[slot].ch;
-        if (ch == 4) slot_pass<FILT, MODE, 4>(a, slot, P, lds);
-        else if (ch == 2) slot_pass<FILT, MODE, 2>(a, slot, P, lds);
-        else slot_pass<FILT, MODE, 1>(a, slot, P, lds);
+    float* lds = lds_all + ((MODE == kModeRecords || MODE == kModeBins) ? (threadIdx.x >> 6) * kLdsFloatsPerWave : 0);
+    TexArg t[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) t[i] = a.tex[i];
+    SelCtx<FILT> ctx;
+    SlotPick pk[NT];
+    uint4 hq;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        uint32_t hx, hy;
+        slot_uniforms(a, P, i, hq, hx, hy);
+        ctx.update(P, t[i].w, t[i].h);
+        pk[i] = pick_slot<FILT>(t[i], ctx, hx, hy);
+    }
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        ctx.update(P, t[i].w, t[i].h);
+        switch (payload_of(t[i].fmt)) {
+        case kF16x4: slot_pass<FILT, MODE, kF16x4>(a, t[i], i, P, ctx, pk[i], lds); break;
+        case kF16x2: slot_pass<FILT, MODE, kF16x2>(a, t[i], i, P, ctx, pk[i], lds); break;
+        case kF32x1: slot_pass<FILT, MODE, kF32x1>(a, t[i], i, P, ctx, pk[i], lds); break;
+        default: slot_pass<FILT, MODE, kF32x4>(a, t[i], i, P, ctx, pk[i], lds); break;
+        }
     }
 }
 
 // Deterministic filter, Eq. (3): sum over the support of f_c * T.
-template <int FILT, int C>
-__device__ __forceinline__ void reference_slot(const Args& a, int slot, const Pixel& P) {
-    using Fl = Filter<FILT>;
-    constexpr int N = Fl::N;
+template <int FILT, int PL>
+__device__ __forceinline__ void reference_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx) {
+    constexpr int N = SelCtx<FILT>::N;
+    constexpr int C = Texel<PL>::C;
     const TexArg t = a.tex[slot];
-    int i0x, Fx, i0y, Fy;
-    texel_split(P.u, t.w, i0x, Fx);
-    texel_split(P.v, t.h, i0y, Fy);
-    float wx[N], wy[N];
-    (void)Fl::pick(0u, Fx, wx);
-    (void)Fl::pick(0u, Fy, wy);
     const uint32_t mx = (uint32_t)t.w - 1u, my = (uint32_t)t.h - 1u;
+    const int bpp = format_bytes(t.fmt);
     float acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0f;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-        const uint32_t y = (uint32_t)(i0y - Fl::DELTA + b) & my;
+        const uint32_t y = (uint32_t)(ctx.y.base + b) & my;
 #pragma unroll
         for (int aa = 0; aa < N; ++aa) {
-            const uint32_t x = (uint32_t)(i0x - Fl::DELTA + aa) & mx;
-            const Texel<C> T = fetch<C>(t, x, y);
-            const float w = wx[aa] * wy[b];
+            const uint32_t x = (uint32_t)(ctx.x.base + aa) & mx;
+            const Texel<PL> T = decode<PL>(block_texel(fetch_block(t, x, y, bpp), x, bpp), t.fmt);
+            const float w = ctx.wxy[b * N + aa];
 #pragma unroll
-            for (int c = 0; c < C; ++c) acc[c] = fmaf(w, T.v[c], acc[c]);
+            for (int c = 0; c < C; ++c) acc[c] = fmaf(w, T.ch(c), acc[c]);
         }
     }
     if (P.valid) store_out<C>(a.out[slot], (int64_t)P.py * a.sw + P.px, acc);
@@ -309,11 +483,15 @@ template <int FILT>
 __global__ __launch_bounds__(kThreads) void reference_kernel(Args a) {
     Pixel P;
     if (!setup_pixel(a, P)) return;
+    SelCtx<FILT> ctx;
     for (int slot = 0; slot < a.ntex; ++slot) {
-        const int ch = a.tex[slot].ch;
-        if (ch == 4) reference_slot<FILT, 4>(a, slot, P);
-        else if (ch == 2) reference_slot<FILT, 2>(a, slot, P);
-        else reference_slot<FILT, 1>(a, slot, P);
+        ctx.update(P, a.tex[slot].w, a.tex[slot].h);
+        switch (payload_of(a.tex[slot].fmt)) {
+        case kF16x4: reference_slot<FILT, kF16x4>(a, slot, P, ctx); break;
+        case kF16x2: reference_slot<FILT, kF16x2>(a, slot, P, ctx); break;
+        case kF32x1: reference_slot<FILT, kF32x1>(a, slot, P, ctx); break;
+        default: reference_slot<FILT, kF32x4>(a, slot, P, ctx); break;
+        }
     }
 }
 
@@ -330,22 +508,6 @@ __global__ __launch_bounds__(kThreads) void reference_kernel(Args a) {
 // q_c = dL/dout_c / B_c, which is accumulated in LDS bins and flushed with
 // one global atomic per populated bin and channel.
 
-// f_c at texel (sx, sy) and whether it is inside c's support.
-template <int N>
-__device__ __forceinline__ bool own_weight(uint32_t s, int bx, int by, uint32_t mx, uint32_t my,
-                                           const float* wx, const float* wy, float& f) {
-    const uint32_t dx = ((s & 0xFFFFu) - (uint32_t)bx) & mx;
-    const uint32_t dy = ((s >> 16) - (uint32_t)by) & my;
-    float fx = wx[0], fy = wy[0];
-#pragma unroll
-    for (int k = 1; k < N; ++k) {
-        fx = (dx == (uint32_t)k) ? wx[k] : fx;
-        fy = (dy == (uint32_t)k) ? wy[k] : fy;
-    }
-    f = fx * fy;
-    return dx < (uint32_t)N && dy < (uint32_t)N;
-}
-
 template <int C>
 __device__ __forceinline__ void atomic_texel(float* g, int tw, uint32_t s, const float* v, float scale) {
     float* p = g + ((int64_t)(s >> 16) * tw + (s & 0xFFFFu)) * C;
@@ -354,24 +516,18 @@ __device__ __forceinline__ void atomic_texel(float* g, int tw, uint32_t s, const
 }
 
 template <int FILT, int MODE, int C>
-__device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pixel& P, float* lds) {
-    using Fl = Filter<FILT>;
-    constexpr int N = Fl::N;
+__device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
+                                              uint32_t hx, uint32_t hy, float* lds) {
+    constexpr int N = SelCtx<FILT>::N;
     const TexArg t = a.tex[slot];
     const int lane = lane_id();
-    int i0x, Fx, i0y, Fy;
-    texel_split(P.u, t.w, i0x, Fx);
-    texel_split(P.v, t.h, i0y, Fy);
-    const uint2 h = slot_hash((uint32_t)P.px, (uint32_t)P.py, slot, a.seed, a.frame);
-    float wx[N], wy[N];
-    const int kx = Fl::pick(h.x, Fx, wx);
-    const int ky = Fl::pick(h.y, Fy, wy);
-    const int bx = i0x - Fl::DELTA, by = i0y - Fl::DELTA;
+    const int kx = ctx.x.pick(hx);
+    const int ky = ctx.y.pick(hy);
     const uint32_t mx = (uint32_t)t.w - 1u, my = (uint32_t)t.h - 1u;
-    const uint32_t sx = (uint32_t)(bx + kx) & mx;
-    const uint32_t sy = (uint32_t)(by + ky) & my;
+    const uint32_t sx = (uint32_t)(ctx.x.base + kx) & mx;
+    const uint32_t sy = (uint32_t)(ctx.y.base + ky) & my;
     const uint32_t s = sx | (sy << 16);
-    float* grad = const_cast<float*>(a.out[slot]);           // dL/dT, [th][tw][C]
+    float* grad = a.out[slot];                              // dL/dT, [th][tw][C]
     const int64_t pix = (int64_t)P.py * a.sw + P.px;
     float g[C];
 #pragma unroll
@@ -381,14 +537,7 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
         if (P.valid) atomic_texel<C>(grad, t.w, s, g, 1.0f);
         return;
     } else {
-        float pk_x = wx[0], pk_y = wy[0];
-#pragma unroll
-        for (int k = 1; k < N; ++k) {
-            pk_x = (kx == k) ? wx[k] : pk_x;
-            pk_y = (ky == k) ? wy[k] : pk_y;
-        }
-        const float r = P.valid ? __frcp_rn(pk_x * pk_y) : 0.0f;
-
+        const float r = P.valid ? fast_rcp(ctx.x.wsel(kx) * ctx.y.wsel(ky)) : 0.0f;
         if constexpr (MODE == kModeQuad) {
             uint32_t si[3];
             float ri[3];
@@ -399,11 +548,13 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
             bool in[3];
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                in[m] = own_weight<N>(si[m], bx, by, mx, my, wx, wy, f[m]);
+                uint32_t dx, dy;
+                in[m] = support_offset<N>(si[m], ctx.x.base, ctx.y.base, mx, my, dx, dy);
+                f[m] = ctx.x.wsel(dx) * ctx.y.wsel(dy);
                 if (in[m]) B += f[m] * ri[m];
             }
             if (P.valid) {
-                const float inv = 1.0f / B;
+                const float inv = fast_rcp(B);
                 atomic_texel<C>(grad, t.w, s, g, inv);
 #pragma unroll
                 for (int m = 0; m < 3; ++m)
@@ -412,16 +563,12 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
         } else {
             bool use_bins = false;
             if constexpr (MODE == kModeBins) {
-                constexpr int margin = (kBinG - N) / 2;
-                const int base_x = __builtin_amdgcn_readfirstlane(bx) - margin;
-                const int base_y = __builtin_amdgcn_readfirstlane(by) - margin;
-                const uint32_t rx = (uint32_t)(bx - base_x) & mx;
-                const uint32_t ry = (uint32_t)(by - base_y) & my;
-                const bool fits = !P.valid || (rx <= (uint32_t)(kBinG - N) && ry <= (uint32_t)(kBinG - N));
-                use_bins = (t.w >= kBinG) && (t.h >= kBinG) && (__builtin_amdgcn_ballot_w64(!fits) == 0);
+                int base_x, base_y;
+                uint32_t rx, ry;
+                use_bins = bin_window<N>(P, ctx.x.base, ctx.y.base, mx, my, t.w, t.h, base_x, base_y, rx, ry);
                 if (use_bins) {
-                    float* Nb = lds;
-                    float* Qb = lds + kBins;
+                    float* Nb = lds;                 // [kBins] sum of 1/p per texel
+                    float* Qb = lds + kBins;         // [kBins][C] sum of f_c(x) q_c
                     reinterpret_cast<float4*>(Nb)[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
                     for (int i = 0; i < C; ++i)
@@ -429,21 +576,21 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                     wave_lds_sync();
                     if (P.valid) atomicAdd(&Nb[(int)(ry + ky) * kBinG + (int)(rx + kx)], r);
                     wave_lds_sync();
+                    const int bin0 = (int)ry * kBinG + (int)rx;
                     float B = 0.0f;
 #pragma unroll
                     for (int b = 0; b < N; ++b)
 #pragma unroll
-                        for (int aa = 0; aa < N; ++aa)
-                            B += wx[aa] * wy[b] * Nb[(int)(ry + b) * kBinG + (int)rx + aa];
+                        for (int aa = 0; aa < N; ++aa) B += ctx.wxy[b * N + aa] * Nb[bin0 + b * kBinG + aa];
                     if (P.valid) {
-                        const float inv = 1.0f / B;
+                        const float inv = fast_rcp(B);
 #pragma unroll
                         for (int b = 0; b < N; ++b)
 #pragma unroll
                             for (int aa = 0; aa < N; ++aa) {
-                                const int idx = (int)(ry + b) * kBinG + (int)rx + aa;
+                                const int idx = bin0 + b * kBinG + aa;
                                 if (Nb[idx] != 0.0f) {
-                                    const float f = wx[aa] * wy[b] * inv;
+                                    const float f = ctx.wxy[b * N + aa] * inv;
 #pragma unroll
                                     for (int c = 0; c < C; ++c) atomicAdd(&Qb[idx * C + c], f * g[c]);
                                 }
@@ -478,20 +625,21 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                     const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
                     if (j == P.q) continue;
                     const uint2 mj = meta[j];
-                    float f;
-                    if (own_weight<N>(mj.x, bx, by, mx, my, wx, wy, f)) B += f * __uint_as_float(mj.y);
+                    uint32_t dx, dy;
+                    if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy))
+                        B += ctx.x.wsel(dx) * ctx.y.wsel(dy) * __uint_as_float(mj.y);
                 }
                 if (P.valid) {
-                    const float inv = 1.0f / B;
+                    const float inv = fast_rcp(B);
                     atomic_texel<C>(grad, t.w, s, g, inv);
                     for (int m = 0; m < K; ++m) {
                         const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
                         if (j == P.q) continue;
                         const uint2 mj = meta[j];
                         const float rj = __uint_as_float(mj.y);
-                        float f;
-                        if (own_weight<N>(mj.x, bx, by, mx, my, wx, wy, f) && rj != 0.0f)
-                            atomic_texel<C>(grad, t.w, mj.x, g, f * rj * inv);
+                        uint32_t dx, dy;
+                        if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy) && rj != 0.0f)
+                            atomic_texel<C>(grad, t.w, mj.x, g, ctx.x.wsel(dx) * ctx.y.wsel(dy) * rj * inv);
                     }
                 }
                 wave_lds_sync();
@@ -506,11 +654,16 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(Args a) {
     Pixel P;
     if (!setup_pixel(a, P)) return;
     float* lds = lds_all + (threadIdx.x >> 6) * kLdsFloatsPerWave;
+    SelCtx<FILT> ctx;
+    uint4 hq;
     for (int slot = 0; slot < a.ntex; ++slot) {
+        uint32_t hx, hy;
+        slot_uniforms(a, P, slot, hq, hx, hy);
+        ctx.update(P, a.tex[slot].w, a.tex[slot].h);
         const int ch = a.tex[slot].ch;
-        if (ch == 4) backward_slot<FILT, MODE, 4>(a, slot, P, lds);
-        else if (ch == 2) backward_slot<FILT, MODE, 2>(a, slot, P, lds);
-        else backward_slot<FILT, MODE, 1>(a, slot, P, lds);
+        if (ch == 4) backward_slot<FILT, MODE, 4>(a, slot, P, ctx, hx, hy, lds);
+        else if (ch == 2) backward_slot<FILT, MODE, 2>(a, slot, P, ctx, hx, hy, lds);
+        else backward_slot<FILT, MODE, 1>(a, slot, P, ctx, hx, hy, lds);
     }
 }
 
@@ -583,11 +736,11 @@ int prepare(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const s
         if (!pow2(t.width) || !pow2(t.height) || t.width < 4 || t.height < 4 || t.width > 32768 || t.height > 32768)
             return fail(STF_EINVAL, "texture %d: %dx%d must be powers of two in 4..32768 for WRAP", i, t.width, t.height);
         if (need_data) {
-            if (t.pitch_bytes < (int64_t)t.width * bpp || t.pitch_bytes % bpp != 0)
-                return fail(STF_EINVAL, "texture %d: pitch %lld invalid for width %d x %d bytes", i,
-                            (long long)t.pitch_bytes, t.width, bpp);
-            if ((reinterpret_cast<uintptr_t>(t.data) % bpp) != 0)
-                return fail(STF_EINVAL, "texture %d: data not aligned to %d bytes", i, bpp);
+            if (t.pitch_bytes < (int64_t)t.width * bpp || t.pitch_bytes % 16 != 0)
+                return fail(STF_EINVAL, "texture %d: pitch %lld must be a multiple of 16 and >= width %d x %d bytes",
+                            i, (long long)t.pitch_bytes, t.width, bpp);
+            if ((reinterpret_cast<uintptr_t>(t.data) % 16) != 0)
+                return fail(STF_EINVAL, "texture %d: data not aligned to 16 bytes", i);
         }
         a.tex[i].data = static_cast<const uint8_t*>(t.data);
         a.tex[i].pitch = t.pitch_bytes;
@@ -638,7 +791,13 @@ int finish_launch(const char* what) {
 
 template <int FILT, int MODE>
 void launch_forward(const stf::Args& a, hipStream_t s) {
-    hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE>), grid_of(a), dim3(stf::kThreads), 0, s, a);
+    const dim3 g = grid_of(a), b(stf::kThreads);
+    switch (a.ntex) {
+    case 1: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 1>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 2>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 3>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 4>), g, b, 0, s, a); break;
+    }
 }
 
 int forward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,

@@ -16,7 +16,10 @@ namespace stf {
 constexpr int kTile = 8;
 constexpr int kWavesPerGroup = 4;          // 256-thread workgroup = 4 tiles side by side (32x8 px)
 constexpr int kThreads = 64 * kWavesPerGroup;
-constexpr int kBinG = 16;                  // texel bins per axis for whole-tile reuse
+#ifndef STF_BIN_G
+#define STF_BIN_G 16
+#endif
+constexpr int kBinG = STF_BIN_G;           // texel bins per axis for whole-tile reuse
 constexpr int kBins = kBinG * kBinG;
 constexpr uint32_t kGolden = 0x9E3779B9u;
 
@@ -72,13 +75,6 @@ __device__ __forceinline__ uint4 pcg4d(uint4 v) {
     return v;
 }
 
-// Two uniforms for pixel (px, py) and texture slot `slot`: slots 2q and
-// 2q+1 share one pcg4d evaluation keyed with seed + q * golden.
-__device__ __forceinline__ uint2 slot_hash(uint32_t px, uint32_t py, int slot, uint32_t seed, uint32_t frame) {
-    uint4 h = pcg4d(make_uint4(px, py, frame, seed + (uint32_t)(slot >> 1) * kGolden));
-    return (slot & 1) ? make_uint2(h.z, h.w) : make_uint2(h.x, h.y);
-}
-
 // ---------------------------------------------------------------- coordinates
 
 // Texel-space coordinate x = u * size - 0.5 in FP32 with two roundings
@@ -86,7 +82,8 @@ __device__ __forceinline__ uint2 slot_hash(uint32_t px, uint32_t py, int slot, u
 // fraction F = floor(2^16 (x - i0)) computed exactly as
 // floor(2^16 x) - 2^16 floor(x) (both terms are exact FP32 integers).
 __device__ __forceinline__ void texel_split(float u, int size, int& i0, int& F) {
-    const float x = __fsub_rn(__fmul_rn(u, (float)size), 0.5f);
+#pragma clang fp contract(off)
+    const float x = u * (float)size - 0.5f;
     const float fl = floorf(x);
     const float X = floorf(__fmul_rn(x, 65536.0f));
     F = (int)__fsub_rn(X, __fmul_rn(fl, 65536.0f)) & 0xFFFF;
@@ -95,21 +92,30 @@ __device__ __forceinline__ void texel_split(float u, int size, int& i0, int& F) 
 
 // ---------------------------------------------------------------- filters
 
-// Per-axis support size, offset of the first texel, selection and weights.
-template <int FILT> struct Filter;
+// Per-axis selection context of one pixel for one texture size: first
+// texel of the filter support, per-axis weights and the integer CDF
+// thresholds. Textures of equal size share it.
+template <int FILT> struct AxisCtx;
 
 // Bilinear (tent): texels i0, i0+1 with weights 1-phi, phi (the per-axis
 // factor of GetFilterPMF, Sec. S6). Offset 1 is picked iff
 // h >= (1-phi) 2^32, i.e. (h >> 16) >= 2^16 - F: probability exactly phi.
-template <> struct Filter<STF_BILINEAR> {
+template <> struct AxisCtx<STF_BILINEAR> {
     static constexpr int N = 2;
-    static constexpr int DELTA = 0;
-    __device__ __forceinline__ static int pick(uint32_t h, int F, float* w) {
-        const int G = 65536 - F;
-        w[0] = (float)G * (1.0f / 65536.0f);
-        w[1] = (float)F * (1.0f / 65536.0f);
-        return (int)((h >> 16) >= (uint32_t)G);
+    int base;            // first texel of the support (unwrapped)
+    uint32_t G;          // 2^16 - F
+    float w0, w1;        // scalars, not an array: lane-varying selection stays in registers
+    __device__ __forceinline__ void init(float u, int size) {
+        int i0, F;
+        texel_split(u, size, i0, F);
+        base = i0;
+        G = 65536u - (uint32_t)F;
+        w0 = (float)G * (1.0f / 65536.0f);
+        w1 = (float)F * (1.0f / 65536.0f);
     }
+    __device__ __forceinline__ int pick(uint32_t h) const { return (int)((h >> 16) >= G); }
+    __device__ __forceinline__ float w(int i) const { return i == 0 ? w0 : w1; }       // constant i
+    __device__ __forceinline__ float wsel(uint32_t k) const { return k ? w1 : w0; }   // lane-varying k
 };
 
 // Uniform cubic B-spline (Sec. 5.4): texels i0-1..i0+2. Multiplied by
@@ -117,73 +123,167 @@ template <> struct Filter<STF_BILINEAR> {
 //   G^3, 3F^3 - 6*2^16 F^2 + 4*2^48, 6*2^48 - (others), F^3   (G = 2^16 - F),
 // all below 2^53 and therefore exact in FP64. The offset is the number of
 // cumulative weights that h * 6 * 2^16 (exact, < 2^51) reaches.
-template <> struct Filter<STF_BICUBIC_BSPLINE> {
+template <> struct AxisCtx<STF_BICUBIC_BSPLINE> {
     static constexpr int N = 4;
-    static constexpr int DELTA = 1;
-    __device__ __forceinline__ static int pick(uint32_t h, int F, float* w) {
+    int base;
+    double c0, c01, c012;   // cumulative integer weights
+    float w0, w1, w2, w3;
+    __device__ __forceinline__ void init(float u, int size) {
+        int i0, F;
+        texel_split(u, size, i0, F);
+        base = i0 - 1;
         const double f = (double)F;
-        const double g = (double)(65536 - F);
+        const double g = 65536.0 - f;
         const double f2 = f * f;
         const double c3 = f2 * f;
-        const double c0 = g * g * g;
-        const double c1 = 3.0 * c3 - 393216.0 * f2 + 1125899906842624.0;   // + 4 * 2^48
-        const double total = 1688849860263936.0;                             // 6 * 2^48
-        const double c01 = c0 + c1;
-        const double c012 = total - c3;
-        const double hs = (double)h * 393216.0;
-        const int k = (int)(hs >= c0) + (int)(hs >= c01) + (int)(hs >= c012);
+        c0 = g * g * g;
+        const double c1 = fma(3.0, c3, fma(-393216.0, f2, 1125899906842624.0));   // + 4 * 2^48
+        const double total = 1688849860263936.0;                                  // 6 * 2^48
+        c01 = c0 + c1;
+        c012 = total - c3;
         const double s = 1.0 / total;
-        w[0] = (float)(c0 * s);
-        w[1] = (float)(c1 * s);
-        w[2] = (float)((c012 - c01) * s);
-        w[3] = (float)(c3 * s);
-        return k;
+        w0 = (float)(c0 * s);
+        w1 = (float)(c1 * s);
+        w2 = (float)((c012 - c01) * s);
+        w3 = (float)(c3 * s);
+    }
+    __device__ __forceinline__ int pick(uint32_t h) const {
+        const double hs = (double)h * 393216.0;
+        return (int)(hs >= c0) + (int)(hs >= c01) + (int)(hs >= c012);
+    }
+    __device__ __forceinline__ float w(int i) const { return i == 0 ? w0 : i == 1 ? w1 : i == 2 ? w2 : w3; }
+    __device__ __forceinline__ float wsel(uint32_t k) const {
+        const float lo = (k & 1u) ? w1 : w0;
+        const float hi = (k & 1u) ? w3 : w2;
+        return (k & 2u) ? hi : lo;
     }
 };
 
-// ---------------------------------------------------------------- texels
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-template <int C> struct Texel { float v[C]; };
+// ---------------------------------------------------------------- texels
 
 // clang vector types for the non-temporal load/store builtins
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 
-// Decode one texel of slot descriptor t at canonical (x, y). C is the
-// channel count of the format (validated on the host).
-template <int C>
-__device__ __forceinline__ Texel<C> fetch(const TexArg& t, uint32_t x, uint32_t y) {
-    Texel<C> r;
+__device__ __forceinline__ float h2f(uint32_t bits16) {
+    return __half2float(__ushort_as_half((unsigned short)(bits16 & 0xFFFFu)));
+}
+
+// Exact-once-rounded (half(lo or hi 16 bits of x) - c) in one v_fma_mix_f32:
+// fma(half, 1.0, -c) with the half operand converted inside the ALU. The
+// compiler folds fma(x, 1, c) into an add before it can form the mix
+// instruction, so it is written out (ALU only, no memory operands).
+template <int HI>
+__device__ __forceinline__ float half_minus(uint32_t x, float neg_c) {
+    float d;
+    if constexpr (HI)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(d) : "v"(x), "v"(neg_c));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(d) : "v"(x), "v"(neg_c));
+    return d;
+}
+
+// Texel payload kinds. F16x4 / F16x2 keep the raw half bits (exchanged and
+// binned as stored); F32x4 / F32x1 decode at fetch (RGBA8, RGBA32F / R8, R32F).
+enum Payload { kF16x4 = 0, kF16x2 = 1, kF32x4 = 2, kF32x1 = 3 };
+
+template <int P> struct Texel;
+template <> struct Texel<kF16x4> {
+    static constexpr int C = 4;
+    uint2 raw;
+    __device__ __forceinline__ float ch(int c) const {
+        return h2f(c < 2 ? (raw.x >> (16 * c)) : (raw.y >> (16 * (c - 2))));
+    }
+};
+template <> struct Texel<kF16x2> {
+    static constexpr int C = 2;
+    uint32_t raw;
+    __device__ __forceinline__ float ch(int c) const { return h2f(raw >> (16 * c)); }
+};
+template <> struct Texel<kF32x4> {
+    static constexpr int C = 4;
+    float v[4];
+    __device__ __forceinline__ float ch(int c) const { return v[c]; }
+};
+template <> struct Texel<kF32x1> {
+    static constexpr int C = 1;
+    float v[1];
+    __device__ __forceinline__ float ch(int) const { return v[0]; }
+};
+
+__device__ __forceinline__ int format_bytes(int fmt) {
+    switch (fmt) {
+    case STF_R8_UNORM: return 1;
+    case STF_RGBA16F: return 8;
+    case STF_RGBA32F: return 16;
+    default: return 4;               // RGBA8, RG16F, R32F
+    }
+}
+
+// One texel's payload as stored (1, 4, 8 or 16 bytes), zero-extended.
+__device__ __forceinline__ uint4 fetch_raw(const TexArg& t, uint32_t x, uint32_t y) {
     const uint8_t* row = t.data + (int64_t)y * t.pitch;
-    if constexpr (C == 4) {
-        if (t.fmt == STF_RGBA16F) {
-            const uint2 q = *reinterpret_cast<const uint2*>(row + (size_t)x * 8);
-            r.v[0] = __half2float(__ushort_as_half((unsigned short)(q.x & 0xFFFF)));
-            r.v[1] = __half2float(__ushort_as_half((unsigned short)(q.x >> 16)));
-            r.v[2] = __half2float(__ushort_as_half((unsigned short)(q.y & 0xFFFF)));
-            r.v[3] = __half2float(__ushort_as_half((unsigned short)(q.y >> 16)));
-        } else if (t.fmt == STF_RGBA8_UNORM) {
-            const uint32_t q = *reinterpret_cast<const uint32_t*>(row + (size_t)x * 4);
-            r.v[0] = (float)(q & 0xFF) * (1.0f / 255.0f);
-            r.v[1] = (float)((q >> 8) & 0xFF) * (1.0f / 255.0f);
-            r.v[2] = (float)((q >> 16) & 0xFF) * (1.0f / 255.0f);
-            r.v[3] = (float)(q >> 24) * (1.0f / 255.0f);
+    switch (format_bytes(t.fmt)) {
+    case 1: return make_uint4(row[x], 0u, 0u, 0u);
+    case 8: { const uint2 q = *reinterpret_cast<const uint2*>(row + (size_t)x * 8); return make_uint4(q.x, q.y, 0u, 0u); }
+    case 16: return *reinterpret_cast<const uint4*>(row + (size_t)x * 16);
+    default: return make_uint4(*reinterpret_cast<const uint32_t*>(row + (size_t)x * 4), 0u, 0u, 0u);
+    }
+}
+
+// The aligned 16-byte block holding texel (x, y): one load instruction for
+// every format, so the loads of several textures issue back to back with
+// no control flow between them. In bounds because pitch and base address
+// are multiples of 16 (validated on the host): the block starts at the
+// largest multiple of 16 not above the texel's row offset, which is at
+// most pitch - 16.
+__device__ __forceinline__ uint4 fetch_block(const TexArg& t, uint32_t x, uint32_t y, int bpp) {
+    const uint32_t off = (x * (uint32_t)bpp) & ~15u;
+    return *reinterpret_cast<const uint4*>(t.data + (int64_t)y * t.pitch + off);
+}
+
+// The texel's payload inside its block (zero-extended).
+__device__ __forceinline__ uint4 block_texel(uint4 b, uint32_t x, int bpp) {
+    const uint32_t o = (x * (uint32_t)bpp) & 15u;
+    const uint32_t lo = (o & 8u) ? b.z : b.x;
+    const uint32_t hi = (o & 8u) ? b.w : b.y;
+    switch (bpp) {
+    case 16: return b;
+    case 8: return make_uint4(lo, hi, 0u, 0u);
+    case 4: return make_uint4((o & 4u) ? hi : lo, 0u, 0u, 0u);
+    default: return make_uint4((((o & 4u) ? hi : lo) >> (8u * (o & 3u))) & 0xFFu, 0u, 0u, 0u);
+    }
+}
+
+// Texel of payload kind P from the raw payload of a texel of format fmt.
+template <int P>
+__device__ __forceinline__ Texel<P> decode(uint4 q, int fmt) {
+    Texel<P> r;
+    if constexpr (P == kF16x4) {
+        r.raw = make_uint2(q.x, q.y);
+    } else if constexpr (P == kF16x2) {
+        r.raw = q.x;
+    } else if constexpr (P == kF32x4) {
+        if (fmt == STF_RGBA8_UNORM) {
+            r.v[0] = (float)(q.x & 0xFF) * (1.0f / 255.0f);
+            r.v[1] = (float)((q.x >> 8) & 0xFF) * (1.0f / 255.0f);
+            r.v[2] = (float)((q.x >> 16) & 0xFF) * (1.0f / 255.0f);
+            r.v[3] = (float)(q.x >> 24) * (1.0f / 255.0f);
         } else {
-            const float4 q = *reinterpret_cast<const float4*>(row + (size_t)x * 16);
-            r.v[0] = q.x; r.v[1] = q.y; r.v[2] = q.z; r.v[3] = q.w;
+            r.v[0] = __uint_as_float(q.x); r.v[1] = __uint_as_float(q.y);
+            r.v[2] = __uint_as_float(q.z); r.v[3] = __uint_as_float(q.w);
         }
-    } else if constexpr (C == 2) {
-        const uint32_t q = *reinterpret_cast<const uint32_t*>(row + (size_t)x * 4);
-        r.v[0] = __half2float(__ushort_as_half((unsigned short)(q & 0xFFFF)));
-        r.v[1] = __half2float(__ushort_as_half((unsigned short)(q >> 16)));
     } else {
-        if (t.fmt == STF_R8_UNORM) {
-            r.v[0] = (float)row[x] * (1.0f / 255.0f);
-        } else {
-            r.v[0] = *reinterpret_cast<const float*>(row + (size_t)x * 4);
-        }
+        r.v[0] = (fmt == STF_R8_UNORM) ? (float)(q.x & 0xFF) * (1.0f / 255.0f) : __uint_as_float(q.x);
     }
     return r;
+}
+
+template <int P>
+__device__ __forceinline__ Texel<P> fetch(const TexArg& t, uint32_t x, uint32_t y) {
+    return decode<P>(fetch_raw(t, x, y), t.fmt);
 }
 
 template <int C>
