@@ -53,6 +53,41 @@ def measured_traffic():
     return d.get("bytes_per_launch")
 
 
+def summarize_pmc(fetch_csv: str, write_csv: str, out_path: str = TRAFFIC_FILE) -> dict:
+    """Per-launch HBM traffic of the benchmarked reuse kernel from two
+    rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch). Each counter is scaled by what it reads for the 512 MB copy of
+    the copy probe (whose true bytes are known), so the result is in bytes.
+    Only the two-texture dispatches (the timed launches) are averaged."""
+    import csv
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        copy = [float(r["Counter_Value"]) for r in rows
+                if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= 131072]
+        big = max(copy)
+        ref = [v for v in copy if v > 0.9 * big]
+        kern = [float(r["Counter_Value"]) for r in rows if "forward_kernel<1, 3, 2>" in r["Kernel_Name"]]
+        return sum(ref) / len(ref), kern
+
+    f_copy, f_k = per_kernel(fetch_csv, "FETCH_SIZE")
+    w_copy, w_k = per_kernel(write_csv, "WRITE_SIZE")
+    copy_bytes = 512 << 20
+    f_scale = copy_bytes / (f_copy * 1024.0)
+    w_scale = copy_bytes / (w_copy * 1024.0)
+    # the timed launches write outputs only; the selection-buffer launch writes more
+    w_sorted = sorted(w_k)[: max(1, len(w_k) - 1)]
+    fetch = sum(f_k) / len(f_k) * 1024.0 * f_scale
+    write = sum(w_sorted) / len(w_sorted) * 1024.0 * w_scale
+    d = {"kernel": "forward_kernel<bicubic, bins, 2 textures>", "source_hash": source_hash(),
+         "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+         "fetch_bytes_per_launch": int(fetch), "write_bytes_per_launch": int(write),
+         "bytes_per_launch": int(fetch + write), "launches_averaged": [len(f_k), len(w_sorted)]}
+    with open(out_path, "w") as f:
+        json.dump(d, f, indent=1)
+    return d
+
+
 def copy_probe(torch, dev, nbytes=512 << 20, reps=5):
     """Device-to-device copy of a buffer larger than the last-level cache:
     the achievable HBM rate (read + write bytes / time) and the reference
@@ -94,7 +129,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--sets", type=int, default=8, help="rotating UV/output buffer sets")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the per-launch traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(*args.summarize_pmc)))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
               "of this path is described in the design notes, not run.", file=sys.stderr)

@@ -43,10 +43,18 @@ enum Mode { kModeStf = 0, kModeQuad = 1, kModeRecords = 2, kModeBins = 3 };
 #define STF_EXACT_DIFF 1
 #endif
 constexpr bool kExactDiff = STF_EXACT_DIFF != 0;
+// 2D weights f_c = wx * wy from a per-pixel table (16 registers for the
+// B-spline) or formed per bin (one multiply more, fewer live registers).
+#ifndef STF_WEIGHT_TABLE
+#define STF_WEIGHT_TABLE 0
+#endif
+constexpr bool kWeightTable = STF_WEIGHT_TABLE != 0;
 
-// LDS per wavefront: bins (kBins x 16 B records, or kBins floats of N plus
-// kBins x 16 B of decoded texels) or records (64 x {s, r} + 64 x 16 B).
-constexpr int kLdsFloatsPerWave = kBins * 5;
+// LDS per wavefront: bins (kBinRecords x 16 B records, or kBinRecords floats
+// of N plus kBinRecords x 16 B of decoded texels) followed by kBinRecords
+// 64-bit fixed-point accumulators, or records (64 x {s, r} + 64 x 16 B).
+constexpr int kAccFloatOffset = kBinRecords * 5;
+constexpr int kLdsFloatsPerWave = kAccFloatOffset + kBinRecords * 2;
 
 struct Pixel {
     int px, py;          // screen pixel
@@ -146,18 +154,26 @@ __device__ __forceinline__ void accumulate(const SelCtx<FILT>& ctx, uint32_t s, 
 // of  sum_j f_c(j) N_j T_j , and f_c(j) N_j to B.
 template <int P> struct Bins;
 
-template <> struct Bins<kF16x4> {             // record {raw.x, raw.y, N, 0}
-    __device__ static void clear(float* l, int lane) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) reinterpret_cast<uint4*>(l)[lane + 64 * i] = make_uint4(0, 0, 0, 0);
+typedef unsigned int u3 __attribute__((ext_vector_type(3)));
+
+template <> struct Bins<kF16x4> {             // record {raw.x, raw.y, N, pad}, 16-byte aligned
+    __device__ static void clear_one(float* l, int rec) {
+        *reinterpret_cast<u3*>(__builtin_assume_aligned(&l[rec * 4], 16)) = u3{0u, 0u, 0u};
     }
     __device__ static void put(float* l, int bin, float r, const Texel<kF16x4>& T) {
         atomicAdd(&l[bin * 4 + 2], r);
         *reinterpret_cast<uint2*>(&l[bin * 4]) = T.raw;
     }
+    __device__ static void put_texel(float* l, int bin, const Texel<kF16x4>& T) {
+        *reinterpret_cast<uint2*>(&l[bin * 4]) = T.raw;
+    }
+    __device__ static void finalize(float* l, int rec, float n) {
+        if (n == 0.0f) clear_one(l, rec);
+        else l[rec * 4 + 2] = n;
+    }
     template <bool EXACT>
     __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
-        const uint4 q = reinterpret_cast<const uint4*>(l)[bin];
+        const u3 q = *reinterpret_cast<const u3*>(__builtin_assume_aligned(&l[bin * 4], 16));   // 12 of 16 bytes
         const float w = f * __uint_as_float(q.z);
         B += w;
         if constexpr (EXACT) {
@@ -175,13 +191,17 @@ template <> struct Bins<kF16x4> {             // record {raw.x, raw.y, N, 0}
 };
 
 template <> struct Bins<kF16x2> {             // record {raw, N}
-    __device__ static void clear(float* l, int lane) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i) reinterpret_cast<uint4*>(l)[lane + 64 * i] = make_uint4(0, 0, 0, 0);
-    }
+    __device__ static void clear_one(float* l, int rec) { reinterpret_cast<uint2*>(l)[rec] = make_uint2(0u, 0u); }
     __device__ static void put(float* l, int bin, float r, const Texel<kF16x2>& T) {
         atomicAdd(&l[bin * 2 + 1], r);
         reinterpret_cast<uint32_t*>(l)[bin * 2] = T.raw;
+    }
+    __device__ static void put_texel(float* l, int bin, const Texel<kF16x2>& T) {
+        reinterpret_cast<uint32_t*>(l)[bin * 2] = T.raw;
+    }
+    __device__ static void finalize(float* l, int rec, float n) {
+        if (n == 0.0f) clear_one(l, rec);
+        else l[rec * 2 + 1] = n;
     }
     template <bool EXACT>
     __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
@@ -199,13 +219,15 @@ template <> struct Bins<kF16x2> {             // record {raw, N}
 };
 
 template <> struct Bins<kF32x1> {             // record {T, N}
-    __device__ static void clear(float* l, int lane) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i) reinterpret_cast<uint4*>(l)[lane + 64 * i] = make_uint4(0, 0, 0, 0);
-    }
+    __device__ static void clear_one(float* l, int rec) { reinterpret_cast<uint2*>(l)[rec] = make_uint2(0u, 0u); }
     __device__ static void put(float* l, int bin, float r, const Texel<kF32x1>& T) {
         atomicAdd(&l[bin * 2 + 1], r);
         l[bin * 2] = T.v[0];
+    }
+    __device__ static void put_texel(float* l, int bin, const Texel<kF32x1>& T) { l[bin * 2] = T.v[0]; }
+    __device__ static void finalize(float* l, int rec, float n) {
+        if (n == 0.0f) clear_one(l, rec);
+        else l[rec * 2 + 1] = n;
     }
     template <bool EXACT>
     __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
@@ -216,19 +238,26 @@ template <> struct Bins<kF32x1> {             // record {T, N}
     }
 };
 
-template <> struct Bins<kF32x4> {             // float4 T[kBins], then float N[kBins]
-    __device__ static void clear(float* l, int lane) {
-#pragma unroll
-        for (int i = 0; i < 5; ++i) reinterpret_cast<uint4*>(l)[lane + 64 * i] = make_uint4(0, 0, 0, 0);
+template <> struct Bins<kF32x4> {             // float4 T[kBinRecords], then float N[kBinRecords]
+    __device__ static void clear_one(float* l, int rec) {
+        reinterpret_cast<uint4*>(l)[rec] = make_uint4(0u, 0u, 0u, 0u);
+        l[4 * kBinRecords + rec] = 0.0f;
     }
     __device__ static void put(float* l, int bin, float r, const Texel<kF32x4>& T) {
-        atomicAdd(&l[4 * kBins + bin], r);
+        atomicAdd(&l[4 * kBinRecords + bin], r);
         reinterpret_cast<float4*>(l)[bin] = make_float4(T.v[0], T.v[1], T.v[2], T.v[3]);
+    }
+    __device__ static void put_texel(float* l, int bin, const Texel<kF32x4>& T) {
+        reinterpret_cast<float4*>(l)[bin] = make_float4(T.v[0], T.v[1], T.v[2], T.v[3]);
+    }
+    __device__ static void finalize(float* l, int rec, float n) {
+        if (n == 0.0f) clear_one(l, rec);
+        else l[4 * kBinRecords + rec] = n;
     }
     template <bool EXACT>
     __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
         const float4 q = reinterpret_cast<const float4*>(l)[bin];
-        const float w = f * l[4 * kBins + bin];
+        const float w = f * l[4 * kBinRecords + bin];
         B += w;
         const float T[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
@@ -249,6 +278,50 @@ __device__ __forceinline__ bool bin_window(const Pixel& P, int bx, int by, uint3
     ry = (uint32_t)(by - base_y) & my;
     const bool fits = !P.valid || (rx <= (uint32_t)(kBinG - N) && ry <= (uint32_t)(kBinG - N));
     return (tw >= kBinG) && (th >= kBinG) && (__builtin_amdgcn_ballot_w64(!fits) == 0);
+}
+
+// Bounding box, in window coordinates, of every on-screen pixel's support:
+// one bit per support start column / row, OR-reduced over the wave.
+struct BinBox {
+    int x0, x1, y0, y1;
+};
+
+template <int N>
+__device__ __forceinline__ BinBox support_box(const Pixel& P, uint32_t rx, uint32_t ry) {
+    const uint32_t bits = wave_or(P.valid ? ((1u << rx) | (1u << (16u + ry))) : 0u);
+    BinBox b;
+    b.x0 = __builtin_ctz(bits & 0xFFFFu);
+    b.x1 = 31 - __builtin_clz(bits & 0xFFFFu) + N - 1;
+    b.y0 = __builtin_ctz(bits >> 16);
+    b.y1 = 31 - __builtin_clz(bits >> 16) + N - 1;
+    return b;
+}
+
+// Calls f(record) for every bin of the box: lanes cover four rows of 16
+// columns per step (wave-uniform trip count).
+template <typename F>
+__device__ __forceinline__ void for_box(const BinBox& b, int lane, F f) {
+    const int col = lane & 15;
+    for (int y = b.y0 + (lane >> 4); y - (lane >> 4) <= b.y1; y += 4)
+        if (y <= b.y1 && col >= b.x0 && col <= b.x1) f(y * kBinStride + col);
+}
+
+// Exact sums of 1/p per bin. With e_max the largest biased exponent of the
+// wave's reciprocal PMFs, every r whose exponent is at least e_max - 33 is
+// the integer m * 2^(e - e_max + 33) times 2^(e_max - 183) (m = 24-bit
+// significand), and at most 64 of them stay below 2^63: the 64-bit integer
+// sums are exact and independent of the order of the atomic adds. Bins are
+// then converted once (rounded once to FP32). Waves whose exponents span
+// more than 33 fall back to FP32 atomics.
+__device__ __forceinline__ uint64_t fixed_of(float r, uint32_t e_max) {
+    const uint32_t b = __float_as_uint(r);
+    const uint32_t m = (b & 0x7FFFFFu) | 0x800000u;
+    return (uint64_t)m << ((b >> 23) - e_max + 33u);
+}
+
+__device__ __forceinline__ float float_of(uint64_t n, uint32_t e_max) {
+    const double d = fma((double)(uint32_t)(n >> 32), 4294967296.0, (double)(uint32_t)n);   // exact below 2^53, else rounded once
+    return (float)ldexp(d, (int)e_max - 183);
 }
 
 // Receive the pick of quad partner lane^X through DPP and accumulate it.
@@ -329,21 +402,42 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
                 uint32_t rx, ry;
                 use_bins = bin_window<N>(P, ctx.x.base, ctx.y.base, mx, my, t.w, t.h, base_x, base_y, rx, ry);
                 if (use_bins) {
-                    Bins<PL>::clear(lds, lane);
-                    wave_lds_sync();
-                    if (P.valid) Bins<PL>::put(lds, (int)(ry + ky) * kBinG + (int)(rx + kx), r, T);
+                    const BinBox box = support_box<N>(P, rx, ry);
+                    const int my_bin = (int)(ry + ky) * kBinStride + (int)(rx + kx);
+                    const uint32_t e = P.valid ? (__float_as_uint(r) >> 23) : 0u;
+                    const uint32_t e_max = wave_max(e);
+                    const bool fixed = __builtin_amdgcn_ballot_w64(P.valid && e + 33u < e_max) == 0;
+                    if (fixed) {
+                        uint64_t* acc64 = reinterpret_cast<uint64_t*>(lds + kAccFloatOffset);
+                        for_box(box, lane, [&](int rec) { acc64[rec] = 0ull; });
+                        wave_lds_sync();
+                        if (P.valid) {
+                            atomicAdd(reinterpret_cast<unsigned long long*>(&acc64[my_bin]),
+                                      (unsigned long long)fixed_of(r, e_max));
+                            Bins<PL>::put_texel(lds, my_bin, T);
+                        }
+                        wave_lds_sync();
+                        for_box(box, lane, [&](int rec) { Bins<PL>::finalize(lds, rec, float_of(acc64[rec], e_max)); });
+                    } else {
+                        for_box(box, lane, [&](int rec) { Bins<PL>::clear_one(lds, rec); });
+                        wave_lds_sync();
+                        if (P.valid) Bins<PL>::put(lds, my_bin, r, T);
+                    }
                     wave_lds_sync();
                     B = 0.0f;                        // the own pick is in the bins
-                    const int bin0 = (int)ry * kBinG + (int)rx;
+                    const int bin0 = (int)ry * kBinStride + (int)rx;
                     float nTc[C];
 #pragma unroll
                     for (int c = 0; c < C; ++c) nTc[c] = -Tv[c];
 #pragma unroll
-                    for (int b = 0; b < N; ++b)
+                    for (int b = 0; b < N; ++b) {
+                        const float wyb = ctx.y.w(b);
 #pragma unroll
                         for (int aa = 0; aa < N; ++aa)
-                            Bins<PL>::template gather<kExactDiff>(lds, bin0 + b * kBinG + aa, ctx.wxy[b * N + aa], nTc,
-                                                                  B, acc);
+                            Bins<PL>::template gather<kExactDiff>(lds, bin0 + b * kBinStride + aa,
+                                                                  kWeightTable ? ctx.wxy[b * N + aa] : ctx.x.w(aa) * wyb,
+                                                                  nTc, B, acc);
+                    }
                     if constexpr (!kExactDiff) {
                         // sum_j w_j T_j  ->  sum_j w_j (T_j - T_c), the form the final step expects
 #pragma unroll
@@ -569,10 +663,8 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                 if (use_bins) {
                     float* Nb = lds;                 // [kBins] sum of 1/p per texel
                     float* Qb = lds + kBins;         // [kBins][C] sum of f_c(x) q_c
-                    reinterpret_cast<float4*>(Nb)[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-                    for (int i = 0; i < C; ++i)
-                        reinterpret_cast<float4*>(Qb)[lane * C + i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    static_assert(kBins * (1 + 4) <= kLdsFloatsPerWave, "backward bins exceed the wave's LDS");
+                    for (int i = lane; i < kBins * (1 + C); i += 64) lds[i] = 0.0f;
                     wave_lds_sync();
                     if (P.valid) atomicAdd(&Nb[(int)(ry + ky) * kBinG + (int)(rx + kx)], r);
                     wave_lds_sync();
@@ -597,10 +689,8 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                             }
                     }
                     wave_lds_sync();
-                    // flush: lane handles bins lane, lane+64, lane+128, lane+192
-#pragma unroll
-                    for (int k = 0; k < kBins / 64; ++k) {
-                        const int idx = lane + 64 * k;
+                    // flush: lane handles bins lane, lane + 64, ...
+                    for (int idx = lane; idx < kBins; idx += 64) {
                         const float nx = Nb[idx];
                         if (nx != 0.0f) {
                             const uint32_t tx = (uint32_t)(base_x + (idx % kBinG)) & mx;

@@ -17,10 +17,12 @@ constexpr int kTile = 8;
 constexpr int kWavesPerGroup = 4;          // 256-thread workgroup = 4 tiles side by side (32x8 px)
 constexpr int kThreads = 64 * kWavesPerGroup;
 #ifndef STF_BIN_G
-#define STF_BIN_G 16
+#define STF_BIN_G 12
 #endif
 constexpr int kBinG = STF_BIN_G;           // texel bins per axis for whole-tile reuse
 constexpr int kBins = kBinG * kBinG;
+constexpr int kBinStride = kBinG + 1;      // records per bin row (padded: rows fall on different LDS banks)
+constexpr int kBinRecords = kBinG * kBinStride;
 constexpr uint32_t kGolden = 0x9E3779B9u;
 
 struct TexArg {
@@ -301,6 +303,29 @@ __device__ __forceinline__ void store_out(float* out, int64_t pix, const float* 
 }
 
 // ---------------------------------------------------------------- DPP
+
+// Maximum of v over the 64 lanes of the wavefront (DPP within rows of 16
+// lanes, then the four row results).
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+    const uint32_t a = max((uint32_t)__builtin_amdgcn_readlane((int)v, 0), (uint32_t)__builtin_amdgcn_readlane((int)v, 16));
+    const uint32_t b = max((uint32_t)__builtin_amdgcn_readlane((int)v, 32), (uint32_t)__builtin_amdgcn_readlane((int)v, 48));
+    return max(a, b);
+}
+
+// Bitwise OR of v over the 64 lanes of the wavefront (DPP within rows of
+// 16 lanes, then the four row results).
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);    // quad_perm [1,0,3,2]
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);    // quad_perm [2,3,0,1]
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);   // row_half_mirror
+    v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);   // row_mirror
+    return (uint32_t)(__builtin_amdgcn_readlane((int)v, 0) | __builtin_amdgcn_readlane((int)v, 16) |
+                      __builtin_amdgcn_readlane((int)v, 32) | __builtin_amdgcn_readlane((int)v, 48));
+}
 
 // Value of `v` held by lane (lane ^ X) within the same quad of 4 lanes.
 template <int X>

@@ -28,7 +28,7 @@ import numpy as np
 __all__ = [
     "value_noise", "small_texture", "small_screen", "plane_albedo", "plane_normal",
     "PlaneCamera", "perspective_plane", "tile_texture_rgba8", "r8_texture",
-    "latent_grid", "mlp_weights", "view_set",
+    "latent_grid", "mlp_weights", "view_set", "halton", "material_set", "frame_jitter",
 ]
 
 
@@ -336,3 +336,29 @@ def view_set(n_views: int = 8, width: int = 1920, height: int = 1080, tex_size: 
         uv, _, _, _ = perspective_plane(width, height, tex_size, 2.0, 16.0, jitter=jit, uv_offset=off)
         views.append(uv)
     return views
+
+
+# ----------------------------------------------------------------------------
+# four-texture 4K material workload
+# ----------------------------------------------------------------------------
+
+def halton(i: int, base: int) -> float:
+    """i-th element (1-based) of the radical-inverse Halton sequence."""
+    f, r = 1.0, 0.0
+    while i > 0:
+        f /= base
+        r += f * (i % base)
+        i //= base
+    return r
+
+
+def frame_jitter(frame: int) -> tuple:
+    """Sub-pixel jitter of frame `frame`: Halton(2, 3) point minus 1/2."""
+    return (halton(frame + 1, 2) - 0.5, halton(frame + 1, 3) - 0.5)
+
+
+def material_set(seed: int = 0):
+    """Four material textures sharing one UV set: albedo RGBA8 2048^2,
+    normal RG16F 2048^2, roughness R8 1024^2, mask R8 512^2."""
+    return [tile_texture_rgba8(seed, 2048), plane_normal(seed, 2048), r8_texture(seed + 1, 1024),
+            r8_texture(seed + 2, 512)]
