@@ -31,6 +31,7 @@ __all__ = [
     "footprint_members", "decode_texels", "stf_samples",
     "stf_filter", "stf_filter_reuse", "reference_filter", "stf_adjoint",
     "tiles_to_image", "all_tiles", "psnr",
+    "fp8e4m3_value", "bf16_value", "dequantize", "mlp_decode", "decode_latent_texture",
 ]
 
 BILINEAR = "bilinear"
@@ -266,6 +267,68 @@ def decode_texels(raw: np.ndarray) -> np.ndarray:
     if raw.dtype in (np.float16, np.float32, np.float64):
         return raw.astype(np.float64)
     raise TypeError(raw.dtype)
+
+
+# --------------------------------------------------------------------------
+# reduced-precision payloads and the latent decoder
+# --------------------------------------------------------------------------
+
+def fp8e4m3_value(codes) -> np.ndarray:
+    """Value of OCP FP8 E4M3 (e4m3fn) codes: 1 sign bit, 4 exponent bits with
+    bias 7, 3 mantissa bits; exponent 0 is subnormal (m/8 * 2^-6); the two
+    codes S.1111.111 are NaN; there are no infinities (max finite 448)."""
+    c = np.asarray(codes).astype(np.int64)
+    sign = np.where(c & 0x80, -1.0, 1.0)
+    e = (c >> 3) & 0xF
+    m = (c & 0x7).astype(np.float64)
+    val = np.where(e == 0, m / 8.0 * 2.0 ** -6, (1.0 + m / 8.0) * np.exp2(e.astype(np.float64) - 7.0))
+    val = np.where((e == 0xF) & ((c & 0x7) == 0x7), np.nan, val)
+    return sign * val
+
+
+def bf16_value(bits) -> np.ndarray:
+    """Value of bfloat16 bit patterns (the upper half of an FP32)."""
+    b = np.asarray(bits).astype(np.uint32) << np.uint32(16)
+    return b.view(np.float32).astype(np.float64)
+
+
+def dequantize(stored: np.ndarray, kind: str, scale) -> np.ndarray:
+    """Payload of kind 'f16' | 'bf16' (uint16 bits) | 'fp8' (uint8 codes) |
+    'f32' times its per-channel scale (last axis), in FP64."""
+    if kind == "f16":
+        v = np.asarray(stored).view(np.float16).astype(np.float64) if np.asarray(stored).dtype != np.float16 \
+            else np.asarray(stored).astype(np.float64)
+    elif kind == "bf16":
+        v = bf16_value(stored)
+    elif kind == "fp8":
+        v = fp8e4m3_value(stored)
+    elif kind == "f32":
+        v = np.asarray(stored, dtype=np.float64)
+    else:
+        raise ValueError(kind)
+    if scale is None:
+        return v
+    return v * np.asarray(scale, dtype=np.float64)
+
+
+def mlp_decode(latent: np.ndarray, layers) -> np.ndarray:
+    """The latent decoder MLP in FP64: ReLU(W1 x + b1) -> ReLU(W2 . + b2) ->
+    W3 . + b3, weights W_l [out, in] and biases b_l given in FP64 (already
+    dequantized). latent [..., in]; returns [..., out]."""
+    h = np.asarray(latent, dtype=np.float64)
+    for li, (w, b) in enumerate(layers):
+        h = h @ np.asarray(w, dtype=np.float64).T + np.asarray(b, dtype=np.float64)
+        if li < len(layers) - 1:
+            h = np.maximum(h, 0.0)
+    return h
+
+
+def decode_latent_texture(stored, kind, scale, layers) -> np.ndarray:
+    """Every texel of a latent grid decoded once: [H, W, 8] -> [H, W, 4] FP64.
+    Decoding is per texel, so filtering the decoded texture with one-tap STF,
+    reuse or Eq. (3) equals decoding each texel the filter touches (the
+    neural-texture setting of Sec. 1 and Sec. 5.6)."""
+    return mlp_decode(dequantize(stored, kind, scale), layers)
 
 
 # --------------------------------------------------------------------------
