@@ -25,7 +25,8 @@
  *     texture slot index.
  *   - Screen layout: UV is FP32 [height][width][2] row-major (u then v);
  *     outputs are FP32 [height][width][C] row-major, C = channels of the
- *     texture format; pixel (px, py) has its centre at (px+1/2, py+1/2).
+ *     texture format (4 for latent formats, which are decoded); pixel
+ *     (px, py) has its centre at (px+1/2, py+1/2).
  *   - Texture layout: row y starts at data + y * pitch_bytes; texels are
  *     tightly packed within a row. Texel (0,0) is the first texel. The base
  *     address and pitch_bytes are multiples of 16 and the allocation holds
@@ -46,7 +47,7 @@
 extern "C" {
 #endif
 
-#define STF_VERSION 1
+#define STF_VERSION 2
 #define STF_MAX_TEXTURES 4
 #define STF_MAX_SCREEN 32768
 
@@ -62,13 +63,18 @@ typedef enum stf_filter_kind {
     STF_BICUBIC_BSPLINE = 1  /* uniform cubic B-spline, 4x4 support (Sec. 5.4) */
 } stf_filter_kind;
 
-typedef enum stf_format {      /* channels, bytes per texel, decode */
+typedef enum stf_format {      /* channels, bytes per texel, decode (times the optional per-channel scale) */
     STF_RGBA8_UNORM = 0,       /* 4, 4,  byte / 255 (linear, no sRGB) */
     STF_RGBA16F = 1,           /* 4, 8,  IEEE half, exact */
     STF_RG16F = 2,             /* 2, 4,  IEEE half, exact */
     STF_R8_UNORM = 3,          /* 1, 1,  byte / 255 */
     STF_RGBA32F = 4,           /* 4, 16, exact */
-    STF_R32F = 5               /* 1, 4,  exact */
+    STF_R32F = 5,              /* 1, 4,  exact */
+    STF_RGBA_BF16 = 6,         /* 4, 8,  bfloat16, exact */
+    STF_RGBA_FP8 = 7,          /* 4, 4,  OCP FP8 E4M3 (bias 7, no infinities), exact */
+    STF_LATENT8_F16 = 8,       /* 8 latent channels, 16, half; decoded to RGBA by the texture's decoder */
+    STF_LATENT8_BF16 = 9,      /* 8 latent channels, 16, bfloat16; decoded likewise */
+    STF_LATENT8_FP8 = 10       /* 8 latent channels, 8, FP8 E4M3; decoded likewise */
 } stf_format;
 
 typedef enum stf_address {
@@ -96,6 +102,12 @@ typedef struct stf_texture {
     int64_t pitch_bytes;    /* >= width * bytes per texel, multiple of 16 */
     int32_t format;         /* stf_format */
     int32_t reserved;       /* must be 0 */
+    const float* scale;     /* host, nullable: per-channel dequantization scale (one per stored
+                               channel: 8 for latent formats, applied before the decoder),
+                               finite; NULL means 1. Read during the call only. */
+    const void* decoder;    /* device, STF_DECODER_BYTES written by stf_decoder_pack: required
+                               for latent formats (all latent textures of one call share one
+                               decoder), NULL otherwise; 16-byte aligned */
 } stf_texture;
 
 typedef struct stf_screen {
@@ -174,11 +186,42 @@ int stf_filter_reference(const stf_texture* tex, int32_t ntex, const stf_screen*
  *          dense (pitch = width * C_t * 4); ACCUMULATED into (+=), so clear
  *          it first for a plain gradient. Summation order is not fixed
  *          (floating-point atomics): results agree to rounding, not bits.
- * Same p and r as the forward call being differentiated.
+ * Same p and r as the forward call being differentiated. Latent formats
+ * are rejected (STF_EUNSUPPORTED). A per-channel scale multiplies dL/dout,
+ * so dtex is the gradient with respect to the texel before its scale.
  */
 int stf_backward(const stf_texture* tex, int32_t ntex, const stf_screen* scr,
                  const stf_params* p, const stf_reuse* r, const float* const* dout,
                  float* const* dtex, void* hip_stream);
+
+/*
+ * Latent decoder MLP of the neural-texture setting (Sec. 1, Sec. 5.6):
+ *     RGBA = W3 ReLU(W2 ReLU(W1 x + b1) + b2) + b3,   x = 8 latent channels.
+ * Arrays are device FP32, row-major [out][in]. Latent textures are decoded
+ * per picked texel on the matrix cores with BF16 operands and FP32
+ * accumulation: w1, b1, w2 and w3 are rounded to BF16 (round to nearest
+ * even) when packed, b2 and b3 stay FP32, the latents (times their scale)
+ * and the hidden activations are rounded to BF16.
+ */
+typedef struct stf_mlp {
+    const float* w1;        /* [64][8] */
+    const float* b1;        /* [64] */
+    const float* w2;        /* [64][64] */
+    const float* b2;        /* [64] */
+    const float* w3;        /* [4][64] */
+    const float* b3;        /* [4] */
+} stf_mlp;
+
+#define STF_DECODER_BYTES 14720
+
+/*
+ * Pack `mlp` into the device buffer `packed` (STF_DECODER_BYTES, 16-byte
+ * aligned, owned by the caller), enqueued on `hip_stream`. The buffer is then
+ * named by stf_texture.decoder of latent textures, in calls on the same
+ * stream or after synchronisation. The weights are read on the device and
+ * are not validated (non-finite values propagate to the outputs).
+ */
+int stf_decoder_pack(const stf_mlp* mlp, void* packed, void* hip_stream);
 
 /* Message for the last non-OK status returned on this thread ("" if none).
  * The pointer stays valid until the next call on this thread. */

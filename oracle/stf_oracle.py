@@ -32,6 +32,7 @@ __all__ = [
     "stf_filter", "stf_filter_reuse", "reference_filter", "stf_adjoint",
     "tiles_to_image", "all_tiles", "psnr",
     "fp8e4m3_value", "bf16_value", "dequantize", "mlp_decode", "decode_latent_texture",
+    "texture_values",
 ]
 
 BILINEAR = "bilinear"
@@ -293,9 +294,12 @@ def bf16_value(bits) -> np.ndarray:
 
 
 def dequantize(stored: np.ndarray, kind: str, scale) -> np.ndarray:
-    """Payload of kind 'f16' | 'bf16' (uint16 bits) | 'fp8' (uint8 codes) |
-    'f32' times its per-channel scale (last axis), in FP64."""
-    if kind == "f16":
+    """Payload of kind 'unorm8' (bytes) | 'f16' | 'bf16' (uint16 bits) |
+    'fp8' (uint8 codes) | 'f32' times its per-channel scale (last axis), in
+    FP64."""
+    if kind == "unorm8":
+        v = np.asarray(stored).astype(np.float64) / 255.0
+    elif kind == "f16":
         v = np.asarray(stored).view(np.float16).astype(np.float64) if np.asarray(stored).dtype != np.float16 \
             else np.asarray(stored).astype(np.float64)
     elif kind == "bf16":
@@ -331,6 +335,27 @@ def decode_latent_texture(stored, kind, scale, layers) -> np.ndarray:
     return mlp_decode(dequantize(stored, kind, scale), layers)
 
 
+def texture_values(tex) -> np.ndarray:
+    """FP64 texel values [H, W, C] of a texture argument. A plain array is
+    decoded by decode_texels; a tuple (stored, kind, scale) is dequantized
+    (per-channel scale, None for 1); a tuple (stored, kind, scale, layers) is
+    a latent grid decoded per texel by the MLP."""
+    if isinstance(tex, tuple):
+        if len(tex) == 4:
+            return decode_latent_texture(*tex)
+        stored, kind, scale = tex
+        return dequantize(stored, kind, scale)
+    return decode_texels(tex)
+
+
+def _texture_scale(tex, channels: int) -> np.ndarray:
+    """Per-channel factor applied after decoding a stored texel (1 for
+    plain arrays and latent grids, whose scale precedes the decoder)."""
+    if isinstance(tex, tuple) and len(tex) == 3 and tex[2] is not None:
+        return np.asarray(tex[2], dtype=np.float64)
+    return np.ones(channels)
+
+
 # --------------------------------------------------------------------------
 # one-tap STF samples for a batch of tiles
 # --------------------------------------------------------------------------
@@ -344,7 +369,8 @@ def stf_samples(tex: np.ndarray, uv: np.ndarray, tiles: np.ndarray, slot: int,
     filter, exactly as one-tap STF does (Sec. 2.2; Sec. S1 shows the
     importance-sampling estimator then returns the texel unweighted)."""
     H, W = uv.shape[:2]
-    th, tw = tex.shape[:2]
+    values = texture_values(tex)
+    th, tw = values.shape[:2]
     px, py = _tile_pixels(tiles)
     valid = (px < W) & (py < H)
     pxc = np.minimum(px, W - 1)
@@ -366,7 +392,7 @@ def stf_samples(tex: np.ndarray, uv: np.ndarray, tiles: np.ndarray, slot: int,
     wx = axis_weights(Fx, filt)
     wy = axis_weights(Fy, filt)
     p = np.take_along_axis(wx, kx[..., None], -1)[..., 0] * np.take_along_axis(wy, ky[..., None], -1)[..., 0]
-    T = decode_texels(tex)[sy, sx]
+    T = values[sy, sx]
     return dict(valid=valid, px=px, py=py, i0x=i0x, i0y=i0y, Fx=Fx, Fy=Fy, wx=wx, wy=wy,
                 kx=kx, ky=ky, sx=sx, sy=sy, p=p, T=T, delta=delta, tw=tw, th=th)
 
@@ -460,7 +486,7 @@ def reference_filter(textures, uv, filt, tiles=None):
     out = []
     for tex in textures:
         s = stf_samples(tex, uv, tiles, 0, filt, 0, 0)
-        T = decode_texels(tex)
+        T = texture_values(tex)
         n = s["wx"].shape[-1]
         acc = np.zeros(s["T"].shape, dtype=np.float64)
         for b in range(n):
@@ -482,7 +508,9 @@ def stf_adjoint(textures, uv, filt, seed, frame, footprint, grads, lut=None, til
     The weights of Eq. (14) depend only on positions and random numbers, so
     out_c = sum_i a_ci T[x_i] with a_ci = w_i / sum_j w_j is linear in the
     texels and dL/dT[x] = sum_c sum_{i in S(c), x_i = x} a_ci dL/dout_c.
-    grads: per slot [n, 64, C] (tile layout). Returns per slot [H_t, W_t, C]."""
+    grads: per slot [n, 64, C] (tile layout). Returns per slot [H_t, W_t, C],
+    the gradient with respect to the texel before its per-channel scale
+    (out is linear in it, with the scale as factor)."""
     if tiles is None:
         tiles = all_tiles(uv.shape[1], uv.shape[0])
     members = footprint_members(footprint, lut)
@@ -503,7 +531,7 @@ def stf_adjoint(textures, uv, filt, seed, frame, footprint, grads, lut=None, til
             ws.append(w)
             ids.append(jj)
         grad = np.zeros((s["th"], s["tw"], C))
-        gg = np.asarray(g, dtype=np.float64).reshape(s["T"].shape)
+        gg = np.asarray(g, dtype=np.float64).reshape(s["T"].shape) * _texture_scale(tex, C)
         for w, jj in zip(ws, ids):
             a = np.where(den > 0, w / np.where(den > 0, den, 1.0), 0.0)
             contrib = a[..., None] * gg

@@ -8,8 +8,9 @@ anything without the built library raises.
 
 Textures are torch tensors [H, W, C] on the GPU: uint8 with C=4 (RGBA8 UNORM)
 or C=1 (R8 UNORM), float16 with C=4 (RGBA16F) or C=2 (RG16F), float32 with
-C=4 (RGBA32F) or C=1 (R32F). UV is float32 [H, W, 2]. Outputs are float32
-[H, W, C] per texture.
+C=4 (RGBA32F) or C=1 (R32F), bfloat16 or float8_e4m3fn with C=4. Each texture
+may carry a per-channel dequantization scale (`scales`). UV is float32
+[H, W, 2]. Outputs are float32 [H, W, C] per texture.
 """
 from __future__ import annotations
 
@@ -33,7 +34,12 @@ FOOTPRINTS = {"self": 0, "quad2x2": 1, "wave2x2": 2, "square3x3": 3, "square4x4"
 FORMATS = {
     ("uint8", 4): (0, 4), ("float16", 4): (1, 8), ("float16", 2): (2, 4),
     ("uint8", 1): (3, 1), ("float32", 4): (4, 16), ("float32", 1): (5, 4),
+    ("bfloat16", 4): (6, 8), ("float8_e4m3fn", 4): (7, 4),
+    ("float16", 8): (8, 16), ("bfloat16", 8): (9, 16), ("float8_e4m3fn", 8): (10, 8),
 }
+# 8-channel textures are latent grids, decoded to RGBA by a packed decoder
+LATENT_FORMATS = (8, 9, 10)
+LATENT_OUT_CHANNELS = 4
 STF_MAX_TEXTURES = 4
 
 
@@ -43,7 +49,15 @@ class StfError(RuntimeError):
 
 class Texture(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
-                ("pitch_bytes", ctypes.c_int64), ("format", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("pitch_bytes", ctypes.c_int64), ("format", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("scale", ctypes.c_void_p), ("decoder", ctypes.c_void_p)]
+
+
+class Mlp(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("w1", "b1", "w2", "b2", "w3", "b3")]
+
+
+DECODER_BYTES = 14720
 
 
 class Screen(ctypes.Structure):
@@ -61,7 +75,7 @@ class Reuse(ctypes.Structure):
 
 _lib = None
 _SYMBOLS = ("stf_filter", "stf_filter_reuse", "stf_filter_reference", "stf_backward",
-            "stf_last_error", "stf_version")
+            "stf_decoder_pack", "stf_last_error", "stf_version")
 
 
 def library() -> ctypes.CDLL:
@@ -78,7 +92,9 @@ def library() -> ctypes.CDLL:
         lib.stf_filter_reuse.argtypes = tex_args + [P(Reuse), P(vp), vp, vp]
         lib.stf_filter_reference.argtypes = tex_args + [P(vp), vp]
         lib.stf_backward.argtypes = tex_args + [P(Reuse), P(vp), P(vp), vp]
-        for name in ("stf_filter", "stf_filter_reuse", "stf_filter_reference", "stf_backward", "stf_version"):
+        lib.stf_decoder_pack.argtypes = [P(Mlp), vp, vp]
+        for name in ("stf_filter", "stf_filter_reuse", "stf_filter_reference", "stf_backward",
+                     "stf_decoder_pack", "stf_version"):
             getattr(lib, name).restype = ctypes.c_int
         lib.stf_last_error.restype = ctypes.c_char_p
         lib.stf_last_error.argtypes = []
@@ -102,11 +118,36 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _texture_descs(textures: Sequence, need_data: bool = True):
+def pack_decoder(layers, stream=None):
+    """Pack the latent decoder MLP [(W1 [64,8], b1), (W2 [64,64], b2),
+    (W3 [4,64], b3)] (float32 GPU tensors) with stf_decoder_pack. Returns
+    the packed uint8 GPU tensor to pass as `decoder=`."""
+    import torch
+    shapes = [((64, 8), (64,)), ((64, 64), (64,)), ((4, 64), (4,))]
+    if len(layers) != 3:
+        raise ValueError("three (W, b) layers expected")
+    flat = []
+    for (wt, bt), (ws, bs) in zip(layers, shapes):
+        for t, sh in ((wt, ws), (bt, bs)):
+            if tuple(t.shape) != sh or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"decoder arrays must be contiguous float32 GPU tensors of shape {sh}")
+            flat.append(t)
+    packed = torch.empty(DECODER_BYTES, dtype=torch.uint8, device=flat[0].device)
+    m = Mlp(*[t.data_ptr() for t in flat])
+    _check(library().stf_decoder_pack(ctypes.byref(m), ctypes.c_void_p(packed.data_ptr()), _stream_handle(stream)))
+    return packed
+
+
+def _texture_descs(textures: Sequence, need_data: bool = True, scales=None, decoder=None):
+    """Descriptors, filtered channels per texture, and the host scale arrays
+    (kept alive by the caller for the duration of the call)."""
     if not 1 <= len(textures) <= STF_MAX_TEXTURES:
         raise ValueError(f"1..{STF_MAX_TEXTURES} textures expected")
+    if scales is not None and len(scales) != len(textures):
+        raise ValueError("one scale entry (or None) per texture expected")
     arr = (Texture * len(textures))()
     chans = []
+    keep = []
     for i, t in enumerate(textures):
         if t.dim() != 3:
             raise ValueError("texture tensors are [H, W, C]")
@@ -126,8 +167,24 @@ def _texture_descs(textures: Sequence, need_data: bool = True):
         arr[i].pitch_bytes = int(t.stride(0)) * t.element_size()
         arr[i].format = fmt
         arr[i].reserved = 0
-        chans.append(int(t.shape[2]))
-    return arr, chans
+        sc = None if scales is None else scales[i]
+        if sc is not None:
+            vals = [float(v) for v in sc]
+            if len(vals) != int(t.shape[2]):
+                raise ValueError(f"texture {i}: {int(t.shape[2])} scale values expected")
+            buf = (ctypes.c_float * len(vals))(*vals)
+            keep.append(buf)
+            arr[i].scale = ctypes.cast(buf, ctypes.c_void_p)
+        else:
+            arr[i].scale = None
+        if fmt in LATENT_FORMATS:
+            if decoder is None:
+                raise ValueError(f"texture {i} holds latents: pass decoder= (from pack_decoder)")
+            arr[i].decoder = decoder.data_ptr()
+        else:
+            arr[i].decoder = None
+        chans.append(LATENT_OUT_CHANNELS if fmt in LATENT_FORMATS else int(t.shape[2]))
+    return arr, chans, keep
 
 
 def _screen(uv):
@@ -158,12 +215,13 @@ def _reuse(footprint, lut):
     return Reuse(fp, int(lut.shape[1]), lut.data_ptr())
 
 
-def filter(textures, uv, filter="bicubic", seed=0, frame=0, sel=False, out=None, stream=None):
+def filter(textures, uv, filter="bicubic", seed=0, frame=0, sel=False, out=None, stream=None, scales=None, decoder=None):
     """One-tap STF (stf_filter). Returns a list of outputs, plus the int32
-    selection tensor [ntex, H, W, 2] if sel=True."""
+    selection tensor [ntex, H, W, 2] if sel=True. `scales` holds, per
+    texture, None or one dequantization scale per channel."""
     import torch
     lib = library()
-    descs, chans = _texture_descs(textures)
+    descs, chans, _keep = _texture_descs(textures, scales=scales, decoder=decoder)
     scr = _screen(uv)
     prm = _params(filter, seed, frame)
     out, ptrs = _outputs(uv, chans, out)
@@ -174,12 +232,12 @@ def filter(textures, uv, filter="bicubic", seed=0, frame=0, sel=False, out=None,
 
 
 def filter_reuse(textures, uv, footprint="tile8x8", filter="bicubic", seed=0, frame=0, lut=None,
-                 sel=False, out=None, stream=None):
+                 sel=False, out=None, stream=None, scales=None, decoder=None):
     """STF with sample reuse (stf_filter_reuse). `lut` is a uint8 GPU tensor
     [64, K] of tile pixel ids for footprint='lut'."""
     import torch
     lib = library()
-    descs, chans = _texture_descs(textures)
+    descs, chans, _keep = _texture_descs(textures, scales=scales, decoder=decoder)
     scr = _screen(uv)
     prm = _params(filter, seed, frame)
     r = _reuse(footprint, lut)
@@ -190,10 +248,10 @@ def filter_reuse(textures, uv, footprint="tile8x8", filter="bicubic", seed=0, fr
     return (out, s) if sel else out
 
 
-def filter_reference(textures, uv, filter="bicubic", out=None, stream=None):
+def filter_reference(textures, uv, filter="bicubic", out=None, stream=None, scales=None, decoder=None):
     """Deterministic filter of Eq. (3) (stf_filter_reference)."""
     lib = library()
-    descs, chans = _texture_descs(textures)
+    descs, chans, _keep = _texture_descs(textures, scales=scales, decoder=decoder)
     scr = _screen(uv)
     prm = _params(filter, 0, 0)
     out, ptrs = _outputs(uv, chans, out)
@@ -203,12 +261,12 @@ def filter_reference(textures, uv, filter="bicubic", out=None, stream=None):
 
 
 def backward(textures, uv, grads, footprint="tile8x8", filter="bicubic", seed=0, frame=0, lut=None,
-             dtex=None, stream=None):
+             dtex=None, stream=None, scales=None):
     """Adjoint of filter_reuse (stf_backward): accumulates dL/dT into `dtex`
     (float32 [H_t, W_t, C] per texture; zero-initialised if not given)."""
     import torch
     lib = library()
-    descs, chans = _texture_descs(textures)
+    descs, chans, _keep = _texture_descs(textures, scales=scales)
     scr = _screen(uv)
     prm = _params(filter, seed, frame)
     r = _reuse(footprint, lut)

@@ -25,12 +25,14 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
 
 #include "stf_device.h"
+#include "stf_decoder.h"
 
 namespace stf {
 
@@ -297,22 +299,24 @@ __device__ __forceinline__ BinBox support_box(const Pixel& P, uint32_t rx, uint3
     return b;
 }
 
-// Calls f(record) for every bin of the box: lanes cover four rows of 16
-// columns per step (wave-uniform trip count).
+// Calls f(record) for every bin of the box, one 8x8 block of bins per step
+// (lane -> (lane & 7, lane >> 3)); wave-uniform trip counts.
 template <typename F>
 __device__ __forceinline__ void for_box(const BinBox& b, int lane, F f) {
-    const int col = lane & 15;
-    for (int y = b.y0 + (lane >> 4); y - (lane >> 4) <= b.y1; y += 4)
-        if (y <= b.y1 && col >= b.x0 && col <= b.x1) f(y * kBinStride + col);
+    for (int by = b.y0; by <= b.y1; by += 8)
+        for (int bx = b.x0; bx <= b.x1; bx += 8) {
+            const int x = bx + (lane & 7), y = by + (lane >> 3);
+            if (x <= b.x1 && y <= b.y1) f(y * kBinStride + x);
+        }
 }
 
 // Exact sums of 1/p per bin. With e_max the largest biased exponent of the
 // wave's reciprocal PMFs, every r whose exponent is at least e_max - 33 is
 // the integer m * 2^(e - e_max + 33) times 2^(e_max - 183) (m = 24-bit
 // significand), and at most 64 of them stay below 2^63: the 64-bit integer
-// sums are exact and independent of the order of the atomic adds. Bins are
-// then converted once (rounded once to FP32). Waves whose exponents span
-// more than 33 fall back to FP32 atomics.
+// sums are exact and independent of the order of the atomic adds; each bin
+// is then converted to FP32 (within 2 ulp, deterministically). Waves whose
+// exponents span more than 33 fall back to FP32 atomics.
 __device__ __forceinline__ uint64_t fixed_of(float r, uint32_t e_max) {
     const uint32_t b = __float_as_uint(r);
     const uint32_t m = (b & 0x7FFFFFu) | 0x800000u;
@@ -320,8 +324,31 @@ __device__ __forceinline__ uint64_t fixed_of(float r, uint32_t e_max) {
 }
 
 __device__ __forceinline__ float float_of(uint64_t n, uint32_t e_max) {
-    const double d = fma((double)(uint32_t)(n >> 32), 4294967296.0, (double)(uint32_t)n);   // exact below 2^53, else rounded once
-    return (float)ldexp(d, (int)e_max - 183);
+    const float f = fmaf((float)(uint32_t)(n >> 32), 4294967296.0f, (float)(uint32_t)n);   // within 2 ulp
+    return ldexpf(f, (int)e_max - 183);
+}
+
+// Bin window and support box of the wave for one texture size (shared by
+// every texture of that size).
+template <int N>
+struct BinGeom {
+    bool ok = false;         // every on-screen support fits the window
+    uint32_t rx = 0, ry = 0; // this pixel's support start inside the window
+    BinBox box;
+    int tw = 0, th = 0;
+};
+
+template <int FILT>
+__device__ __forceinline__ void update_geom(BinGeom<AxisCtx<FILT>::N>& g, const Pixel& P, const SelCtx<FILT>& ctx,
+                                            int tw, int th) {
+    constexpr int N = AxisCtx<FILT>::N;
+    if (g.tw == tw && g.th == th) return;                // wave-uniform
+    int base_x, base_y;
+    g.ok = bin_window<N>(P, ctx.x.base, ctx.y.base, (uint32_t)tw - 1u, (uint32_t)th - 1u, tw, th, base_x, base_y,
+                         g.rx, g.ry);
+    if (g.ok) g.box = support_box<N>(P, g.rx, g.ry);
+    g.tw = tw;
+    g.th = th;
 }
 
 // Receive the pick of quad partner lane^X through DPP and accumulate it.
@@ -355,17 +382,26 @@ __device__ __forceinline__ SlotPick pick_slot(const TexArg& t, const SelCtx<FILT
     return k;
 }
 
-// Exchange and estimator for one texture slot of one pixel.
-template <int FILT, int MODE, int PL>
+// Exchange and estimator for one texture slot of one pixel. LAT: the texture
+// holds latents; the picked texel is decoded by the MLP in `dec` (LDS) before
+// it is shared, so every pixel decodes exactly one texel.
+template <int FILT, int MODE, int PL, bool LAT = false>
 __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int slot, const Pixel& P,
-                                          const SelCtx<FILT>& ctx, const SlotPick& pk, float* lds) {
+                                          const SelCtx<FILT>& ctx, const BinGeom<AxisCtx<FILT>::N>& geom,
+                                          const SlotPick& pk, float* lds, const uint8_t* dec = nullptr) {
+    static_assert(!LAT || PL == kF32x4, "decoded latents are RGBA FP32");
     constexpr int N = SelCtx<FILT>::N;
     constexpr int C = Texel<PL>::C;
     const int lane = lane_id();
     const int kx = pk.kx, ky = pk.ky;
     const uint32_t mx = (uint32_t)t.w - 1u, my = (uint32_t)t.h - 1u;
     const uint32_t sx = pk.sx, sy = pk.sy;
-    const Texel<PL> T = decode<PL>(block_texel(pk.raw, sx, format_bytes(t.fmt)), t.fmt);
+    Texel<PL> T;
+    if constexpr (LAT)
+        decode_latent(dec, latent_bf16(block_texel(pk.raw, sx, format_bytes(t.fmt)), t), T.v);
+    else
+        T = decode<PL>(block_texel(pk.raw, sx, format_bytes(t.fmt)), t.fmt);
+    const bool scale_out = !LAT && t.has_scale;       // a latent scale precedes the decoder
     const int64_t pix = (int64_t)P.py * a.sw + P.px;
 
     if (a.sel != nullptr && P.valid) {
@@ -376,7 +412,13 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
 #pragma unroll
     for (int c = 0; c < C; ++c) Tv[c] = T.ch(c);
     if constexpr (MODE == kModeStf) {
-        if (P.valid) store_out<C>(a.out[slot], pix, Tv);
+        if (P.valid) {
+            if (scale_out) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) Tv[c] *= t.scale[c];
+            }
+            store_out<C>(a.out[slot], pix, Tv);
+        }
         return;
     } else {
         // 1/p of the own pick; off-screen pixels share a pick of weight zero
@@ -398,11 +440,10 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
         } else {
             bool use_bins = false;
             if constexpr (MODE == kModeBins) {
-                int base_x, base_y;
-                uint32_t rx, ry;
-                use_bins = bin_window<N>(P, ctx.x.base, ctx.y.base, mx, my, t.w, t.h, base_x, base_y, rx, ry);
+                use_bins = geom.ok;
                 if (use_bins) {
-                    const BinBox box = support_box<N>(P, rx, ry);
+                    const uint32_t rx = geom.rx, ry = geom.ry;
+                    const BinBox& box = geom.box;
                     const int my_bin = (int)(ry + ky) * kBinStride + (int)(rx + kx);
                     const uint32_t e = P.valid ? (__float_as_uint(r) >> 23) : 0u;
                     const uint32_t e_max = wave_max(e);
@@ -473,6 +514,10 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
             const float inv = fast_rcp(B);
 #pragma unroll
             for (int c = 0; c < C; ++c) o[c] = fmaf(acc[c], inv, Tv[c]);
+            if (scale_out) {                     // Eq. (14) is linear in the texels
+#pragma unroll
+                for (int c = 0; c < C; ++c) o[c] *= t.scale[c];
+            }
             store_out<C>(a.out[slot], pix, o);
         }
     }
@@ -510,15 +555,21 @@ __device__ __forceinline__ int payload_of(int fmt) {
     case STF_RGBA16F: return kF16x4;
     case STF_RG16F: return kF16x2;
     case STF_R8_UNORM: case STF_R32F: return kF32x1;
-    default: return kF32x4;
+    case STF_LATENT8_F16: case STF_LATENT8_BF16: case STF_LATENT8_FP8: return kLatent;
+    default: return kF32x4;          // RGBA8, RGBA32F, RGBA BF16, RGBA FP8
     }
 }
 
 // NT textures, unrolled: descriptors are loaded once, and every pick and
 // texel fetch is issued before the first exchange so their latencies overlap.
-template <int FILT, int MODE, int NT>
+template <int FILT, int MODE, int NT, bool DEC>
 __global__ __launch_bounds__(kThreads) void forward_kernel(Args a) {
     __shared__ __align__(16) float lds_all[(MODE == kModeRecords || MODE == kModeBins) ? kWavesPerGroup * kLdsFloatsPerWave : 4];
+    __shared__ __align__(16) uint8_t dec[DEC ? kDecBytes : 16];
+    if constexpr (DEC) {                       // before any wave of the group can leave
+        stage_decoder(a.dec, dec);
+        __syncthreads();
+    }
     Pixel P;
     if (!setup_pixel(a, P)) return;
     float* lds = lds_all + ((MODE == kModeRecords || MODE == kModeBins) ? (threadIdx.x >> 6) * kLdsFloatsPerWave : 0);
@@ -535,21 +586,27 @@ __global__ __launch_bounds__(kThreads) void forward_kernel(Args a) {
         ctx.update(P, t[i].w, t[i].h);
         pk[i] = pick_slot<FILT>(t[i], ctx, hx, hy);
     }
+    BinGeom<AxisCtx<FILT>::N> geom;
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
         ctx.update(P, t[i].w, t[i].h);
+        if constexpr (MODE == kModeBins) update_geom<FILT>(geom, P, ctx, t[i].w, t[i].h);
         switch (payload_of(t[i].fmt)) {
-        case kF16x4: slot_pass<FILT, MODE, kF16x4>(a, t[i], i, P, ctx, pk[i], lds); break;
-        case kF16x2: slot_pass<FILT, MODE, kF16x2>(a, t[i], i, P, ctx, pk[i], lds); break;
-        case kF32x1: slot_pass<FILT, MODE, kF32x1>(a, t[i], i, P, ctx, pk[i], lds); break;
-        default: slot_pass<FILT, MODE, kF32x4>(a, t[i], i, P, ctx, pk[i], lds); break;
+        case kF16x4: slot_pass<FILT, MODE, kF16x4>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
+        case kF16x2: slot_pass<FILT, MODE, kF16x2>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
+        case kF32x1: slot_pass<FILT, MODE, kF32x1>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
+        case kLatent:
+            if constexpr (DEC) slot_pass<FILT, MODE, kF32x4, true>(a, t[i], i, P, ctx, geom, pk[i], lds, dec);
+            break;
+        default: slot_pass<FILT, MODE, kF32x4>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
         }
     }
 }
 
 // Deterministic filter, Eq. (3): sum over the support of f_c * T.
-template <int FILT, int PL>
-__device__ __forceinline__ void reference_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx) {
+template <int FILT, int PL, bool LAT = false>
+__device__ __forceinline__ void reference_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
+                                               const uint8_t* dec = nullptr) {
     constexpr int N = SelCtx<FILT>::N;
     constexpr int C = Texel<PL>::C;
     const TexArg t = a.tex[slot];
@@ -564,17 +621,32 @@ __device__ __forceinline__ void reference_slot(const Args& a, int slot, const Pi
 #pragma unroll
         for (int aa = 0; aa < N; ++aa) {
             const uint32_t x = (uint32_t)(ctx.x.base + aa) & mx;
-            const Texel<PL> T = decode<PL>(block_texel(fetch_block(t, x, y, bpp), x, bpp), t.fmt);
+            Texel<PL> T;
+            if constexpr (LAT)                       // every tap decodes (the full-filter cost)
+                decode_latent(dec, latent_bf16(block_texel(fetch_block(t, x, y, bpp), x, bpp), t), T.v);
+            else
+                T = decode<PL>(block_texel(fetch_block(t, x, y, bpp), x, bpp), t.fmt);
             const float w = ctx.wxy[b * N + aa];
 #pragma unroll
             for (int c = 0; c < C; ++c) acc[c] = fmaf(w, T.ch(c), acc[c]);
         }
     }
-    if (P.valid) store_out<C>(a.out[slot], (int64_t)P.py * a.sw + P.px, acc);
+    if (P.valid) {
+        if (!LAT && t.has_scale) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] *= t.scale[c];
+        }
+        store_out<C>(a.out[slot], (int64_t)P.py * a.sw + P.px, acc);
+    }
 }
 
-template <int FILT>
+template <int FILT, bool DEC>
 __global__ __launch_bounds__(kThreads) void reference_kernel(Args a) {
+    __shared__ __align__(16) uint8_t dec[DEC ? kDecBytes : 16];
+    if constexpr (DEC) {
+        stage_decoder(a.dec, dec);
+        __syncthreads();
+    }
     Pixel P;
     if (!setup_pixel(a, P)) return;
     SelCtx<FILT> ctx;
@@ -584,8 +656,49 @@ __global__ __launch_bounds__(kThreads) void reference_kernel(Args a) {
         case kF16x4: reference_slot<FILT, kF16x4>(a, slot, P, ctx); break;
         case kF16x2: reference_slot<FILT, kF16x2>(a, slot, P, ctx); break;
         case kF32x1: reference_slot<FILT, kF32x1>(a, slot, P, ctx); break;
+        case kLatent:
+            if constexpr (DEC) reference_slot<FILT, kF32x4, true>(a, slot, P, ctx, dec);
+            break;
         default: reference_slot<FILT, kF32x4>(a, slot, P, ctx); break;
         }
+    }
+}
+
+// Pack the decoder MLP for decode_latent: BF16 A operands in lane order with
+// the K permutation of dec_unit, b1 folded into layer 1 as K index 8, b2 and
+// b3 as FP32 accumulator start values. One workgroup.
+__global__ __launch_bounds__(256) void decoder_pack_kernel(stf_mlp m, uint8_t* out) {
+    u32x4* A = reinterpret_cast<u32x4*>(out);
+    for (int idx = threadIdx.x; idx < 14 * 64; idx += blockDim.x) {
+        const int o = idx >> 6, lane = idx & 63, h = lane >> 5, row = lane & 31;
+        float v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int k = 8 * h + t;
+            if (o < 2) {                                      // layer 1, row tile o
+                const int u = 32 * o + row;
+                v[t] = h == 0 ? m.w1[u * 8 + t] : (t == 0 ? m.b1[u] : 0.0f);
+            } else if (o < 10) {                              // layer 2, row tile, K step
+                const int mt = (o - 2) >> 2, st = (o - 2) & 3;
+                v[t] = m.w2[(32 * mt + row) * 64 + dec_unit(st, k)];
+            } else {                                          // layer 3, K step (rows >= 4 are padding)
+                v[t] = row < 4 ? m.w3[row * 64 + dec_unit(o - 10, k)] : 0.0f;
+            }
+        }
+        u32x4 q;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[i] = pack_bf16(v[2 * i], v[2 * i + 1]);
+        A[idx] = q;
+    }
+    float* C2 = reinterpret_cast<float*>(out + kDecC2);
+    for (int idx = threadIdx.x; idx < 64; idx += blockDim.x) {
+        const int mt = idx >> 5, h = (idx >> 4) & 1, j = idx & 15;
+        C2[idx] = m.b2[32 * mt + acc_row(j, h)];
+    }
+    float* C3 = reinterpret_cast<float*>(out + kDecC3);
+    for (int idx = threadIdx.x; idx < 32; idx += blockDim.x) {
+        const int h = idx >> 4, j = idx & 15, r = acc_row(j, h);
+        C3[idx] = r < 4 ? m.b3[r] : 0.0f;
     }
 }
 
@@ -625,7 +738,7 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
     const int64_t pix = (int64_t)P.py * a.sw + P.px;
     float g[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) g[c] = P.valid ? a.dout[slot][pix * C + c] : 0.0f;
+    for (int c = 0; c < C; ++c) g[c] = P.valid ? a.dout[slot][pix * C + c] * t.scale[c] : 0.0f;
 
     if constexpr (MODE == kModeStf) {
         if (P.valid) atomic_texel<C>(grad, t.w, s, g, 1.0f);
@@ -778,23 +891,28 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
-int format_channels(int fmt) {
+// Channels of the stored texel (8 for latent grids) and of the filtered,
+// decoded texel (4 for latent grids).
+int stored_channels(int fmt) {
     switch (fmt) {
-    case STF_RGBA8_UNORM: case STF_RGBA16F: case STF_RGBA32F: return 4;
+    case STF_RGBA8_UNORM: case STF_RGBA16F: case STF_RGBA32F: case STF_RGBA_BF16: case STF_RGBA_FP8: return 4;
     case STF_RG16F: return 2;
     case STF_R8_UNORM: case STF_R32F: return 1;
+    case STF_LATENT8_F16: case STF_LATENT8_BF16: case STF_LATENT8_FP8: return 8;
     default: return 0;
     }
 }
 
+bool is_latent(int fmt) { return fmt == STF_LATENT8_F16 || fmt == STF_LATENT8_BF16 || fmt == STF_LATENT8_FP8; }
+
+int format_channels(int fmt) { return is_latent(fmt) ? 4 : stored_channels(fmt); }
+
 int format_bytes(int fmt) {
     switch (fmt) {
-    case STF_RGBA8_UNORM: return 4;
-    case STF_RGBA16F: return 8;
-    case STF_RGBA32F: return 16;
-    case STF_RG16F: return 4;
+    case STF_RGBA8_UNORM: case STF_RG16F: case STF_R32F: case STF_RGBA_FP8: return 4;
+    case STF_RGBA16F: case STF_RGBA_BF16: case STF_LATENT8_FP8: return 8;
+    case STF_RGBA32F: case STF_LATENT8_F16: case STF_LATENT8_BF16: return 16;
     case STF_R8_UNORM: return 1;
-    case STF_R32F: return 4;
     default: return 0;
     }
 }
@@ -802,8 +920,10 @@ int format_bytes(int fmt) {
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // Validates everything the kernels assume and fills the kernel arguments.
+// allow_latent: latent textures are accepted (with a decoder); all latent
+// textures of one call share one packed decoder, stored in a.dec.
 int prepare(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
-            bool need_data, stf::Args& a) {
+            bool need_data, stf::Args& a, bool allow_latent = false) {
     std::memset(&a, 0, sizeof a);
     if (tex == nullptr || scr == nullptr || p == nullptr)
         return fail(STF_EINVAL, "null descriptor pointer");
@@ -822,6 +942,18 @@ int prepare(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const s
         const int bpp = format_bytes(t.format);
         if (ch == 0) return fail(STF_EINVAL, "texture %d: unknown format %d", i, t.format);
         if (t.reserved != 0) return fail(STF_EINVAL, "texture %d: reserved field must be 0", i);
+        if (is_latent(t.format)) {
+            if (!allow_latent)
+                return fail(STF_EUNSUPPORTED, "texture %d: latent formats are not supported by this entry point", i);
+            if (t.decoder == nullptr) return fail(STF_EINVAL, "texture %d: latent format without a decoder", i);
+            if ((reinterpret_cast<uintptr_t>(t.decoder) % 16) != 0)
+                return fail(STF_EINVAL, "texture %d: decoder not aligned to 16 bytes", i);
+            if (a.dec != nullptr && a.dec != static_cast<const uint8_t*>(t.decoder))
+                return fail(STF_EUNSUPPORTED, "texture %d: one call supports one decoder for all latent textures", i);
+            a.dec = static_cast<const uint8_t*>(t.decoder);
+        } else if (t.decoder != nullptr) {
+            return fail(STF_EINVAL, "texture %d: decoder given for a format that is not latent", i);
+        }
         if (need_data && t.data == nullptr) return fail(STF_EINVAL, "texture %d: data is null", i);
         if (!pow2(t.width) || !pow2(t.height) || t.width < 4 || t.height < 4 || t.width > 32768 || t.height > 32768)
             return fail(STF_EINVAL, "texture %d: %dx%d must be powers of two in 4..32768 for WRAP", i, t.width, t.height);
@@ -838,6 +970,14 @@ int prepare(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const s
         a.tex[i].h = t.height;
         a.tex[i].fmt = t.format;
         a.tex[i].ch = ch;
+        a.tex[i].has_scale = t.scale != nullptr;
+        for (int c = 0; c < 8; ++c) a.tex[i].scale[c] = 1.0f;
+        if (t.scale != nullptr) {
+            for (int c = 0; c < stored_channels(t.format); ++c) {
+                if (!std::isfinite(t.scale[c])) return fail(STF_EINVAL, "texture %d: scale[%d] is not finite", i, c);
+                a.tex[i].scale[c] = t.scale[c];
+            }
+        }
     }
     a.uv = scr->uv;
     a.ntex = ntex;
@@ -882,11 +1022,20 @@ int finish_launch(const char* what) {
 template <int FILT, int MODE>
 void launch_forward(const stf::Args& a, hipStream_t s) {
     const dim3 g = grid_of(a), b(stf::kThreads);
+    if (a.dec != nullptr) {
+        switch (a.ntex) {
+        case 1: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 1, true>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 2, true>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 3, true>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 4, true>), g, b, 0, s, a); break;
+        }
+        return;
+    }
     switch (a.ntex) {
-    case 1: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 1>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 2>), g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 3>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 4>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 1, false>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 2, false>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 3, false>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 4, false>), g, b, 0, s, a); break;
     }
 }
 
@@ -894,7 +1043,7 @@ int forward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const s
             const stf_reuse* r, float* const* out, int32_t* sel, void* hip_stream) {
     g_last_error.clear();
     stf::Args a;
-    int rc = prepare(tex, ntex, scr, p, true, a);
+    int rc = prepare(tex, ntex, scr, p, true, a, true);
     if (rc != STF_OK) return rc;
     if ((rc = check_outputs(out, ntex)) != STF_OK) return rc;
     if (sel != nullptr && (reinterpret_cast<uintptr_t>(sel) & 7) != 0) return fail(STF_EINVAL, "sel not 8-byte aligned");
@@ -946,16 +1095,36 @@ int stf_filter_reference(const stf_texture* tex, int32_t ntex, const stf_screen*
                          float* const* out, void* hip_stream) {
     g_last_error.clear();
     stf::Args a;
-    int rc = prepare(tex, ntex, scr, p, true, a);
+    int rc = prepare(tex, ntex, scr, p, true, a, true);
     if (rc != STF_OK) return rc;
     if ((rc = check_outputs(out, ntex)) != STF_OK) return rc;
     for (int i = 0; i < ntex; ++i) a.out[i] = out[i];
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    if (p->filter == STF_BICUBIC_BSPLINE)
-        hipLaunchKernelGGL((stf::reference_kernel<1>), grid_of(a), dim3(stf::kThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL((stf::reference_kernel<0>), grid_of(a), dim3(stf::kThreads), 0, s, a);
+    const dim3 g = grid_of(a), b(stf::kThreads);
+    const bool cubic = p->filter == STF_BICUBIC_BSPLINE;
+    if (a.dec != nullptr) {
+        if (cubic) hipLaunchKernelGGL((stf::reference_kernel<1, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((stf::reference_kernel<0, true>), g, b, 0, s, a);
+    } else {
+        if (cubic) hipLaunchKernelGGL((stf::reference_kernel<1, false>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((stf::reference_kernel<0, false>), g, b, 0, s, a);
+    }
     return finish_launch("reference");
+}
+
+int stf_decoder_pack(const stf_mlp* mlp, void* packed, void* hip_stream) {
+    g_last_error.clear();
+    if (mlp == nullptr || packed == nullptr) return fail(STF_EINVAL, "null mlp descriptor or packed buffer");
+    const float* ws[6] = {mlp->w1, mlp->b1, mlp->w2, mlp->b2, mlp->w3, mlp->b3};
+    for (int i = 0; i < 6; ++i) {
+        if (ws[i] == nullptr) return fail(STF_EINVAL, "mlp array %d is null", i);
+        if ((reinterpret_cast<uintptr_t>(ws[i]) & 3) != 0) return fail(STF_EINVAL, "mlp array %d not 4-byte aligned", i);
+    }
+    if ((reinterpret_cast<uintptr_t>(packed) & 15) != 0) return fail(STF_EINVAL, "packed buffer not aligned to 16 bytes");
+    static_assert(stf::kDecBytes == STF_DECODER_BYTES, "packed decoder size");
+    hipLaunchKernelGGL(stf::decoder_pack_kernel, dim3(1), dim3(256), 0, static_cast<hipStream_t>(hip_stream), *mlp,
+                       static_cast<uint8_t*>(packed));
+    return finish_launch("decoder pack");
 }
 
 int stf_backward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,

@@ -1,0 +1,192 @@
+// Latent-texture decoder on the gfx950 matrix cores.
+//
+// A latent texel (8 channels) is decoded to RGBA by the MLP
+//     h1 = ReLU(W1 x + b1)   (8 -> 64)
+//     h2 = ReLU(W2 h1 + b2)  (64 -> 64)
+//     y  = W3 h2 + b3        (64 -> 4)
+// the neural-texture setting the paper motivates stochastic filtering with
+// (Sec. 1, Sec. 5.6): each pixel decodes only the one texel it picked, and
+// sample reuse then shares the decoded colours (Sec. 4).
+//
+// One wavefront decodes the 64 texels its lanes picked at once, as three
+// matrix products with the pixels as columns: H^T = W X^T. Every product
+// is a chain of v_mfma_f32_32x32x16_bf16 (BF16 operands, FP32 accumulation)
+// over two column tiles of 32 pixels:
+//   - layer 1: K = 16 = 8 latents (lanes 0-31 of the B operand) + a
+//     constant 1 that carries b1 (lanes 32-63); 2 row tiles;
+//   - layer 2: K = 64 in 4 steps, 2 row tiles, b2 preloaded in the
+//     accumulators;
+//   - layer 3: the 4 outputs padded to one 32-row tile, b3 preloaded.
+// The accumulator layout of one product (lane l holds rows 8i + 4(l/32) + r,
+// i, r in 0..3, of column l % 32) is consumed directly as the B operand of
+// the next: lane l contributes the 8 rows it holds as its 8 K-values, which
+// permutes K; the packed weights carry the same permutation, so activations
+// never move between lanes. Activations are rounded to BF16 (RN) between
+// layers; ReLU commutes with that rounding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stf {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Packed decoder (device memory written by the pack kernel, staged into LDS
+// by every workgroup that decodes). A operands are stored lane-major: operand
+// o occupies 64 lanes x 16 bytes at kDec*Off + o * 1024.
+constexpr int kDecA1 = 0;                        // [2 row tiles]
+constexpr int kDecA2 = kDecA1 + 2 * 1024;        // [2 row tiles][4 K steps]
+constexpr int kDecA3 = kDecA2 + 8 * 1024;        // [4 K steps]
+constexpr int kDecC2 = kDecA3 + 4 * 1024;        // f32 [2 row tiles][2 lane halves][16] layer-2 bias
+constexpr int kDecC3 = kDecC2 + 2 * 2 * 16 * 4;  // f32 [2 lane halves][16] layer-3 bias
+constexpr int kDecBytes = kDecC3 + 2 * 16 * 4;   // 14720
+static_assert(kDecBytes % 16 == 0, "packed decoder is copied in 16-byte units");
+
+// Hidden unit carried by K index k of K step s of layers 2 and 3: step
+// s = 2 m + g reads accumulator registers 8g..8g+7 of row tile m, and the
+// lane half h = k / 8 holds rows 8i + 4h + r there (t = k % 8 = 4q + r,
+// i = 2g + q).
+__host__ __device__ constexpr int dec_unit(int s, int k) {
+    return 32 * (s >> 1) + 16 * (s & 1) + 8 * ((k & 7) >> 2) + 4 * (k >> 3) + (k & 3);
+}
+
+// Row of accumulator register j held by lane half h (32x32 output tile).
+__host__ __device__ constexpr int acc_row(int j, int h) { return 8 * (j >> 2) + 4 * h + (j & 3); }
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    const f32x2 f = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
+}
+
+__device__ __forceinline__ f32x16 mfma_bf16(u32x4 a, u32x4 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
+// Value of v held by lane l ^ 32.
+__device__ __forceinline__ uint32_t from_other_half(uint32_t v) { return (uint32_t)__shfl_xor((int)v, 32, 64); }
+
+// B operand of the next layer from accumulators: ReLU, round to BF16, and
+// take registers 8g..8g+7 as the lane's 8 K values.
+__device__ __forceinline__ u32x4 relu_pack(const f32x16& d, int g) {
+    u32x4 r;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        r[t] = pack_bf16(fmaxf(d[8 * g + 2 * t], 0.0f), fmaxf(d[8 * g + 2 * t + 1], 0.0f));
+    return r;
+}
+
+// Decode the latent texels of all 64 lanes (`lat`: the lane's 8 latents as
+// BF16, element k in bits 16(k%2) of dword k/2). `dec` is the packed
+// decoder in LDS. Must be called by all 64 lanes in uniform control flow.
+// Returns the lane's RGBA.
+__device__ __forceinline__ void decode_latent(const uint8_t* dec, u32x4 lat, float out[4]) {
+    const int lane = threadIdx.x & 63;
+    const bool hi = lane >= 32;
+    const u32x4* A = reinterpret_cast<const u32x4*>(dec);
+    u32x4 other;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) other[i] = from_other_half(lat[i]);
+    const u32x4 one = {0x3F80u, 0u, 0u, 0u};      // BF16 1.0 at k = 8: the b1 column
+    const u32x4 x0 = hi ? one : lat;               // column tile 0: pixels of lanes 0-31
+    const u32x4 x1 = hi ? one : other;             // column tile 1: pixels of lanes 32-63
+    const f32x16 zero = {};
+
+    u32x4 b2[2][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const u32x4 a = A[(kDecA1 >> 4) + m * 64 + lane];
+        const f32x16 d0 = mfma_bf16(a, x0, zero);
+        const f32x16 d1 = mfma_bf16(a, x1, zero);
+        b2[0][2 * m] = relu_pack(d0, 0);
+        b2[0][2 * m + 1] = relu_pack(d0, 1);
+        b2[1][2 * m] = relu_pack(d1, 0);
+        b2[1][2 * m + 1] = relu_pack(d1, 1);
+    }
+
+    const float* C2 = reinterpret_cast<const float*>(dec + kDecC2);
+    u32x4 b3[2][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        f32x16 c;
+        const float* cb = C2 + (m * 2 + (hi ? 1 : 0)) * 16;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) c[j] = cb[j];
+        f32x16 d0 = c, d1 = c;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const u32x4 a = A[(kDecA2 >> 4) + (m * 4 + s) * 64 + lane];
+            d0 = mfma_bf16(a, b2[0][s], d0);
+            d1 = mfma_bf16(a, b2[1][s], d1);
+        }
+        b3[0][2 * m] = relu_pack(d0, 0);
+        b3[0][2 * m + 1] = relu_pack(d0, 1);
+        b3[1][2 * m] = relu_pack(d1, 0);
+        b3[1][2 * m + 1] = relu_pack(d1, 1);
+    }
+
+    const float* C3 = reinterpret_cast<const float*>(dec + kDecC3) + (hi ? 16 : 0);
+    f32x16 c;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) c[j] = C3[j];
+    f32x16 y0 = c, y1 = c;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const u32x4 a = A[(kDecA3 >> 4) + s * 64 + lane];
+        y0 = mfma_bf16(a, b3[0][s], y0);
+        y1 = mfma_bf16(a, b3[1][s], y1);
+    }
+    // rows 0-3 (the outputs) sit in registers 0-3 of lanes 0-31; lane l + 32
+    // takes column l of tile 1 from lane l
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float t1 = __uint_as_float(from_other_half(__float_as_uint(y1[i])));
+        out[i] = hi ? t1 : y0[i];
+    }
+}
+
+// The lane's 8 latents as BF16 from the raw texel payload (16 bytes for
+// F16/BF16 latents, the low 8 bytes for FP8), times the optional
+// per-channel scale (in FP32, then RN to BF16).
+__device__ __forceinline__ float latent_channel(uint4 q, int fmt, int k) {
+    const uint32_t w = (k < 2) ? q.x : (k < 4) ? q.y : (k < 6) ? q.z : q.w;
+    if (fmt == STF_LATENT8_FP8) {
+        const uint32_t d = (k < 4) ? q.x : q.y;
+        return fp8_e4m3(d >> (8 * (k & 3)));
+    }
+    const uint32_t half = (w >> (16 * (k & 1))) & 0xFFFFu;
+    return fmt == STF_LATENT8_F16 ? h2f(half) : bf16_bits(half);
+}
+
+__device__ __forceinline__ u32x4 latent_bf16(uint4 q, const TexArg& t) {
+    u32x4 r;
+    if (t.fmt == STF_LATENT8_BF16 && !t.has_scale) {
+        r[0] = q.x; r[1] = q.y; r[2] = q.z; r[3] = q.w;
+        return r;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float a = latent_channel(q, t.fmt, 2 * i), b = latent_channel(q, t.fmt, 2 * i + 1);
+        if (t.has_scale) {
+            a *= t.scale[2 * i];
+            b *= t.scale[2 * i + 1];
+        }
+        r[i] = pack_bf16(a, b);
+    }
+    return r;
+}
+
+// Copy the packed decoder into LDS (all threads of the workgroup; the caller
+// synchronises).
+__device__ __forceinline__ void stage_decoder(const uint8_t* src, uint8_t* lds) {
+    const uint4* s = reinterpret_cast<const uint4*>(src);
+    uint4* d = reinterpret_cast<uint4*>(lds);
+    for (int i = threadIdx.x; i < kDecBytes / 16; i += blockDim.x) d[i] = s[i];
+}
+
+}  // namespace stf

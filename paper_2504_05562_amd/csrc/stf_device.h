@@ -30,7 +30,9 @@ struct TexArg {
     int64_t pitch;
     int32_t w, h;
     int32_t fmt;
-    int32_t ch;
+    int32_t ch;              // channels of the filtered (decoded) texel
+    int32_t has_scale;       // per-channel dequantization scale present
+    float scale[8];
 };
 
 struct Args {
@@ -40,6 +42,7 @@ struct Args {
     const float* uv;
     int32_t* sel;
     const uint8_t* lut;
+    const uint8_t* dec;      // packed latent decoder (device), shared by the latent textures
     int32_t ntex, sw, sh, lut_k, footprint;
     uint32_t seed, frame;
 };
@@ -188,8 +191,9 @@ __device__ __forceinline__ float half_minus(uint32_t x, float neg_c) {
 }
 
 // Texel payload kinds. F16x4 / F16x2 keep the raw half bits (exchanged and
-// binned as stored); F32x4 / F32x1 decode at fetch (RGBA8, RGBA32F / R8, R32F).
-enum Payload { kF16x4 = 0, kF16x2 = 1, kF32x4 = 2, kF32x1 = 3 };
+// binned as stored); F32x4 / F32x1 decode at fetch (RGBA8, RGBA32F, BF16,
+// FP8 / R8, R32F). Latent textures are decoded by the MLP to F32x4.
+enum Payload { kF16x4 = 0, kF16x2 = 1, kF32x4 = 2, kF32x1 = 3, kLatent = 4 };
 
 template <int P> struct Texel;
 template <> struct Texel<kF16x4> {
@@ -218,11 +222,25 @@ template <> struct Texel<kF32x1> {
 __device__ __forceinline__ int format_bytes(int fmt) {
     switch (fmt) {
     case STF_R8_UNORM: return 1;
-    case STF_RGBA16F: return 8;
-    case STF_RGBA32F: return 16;
-    default: return 4;               // RGBA8, RG16F, R32F
+    case STF_RGBA16F: case STF_RGBA_BF16: case STF_LATENT8_FP8: return 8;
+    case STF_RGBA32F: case STF_LATENT8_F16: case STF_LATENT8_BF16: return 16;
+    default: return 4;               // RGBA8, RG16F, R32F, RGBA FP8
     }
 }
+
+// OCP FP8 E4M3 code (low 8 bits) to FP32, from the format definition:
+// exponent bias 7, exponent 0 subnormal (m * 2^-9), S.1111.111 NaN.
+__device__ __forceinline__ float fp8_e4m3(uint32_t code) {
+    const uint32_t c = code & 0xFFu;
+    const uint32_t e = (c >> 3) & 0xFu, m = c & 7u;
+    const uint32_t sign = (c & 0x80u) << 24;
+    const float normal = __uint_as_float(sign | ((e + 120u) << 23) | (m << 20));
+    const float sub = __uint_as_float(__float_as_uint((float)m * 0.001953125f) | sign);
+    const float v = (e == 0u) ? sub : normal;
+    return (e == 15u && m == 7u) ? __uint_as_float(0x7FC00000u) : v;
+}
+
+__device__ __forceinline__ float bf16_bits(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
 
 // One texel's payload as stored (1, 4, 8 or 16 bytes), zero-extended.
 __device__ __forceinline__ uint4 fetch_raw(const TexArg& t, uint32_t x, uint32_t y) {
@@ -273,6 +291,12 @@ __device__ __forceinline__ Texel<P> decode(uint4 q, int fmt) {
             r.v[1] = (float)((q.x >> 8) & 0xFF) * (1.0f / 255.0f);
             r.v[2] = (float)((q.x >> 16) & 0xFF) * (1.0f / 255.0f);
             r.v[3] = (float)(q.x >> 24) * (1.0f / 255.0f);
+        } else if (fmt == STF_RGBA_BF16) {
+            r.v[0] = bf16_bits(q.x & 0xFFFFu); r.v[1] = bf16_bits(q.x >> 16);
+            r.v[2] = bf16_bits(q.y & 0xFFFFu); r.v[3] = bf16_bits(q.y >> 16);
+        } else if (fmt == STF_RGBA_FP8) {
+            r.v[0] = fp8_e4m3(q.x); r.v[1] = fp8_e4m3(q.x >> 8);
+            r.v[2] = fp8_e4m3(q.x >> 16); r.v[3] = fp8_e4m3(q.x >> 24);
         } else {
             r.v[0] = __uint_as_float(q.x); r.v[1] = __uint_as_float(q.y);
             r.v[2] = __uint_as_float(q.z); r.v[3] = __uint_as_float(q.w);

@@ -25,7 +25,17 @@ def test_library_exports_every_declared_symbol():
             "stf_last_error", "stf_version"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
-    assert stf.version() == 1
+    assert stf.version() == 2
+
+
+def test_texture_descriptor_layout():
+    # stf_texture: pointer, 2 x int32, int64, 2 x int32, pointer, pointer
+    assert ctypes.sizeof(stf.Texture) == 48
+    assert stf.Texture.scale.offset == 32 and stf.Texture.decoder.offset == 40
+    assert ctypes.sizeof(stf.Mlp) == 48
+
+
+_NAN_SCALE = (ctypes.c_float * 4)(1.0, float("nan"), 1.0, 1.0)
 
 
 def _call_filter(tex, ntex, scr, prm):
@@ -57,6 +67,9 @@ def _good():
     (lambda t, s, p: setattr(t[0], "pitch_bytes", 100), -1, "pitch"),
     (lambda t, s, p: setattr(t[0], "data", None), -1, "data"),
     (lambda t, s, p: setattr(t[0], "reserved", 1), -1, "reserved"),
+    (lambda t, s, p: setattr(t[0], "format", 8), -1, "decoder"),
+    (lambda t, s, p: setattr(t[0], "decoder", 4096), -1, "not latent"),
+    (lambda t, s, p: setattr(t[0], "scale", ctypes.cast(_NAN_SCALE, ctypes.c_void_p)), -1, "scale"),
 ])
 def test_validation_errors(mutate, code, needle):
     tex, scr, prm = _good()
@@ -79,3 +92,27 @@ def test_validation_counts_and_nulls():
     lut_missing = stf.Reuse(6, 4, None)
     assert lib.stf_filter_reuse(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(lut_missing), out, None, None) == -1
     assert b"lut" in lib.stf_last_error()
+
+
+def test_latent_and_decoder_validation():
+    lib = stf.library()
+    tex, scr, prm = _good()
+    tex[0].format = 10                                   # FP8 latents, 8 bytes per texel
+    tex[0].pitch_bytes = 64 * 8
+    tex[0].decoder = 4100                                # misaligned
+    assert _call_filter(tex, 1, ctypes.byref(scr), ctypes.byref(prm)) == -1
+    assert b"aligned" in lib.stf_last_error()
+    two = (stf.Texture * 2)(tex[0], tex[0])
+    two[0].decoder, two[1].decoder = 4096, 8192         # two different decoders in one call
+    assert _call_filter(two, 2, ctypes.byref(scr), ctypes.byref(prm)) == -2
+    # the adjoint does not go through the decoder
+    tex[0].decoder = 4096
+    r = stf.Reuse(5, 0, None)
+    ptrs = (ctypes.c_void_p * 1)(4096)
+    assert lib.stf_backward(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(r), ptrs, ptrs, None) == -2
+    # the packer validates its pointers before launching anything
+    m = stf.Mlp(4096, 4096, 4096, None, 4096, 4096)
+    assert lib.stf_decoder_pack(ctypes.byref(m), ctypes.c_void_p(4096), None) == -1
+    m = stf.Mlp(4096, 4096, 4096, 4096, 4096, 4096)
+    assert lib.stf_decoder_pack(ctypes.byref(m), ctypes.c_void_p(4104), None) == -1
+    assert lib.stf_decoder_pack(None, ctypes.c_void_p(4096), None) == -1

@@ -362,3 +362,36 @@ def material_set(seed: int = 0):
     normal RG16F 2048^2, roughness R8 1024^2, mask R8 512^2."""
     return [tile_texture_rgba8(seed, 2048), plane_normal(seed, 2048), r8_texture(seed + 1, 1024),
             r8_texture(seed + 2, 512)]
+
+
+# ----------------------------------------------------------------------------
+# reduced-precision payloads (inputs for the precision tests and benches)
+# ----------------------------------------------------------------------------
+
+def amax_scale(values: np.ndarray, kind: str) -> np.ndarray:
+    """Per-channel scale that maps each channel's largest magnitude to the
+    largest finite value of the format (448 for FP8 E4M3, 1 for BF16/FP16
+    payloads, which keep their range)."""
+    amax = np.abs(values.reshape(-1, values.shape[-1])).max(axis=0)
+    top = {"fp8": 448.0}.get(kind, None)
+    if top is None:
+        return np.ones(values.shape[-1])
+    return np.where(amax > 0, amax / top, 1.0).astype(np.float32).astype(np.float64)
+
+
+def quantize(values: np.ndarray, kind: str, scale=None) -> np.ndarray:
+    """Stored payload of values / scale in format `kind` (round to nearest
+    even via torch's CPU casts): 'bf16' -> uint16 bits, 'fp8' -> uint8 E4M3
+    codes, 'f16' -> float16."""
+    import torch
+    v = np.asarray(values, dtype=np.float64)
+    if scale is not None:
+        v = v / np.asarray(scale, dtype=np.float64)
+    t = torch.from_numpy(np.ascontiguousarray(v.astype(np.float32)))
+    if kind == "bf16":
+        return t.to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    if kind == "fp8":
+        return t.to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    if kind == "f16":
+        return t.to(torch.float16).numpy()
+    raise ValueError(kind)
