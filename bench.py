@@ -10,7 +10,9 @@ Workload (one step = one stf_filter_reuse launch over one frame):
 
 Prints one JSON line with Mpixel/s (reuse), the one-sample STF rate, the
 HBM roofline of the reuse kernel, PSNR of both against the deterministic
-filter, and the FP64 CPU oracle timed on a bounded sample of the same frame.
+filter, the FP64 CPU oracle timed on a bounded sample of the same frame, and
+the other forms measured on the same GPU: the albedo in five storage
+precisions, the backward pass, and latent textures decoded by the MLP.
 """
 from __future__ import annotations
 
@@ -123,6 +125,116 @@ def cpu_baseline(texs, uv, n_tiles=None, seed=0):
             "sample": f"{n_tiles} of the frame's 8x8 tiles ({px} px), both textures, {dt:.1f} s"}
 
 
+def launch_time(torch, fn, steps, warmup):
+    """Average device time per call of fn() (HIP events on the current
+    stream around `steps` calls, after `warmup` untimed calls)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / 1e3 / steps
+
+
+def psnr_rgb(torch, a, b, peak=1.0):
+    d = a[..., :3].double() - b[..., :3].double()
+    return float(10 * torch.log10(peak * peak / torch.mean(d * d)))
+
+
+def precision_forms(torch, stf, w, uv, steps, warmup):
+    """The albedo alone, stored as RGBA32F, RGBA16F, BF16, FP8 E4M3 (per-channel
+    amax scales) and RGBA8, filtered with whole-tile reuse: launch time and
+    PSNR against the deterministic filter of the RGBA32F texture (the plain
+    FP32 form)."""
+    H, W = uv.shape[:2]
+    vals = w.plane_albedo(0, 2048, np.float32).astype(np.float64)
+    forms = {
+        "fp32": (torch.from_numpy(vals.astype(np.float32)), None),
+        "fp16": (torch.from_numpy(vals.astype(np.float16)), None),
+        "bf16": (torch.from_numpy(w.quantize(vals, "bf16")).view(torch.int16).view(torch.bfloat16), None),
+    }
+    sc = w.amax_scale(vals, "fp8")
+    forms["fp8"] = (torch.from_numpy(w.quantize(vals, "fp8", sc)).view(torch.float8_e4m3fn), [list(sc)])
+    forms["rgba8"] = (torch.from_numpy(np.clip(np.rint(vals * 255.0), 0, 255).astype(np.uint8)), None)
+    ref = stf.filter_reference([forms["fp32"][0].cuda()], uv, "bicubic")[0]
+    out = torch.empty((H, W, 4), dtype=torch.float32, device=uv.device)
+    res = {}
+    for name, (t, scales) in forms.items():
+        tex = [t.cuda()]
+        dt = launch_time(torch, lambda: stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, out=[out],
+                                                        scales=scales), steps, warmup)
+        o = stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, scales=scales)[0]
+        r = stf.filter_reference(tex, uv, "bicubic", scales=scales)[0]
+        res[name] = {"avg_launch_us": round(dt * 1e6, 2), "Mpixel_s": round(H * W / dt / 1e6, 1),
+                     "texel_bytes": int(t.element_size() * 4),
+                     "psnr_reuse_db": round(psnr_rgb(torch, o, ref), 2),
+                     "psnr_own_reference_db": round(psnr_rgb(torch, r, ref), 2)}
+    res["against"] = "deterministic bicubic filter of the RGBA32F albedo"
+    return res
+
+
+def backward_form(torch, stf, texs, uv, steps, warmup):
+    """stf_backward of the benchmark launch (both textures, whole-tile reuse):
+    FP32 gradients accumulated into dense [H_t][W_t][C] buffers."""
+    H, W = uv.shape[:2]
+    g = [torch.randn((H, W, int(t.shape[2])), dtype=torch.float32, device=uv.device) for t in texs]
+    dtex = [torch.zeros((int(t.shape[0]), int(t.shape[1]), int(t.shape[2])), dtype=torch.float32, device=uv.device)
+            for t in texs]
+    dt = launch_time(torch, lambda: stf.backward(texs, uv, g, "tile8x8", "bicubic", 0, 0, dtex=dtex), steps, warmup)
+    return {"avg_launch_us": round(dt * 1e6, 2), "Mpixel_s": round(H * W / dt / 1e6, 1),
+            "textures": "RGBA16F + RG16F 2048^2, FP32 gradients"}
+
+
+DECODE_FLOPS_PER_TEXEL = 2 * (8 * 64 + 64 * 64 + 64 * 4)     # useful MLP flops (biases aside)
+
+
+def latent_form(torch, stf, w, steps, warmup):
+    """1024^2 x 8 FP8 E4M3 latents with per-channel scales, decoder MLP
+    8-64-64-4 on the matrix cores (BF16, FP32 accumulation), 1920x1080
+    perspective plane at 4x-16x, bicubic: one-tap STF and whole-tile reuse
+    decode one texel per pixel; the deterministic filter decodes all 16 taps."""
+    uv_np, _, _, info = w.perspective_plane(1920, 1080, 1024, 4.0, 16.0)
+    H, W = uv_np.shape[:2]
+    uv = torch.from_numpy(uv_np).cuda()
+    lat = w.latent_grid(0, 1024).astype(np.float64)
+    sc = w.amax_scale(lat, "fp8")
+    tex = [torch.from_numpy(w.quantize(lat, "fp8", sc)).view(torch.float8_e4m3fn).cuda()]
+    layers = [(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for a, b in w.decoder_weights(0)]
+    dec = stf.pack_decoder(layers)
+    scales = [list(sc)]
+    out = torch.empty((H, W, 4), dtype=torch.float32, device=uv.device)
+    t_r = launch_time(torch, lambda: stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, out=[out], scales=scales,
+                                                      decoder=dec), steps, warmup)
+    t_s = launch_time(torch, lambda: stf.filter(tex, uv, "bicubic", 0, 0, out=[out], scales=scales, decoder=dec),
+                      steps, warmup)
+    t_f = launch_time(torch, lambda: stf.filter_reference(tex, uv, "bicubic", out=[out], scales=scales, decoder=dec),
+                      max(steps // 10, 5), 2)
+    ref = stf.filter_reference(tex, uv, "bicubic", scales=scales, decoder=dec)[0]
+    o_r = stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, scales=scales, decoder=dec)[0]
+    o_s = stf.filter(tex, uv, "bicubic", 0, 0, scales=scales, decoder=dec)[0]
+    peak = float(ref[..., :3].abs().max())
+    px = H * W
+
+    def row(t, decodes):
+        return {"avg_launch_us": round(t * 1e6, 2), "Mpixel_s": round(px / t / 1e6, 1),
+                "decode_tflops": round(px * decodes * DECODE_FLOPS_PER_TEXEL / t / 1e12, 1)}
+
+    return {"workload": "1024^2x8 FP8 E4M3 latents + per-channel scales, MLP 8-64-64-4 BF16 on MFMA, "
+                        "1920x1080 plane 4x-16x, bicubic",
+            "magnification": info["mag_min_axis"],
+            "reuse_tile8x8": row(t_r, 1), "stf_1sample": row(t_s, 1), "full_filter_16_decodes": row(t_f, 16),
+            "psnr_reuse_db": round(psnr_rgb(torch, o_r, ref, peak), 2),
+            "psnr_stf_db": round(psnr_rgb(torch, o_s, ref, peak), 2),
+            "psnr_against": "the GPU's decoded deterministic filter, peak = max |reference RGB|",
+            "mfma_bf16_peak_tflops": 2500.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +242,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--sets", type=int, default=8, help="rotating UV/output buffer sets")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the precision, backward and latent-decoder comparisons")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the per-launch traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -250,6 +364,10 @@ def main():
         "psnr": {"reuse_db": round(p_r, 2), "stf_db": round(p_s, 2), "gain_db": round(p_r - p_s, 2),
                  "against": "deterministic bicubic filter, albedo RGB, seed 0"},
     }
+    if not args.no_forms:
+        res["precision_forms"] = precision_forms(torch, stf, w, uv0, args.steps // 2, args.warmup)
+        res["backward"] = backward_form(torch, stf, texs, uv0, args.steps // 4, args.warmup // 2)
+        res["latent_decoder"] = latent_form(torch, stf, w, args.steps // 2, args.warmup)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(texs_np, uv_np)
     print(json.dumps(res), flush=True)

@@ -140,12 +140,12 @@ def _plane_content(seed: int, size: int):
     return _PLANE_CACHE[key]
 
 
-def plane_albedo(seed: int = 0, size: int = 2048) -> np.ndarray:
+def plane_albedo(seed: int = 0, size: int = 2048, dtype=np.float16) -> np.ndarray:
     """RGBA16F albedo: 5-octave value noise (base period 64 texels, gain 1/2)
     mixed with a sharp-edged binary field (edge contrast >= 0.5 per channel
-    on average). Values in [0, 1], rounded to FP16."""
+    on average). Values in [0, 1], rounded to FP16 (or to `dtype`)."""
     albedo, _ = _plane_content(seed, size)
-    return albedo.astype(np.float16)
+    return albedo.astype(dtype)
 
 
 def plane_normal(seed: int = 0, size: int = 2048, strength: float = 8.0) -> np.ndarray:
@@ -395,3 +395,18 @@ def quantize(values: np.ndarray, kind: str, scale=None) -> np.ndarray:
     if kind == "f16":
         return t.to(torch.float16).numpy()
     raise ValueError(kind)
+
+
+def bf16_representable(values: np.ndarray) -> np.ndarray:
+    """values rounded to the nearest BF16 number, as float32."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(np.asarray(values, dtype=np.float32)))
+    return t.to(torch.bfloat16).to(torch.float32).numpy()
+
+
+def decoder_weights(seed: int = 0):
+    """Decoder MLP 8 -> 64 -> 64 -> 4 (He-initialised) whose W1, b1, W2, W3 are
+    BF16 numbers (the matrix cores take them exactly) and b2, b3 float32."""
+    (w1, b1), (w2, b2), (w3, b3) = mlp_weights(seed)
+    r = bf16_representable
+    return [(r(w1), r(b1)), (r(w2), b2), (r(w3), b3)]
