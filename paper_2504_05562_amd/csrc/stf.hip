@@ -57,6 +57,10 @@ constexpr bool kWeightTable = STF_WEIGHT_TABLE != 0;
 // 64-bit fixed-point accumulators, or records (64 x {s, r} + 64 x 16 B).
 constexpr int kAccFloatOffset = kBinRecords * 5;
 constexpr int kLdsFloatsPerWave = kAccFloatOffset + kBinRecords * 2;
+// backward bins: Nb float [kBins], then (8-byte aligned) u64 [kBins] + u64 [kBins][4]
+constexpr int kBwdN64Offset = (kBins + 1) & ~1;
+constexpr int kBwdLdsFloatsPerWave = kBwdN64Offset + kBins * (1 + 4) * 2;
+static_assert(kBwdLdsFloatsPerWave >= kLdsFloatsPerWave / 2, "backward LDS layout");
 
 struct Pixel {
     int px, py;          // screen pixel
@@ -326,6 +330,24 @@ __device__ __forceinline__ uint64_t fixed_of(float r, uint32_t e_max) {
 __device__ __forceinline__ float float_of(uint64_t n, uint32_t e_max) {
     const float f = fmaf((float)(uint32_t)(n >> 32), 4294967296.0f, (float)(uint32_t)n);   // within 2 ulp
     return ldexpf(f, (int)e_max - 183);
+}
+
+// Signed values in the same fixed point (two's complement; wrap-around
+// addition is exact). Magnitudes below 2^(e_ref - 183) truncate toward zero:
+// the absolute error per term is below 2^-57 of the largest term allowed.
+__device__ __forceinline__ uint64_t signed_fixed_of(float v, uint32_t e_ref) {
+    const uint32_t b = __float_as_uint(v);
+    const uint32_t e = (b >> 23) & 0xFFu;
+    const uint64_t m = (uint64_t)((b & 0x7FFFFFu) | (e != 0u ? 0x800000u : 0u));
+    const int sh = (int)e - (int)e_ref + 33;
+    const uint64_t a = sh >= 0 ? (m << (sh > 39 ? 39 : sh)) : (sh > -25 ? (m >> -sh) : 0ull);
+    return (b >> 31) ? (0ull - a) : a;
+}
+
+__device__ __forceinline__ float signed_float_of(uint64_t n, uint32_t e_ref) {
+    const bool neg = (int64_t)n < 0;
+    const float f = float_of(neg ? 0ull - n : n, e_ref);
+    return neg ? -f : f;
 }
 
 // Bin window and support box of the wave for one texture size (shared by
@@ -774,12 +796,28 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                 uint32_t rx, ry;
                 use_bins = bin_window<N>(P, ctx.x.base, ctx.y.base, mx, my, t.w, t.h, base_x, base_y, rx, ry);
                 if (use_bins) {
-                    float* Nb = lds;                 // [kBins] sum of 1/p per texel
-                    float* Qb = lds + kBins;         // [kBins][C] sum of f_c(x) q_c
-                    static_assert(kBins * (1 + 4) <= kLdsFloatsPerWave, "backward bins exceed the wave's LDS");
-                    for (int i = lane; i < kBins * (1 + C); i += 64) lds[i] = 0.0f;
+                    // LDS: Nb float [kBins] (sum of 1/p per texel), N64 u64 [kBins]
+                    // (its fixed-point accumulator), Q64 i64 [kBins][C] (sum of
+                    // f_c(x) q_c in fixed point). Integer LDS atomics do not
+                    // serialise on shared addresses the way FP32 ones do.
+                    float* Nb = lds;
+                    uint64_t* N64 = reinterpret_cast<uint64_t*>(lds + kBwdN64Offset);
+                    uint64_t* Q64 = N64 + kBins;
+                    for (int i = lane; i < kBins * (1 + C); i += 64) N64[i] = 0ull;
+                    for (int i = lane; i < kBins; i += 64) Nb[i] = 0.0f;
+                    const int my_bin = (int)(ry + ky) * kBinG + (int)(rx + kx);
+                    const uint32_t e = P.valid ? (__float_as_uint(r) >> 23) : 0u;
+                    const uint32_t e_max = wave_max(e);
+                    const bool fixed = __builtin_amdgcn_ballot_w64(P.valid && e + 33u < e_max) == 0;
                     wave_lds_sync();
-                    if (P.valid) atomicAdd(&Nb[(int)(ry + ky) * kBinG + (int)(rx + kx)], r);
+                    if (fixed) {
+                        if (P.valid) atomicAdd(reinterpret_cast<unsigned long long*>(&N64[my_bin]),
+                                               (unsigned long long)fixed_of(r, e_max));
+                        wave_lds_sync();
+                        for (int i = lane; i < kBins; i += 64) Nb[i] = float_of(N64[i], e_max);
+                    } else {
+                        if (P.valid) atomicAdd(&Nb[my_bin], r);
+                    }
                     wave_lds_sync();
                     const int bin0 = (int)ry * kBinG + (int)rx;
                     float B = 0.0f;
@@ -787,6 +825,13 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                     for (int b = 0; b < N; ++b)
 #pragma unroll
                         for (int aa = 0; aa < N; ++aa) B += ctx.wxy[b * N + aa] * Nb[bin0 + b * kBinG + aa];
+                    // |f_c(x) q_c| <= |dL/dout_c| (B >= 1: the own pick contributes
+                    // f_c / p_c = 1), so the wave's largest gradient exponent fixes
+                    // the scale; 64 terms of at most 2^58 units fit in 64 bits
+                    float gmax = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) gmax = fmaxf(gmax, fabsf(g[c]));
+                    const uint32_t eq = wave_max(__float_as_uint(gmax) >> 23) + 1u;
                     if (P.valid) {
                         const float inv = fast_rcp(B);
 #pragma unroll
@@ -797,7 +842,9 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                                 if (Nb[idx] != 0.0f) {
                                     const float f = ctx.wxy[b * N + aa] * inv;
 #pragma unroll
-                                    for (int c = 0; c < C; ++c) atomicAdd(&Qb[idx * C + c], f * g[c]);
+                                    for (int c = 0; c < C; ++c)
+                                        atomicAdd(reinterpret_cast<unsigned long long*>(&Q64[idx * C + c]),
+                                                  (unsigned long long)signed_fixed_of(f * g[c], eq));
                                 }
                             }
                     }
@@ -810,7 +857,7 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                             const uint32_t ty = (uint32_t)(base_y + (idx / kBinG)) & my;
                             float q[C];
 #pragma unroll
-                            for (int c = 0; c < C; ++c) q[c] = Qb[idx * C + c];
+                            for (int c = 0; c < C; ++c) q[c] = signed_float_of(Q64[idx * C + c], eq);
                             atomic_texel<C>(grad, t.w, tx | (ty << 16), q, nx);
                         }
                     }
@@ -853,10 +900,11 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
 
 template <int FILT, int MODE>
 __global__ __launch_bounds__(kThreads) void backward_kernel(Args a) {
-    __shared__ __align__(16) float lds_all[kWavesPerGroup * kLdsFloatsPerWave];
+    constexpr int kPerWave = kBwdLdsFloatsPerWave > kLdsFloatsPerWave ? kBwdLdsFloatsPerWave : kLdsFloatsPerWave;
+    __shared__ __align__(16) float lds_all[kWavesPerGroup * kPerWave];
     Pixel P;
     if (!setup_pixel(a, P)) return;
-    float* lds = lds_all + (threadIdx.x >> 6) * kLdsFloatsPerWave;
+    float* lds = lds_all + (threadIdx.x >> 6) * kPerWave;
     SelCtx<FILT> ctx;
     uint4 hq;
     for (int slot = 0; slot < a.ntex; ++slot) {

@@ -71,13 +71,22 @@ __device__ __forceinline__ f32x16 mfma_bf16(u32x4 a, u32x4 b, f32x16 c) {
 // Value of v held by lane l ^ 32.
 __device__ __forceinline__ uint32_t from_other_half(uint32_t v) { return (uint32_t)__shfl_xor((int)v, 32, 64); }
 
-// B operand of the next layer from accumulators: ReLU, round to BF16, and
-// take registers 8g..8g+7 as the lane's 8 K values.
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+// B operand of the next layer from accumulators: round to BF16, ReLU, and
+// take registers 8g..8g+7 as the lane's 8 K values. ReLU acts on the BF16
+// bit patterns as a signed 16-bit maximum with 0 (every value with the sign
+// bit set, -0 included, becomes +0; others are unchanged), one packed
+// instruction per two values; rounding first is equivalent because round to
+// nearest preserves the sign.
 __device__ __forceinline__ u32x4 relu_pack(const f32x16& d, int g) {
     u32x4 r;
+    const i16x2 zero = {0, 0};
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-        r[t] = pack_bf16(fmaxf(d[8 * g + 2 * t], 0.0f), fmaxf(d[8 * g + 2 * t + 1], 0.0f));
+    for (int t = 0; t < 4; ++t) {
+        const i16x2 v = __builtin_bit_cast(i16x2, pack_bf16(d[8 * g + 2 * t], d[8 * g + 2 * t + 1]));
+        r[t] = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, zero));
+    }
     return r;
 }
 
