@@ -90,72 +90,67 @@ __device__ __forceinline__ u32x4 relu_pack(const f32x16& d, int g) {
     return r;
 }
 
+// One column tile (32 pixels) through the three layers; returns the tile's
+// output accumulators (rows 0-3 are the outputs).
+__device__ __forceinline__ f32x16 decode_columns(const uint8_t* dec, u32x4 x, int lane, bool hi) {
+    const u32x4* A = reinterpret_cast<const u32x4*>(dec);
+    const f32x16 zero = {};
+    u32x4 b2[4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const f32x16 d = mfma_bf16(A[(kDecA1 >> 4) + m * 64 + lane], x, zero);
+        b2[2 * m] = relu_pack(d, 0);
+        b2[2 * m + 1] = relu_pack(d, 1);
+    }
+    const float* C2 = reinterpret_cast<const float*>(dec + kDecC2);
+    u32x4 b3[4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const float* cb = C2 + (m * 2 + (hi ? 1 : 0)) * 16;
+        f32x16 d;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) d[j] = cb[j];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) d = mfma_bf16(A[(kDecA2 >> 4) + (m * 4 + s) * 64 + lane], b2[s], d);
+        b3[2 * m] = relu_pack(d, 0);
+        b3[2 * m + 1] = relu_pack(d, 1);
+    }
+    const float* C3 = reinterpret_cast<const float*>(dec + kDecC3) + (hi ? 16 : 0);
+    f32x16 y;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) y[j] = C3[j];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) y = mfma_bf16(A[(kDecA3 >> 4) + s * 64 + lane], b3[s], y);
+    return y;
+}
+
 // Decode the latent texels of all 64 lanes (`lat`: the lane's 8 latents as
 // BF16, element k in bits 16(k%2) of dword k/2). `dec` is the packed
 // decoder in LDS. Must be called by all 64 lanes in uniform control flow.
-// Returns the lane's RGBA.
+// The two column tiles go through the layers one after the other, which
+// keeps one tile's activations live at a time.
 __device__ __forceinline__ void decode_latent(const uint8_t* dec, u32x4 lat, float out[4]) {
     const int lane = threadIdx.x & 63;
     const bool hi = lane >= 32;
-    const u32x4* A = reinterpret_cast<const u32x4*>(dec);
     u32x4 other;
 #pragma unroll
     for (int i = 0; i < 4; ++i) other[i] = from_other_half(lat[i]);
     const u32x4 one = {0x3F80u, 0u, 0u, 0u};      // BF16 1.0 at k = 8: the b1 column
-    const u32x4 x0 = hi ? one : lat;               // column tile 0: pixels of lanes 0-31
-    const u32x4 x1 = hi ? one : other;             // column tile 1: pixels of lanes 32-63
-    const f32x16 zero = {};
-
-    u32x4 b2[2][4];
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-        const u32x4 a = A[(kDecA1 >> 4) + m * 64 + lane];
-        const f32x16 d0 = mfma_bf16(a, x0, zero);
-        const f32x16 d1 = mfma_bf16(a, x1, zero);
-        b2[0][2 * m] = relu_pack(d0, 0);
-        b2[0][2 * m + 1] = relu_pack(d0, 1);
-        b2[1][2 * m] = relu_pack(d1, 0);
-        b2[1][2 * m + 1] = relu_pack(d1, 1);
-    }
-
-    const float* C2 = reinterpret_cast<const float*>(dec + kDecC2);
-    u32x4 b3[2][4];
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-        f32x16 c;
-        const float* cb = C2 + (m * 2 + (hi ? 1 : 0)) * 16;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) c[j] = cb[j];
-        f32x16 d0 = c, d1 = c;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const u32x4 a = A[(kDecA2 >> 4) + (m * 4 + s) * 64 + lane];
-            d0 = mfma_bf16(a, b2[0][s], d0);
-            d1 = mfma_bf16(a, b2[1][s], d1);
-        }
-        b3[0][2 * m] = relu_pack(d0, 0);
-        b3[0][2 * m + 1] = relu_pack(d0, 1);
-        b3[1][2 * m] = relu_pack(d1, 0);
-        b3[1][2 * m + 1] = relu_pack(d1, 1);
-    }
-
-    const float* C3 = reinterpret_cast<const float*>(dec + kDecC3) + (hi ? 16 : 0);
-    f32x16 c;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) c[j] = C3[j];
-    f32x16 y0 = c, y1 = c;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const u32x4 a = A[(kDecA3 >> 4) + s * 64 + lane];
-        y0 = mfma_bf16(a, b3[0][s], y0);
-        y1 = mfma_bf16(a, b3[1][s], y1);
-    }
+    // column tile 0: pixels of lanes 0-31; column tile 1: pixels of lanes 32-63
+    const f32x16 y0 = decode_columns(dec, hi ? one : lat, lane, hi);
+    // an empty asm that claims to read tile 0's result and rewrite tile 1's
+    // input: the compiler cannot start tile 1 before tile 0 is done, which
+    // keeps the kernel at about 80 VGPRs (6 waves per SIMD) instead of 120
+    u32x4 x1 = hi ? one : other;
+    float y00 = y0[0];
+    asm volatile("" : "+v"(x1[0]), "+v"(y00));
+    const f32x16 y1 = decode_columns(dec, x1, lane, hi);
     // rows 0-3 (the outputs) sit in registers 0-3 of lanes 0-31; lane l + 32
     // takes column l of tile 1 from lane l
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const float t1 = __uint_as_float(from_other_half(__float_as_uint(y1[i])));
-        out[i] = hi ? t1 : y0[i];
+        out[i] = hi ? t1 : (i == 0 ? y00 : y0[i]);
     }
 }
 
