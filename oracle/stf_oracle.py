@@ -429,7 +429,7 @@ def _own_weight_at(s: dict, sx_i: np.ndarray, sy_i: np.ndarray):
     return np.where(inside, f, 0.0), inside
 
 
-def stf_filter_reuse(textures, uv, filt, seed, frame, footprint, lut=None, tiles=None):
+def stf_filter_reuse(textures, uv, filt, seed, frame, footprint, lut=None, tiles=None, exact_filtering=False):
     """STF with sample reuse (Sec. 4), per slot.
 
     Pixel c combines the samples of the members i of its sharing footprint
@@ -441,6 +441,10 @@ def stf_filter_reuse(textures, uv, filt, seed, frame, footprint, lut=None, tiles
     the own sample (w_c = 1) always remains and with no useful neighbour the
     result is the one-tap STF value.
 
+    exact_filtering (Sec. 4.2, "Exact Filtering"): when the samples of c's
+    footprint include every texel of positive weight in c's own filter
+    support, c returns the deterministic filter value of Eq. (3) instead.
+
     Returns per slot (values [n, 64, C], selections [n, 64, 2])."""
     if tiles is None:
         tiles = all_tiles(uv.shape[1], uv.shape[0])
@@ -449,6 +453,8 @@ def stf_filter_reuse(textures, uv, filt, seed, frame, footprint, lut=None, tiles
     for slot, tex in enumerate(textures):
         s = stf_samples(tex, uv, tiles, slot, filt, seed, frame)
         C = s["T"].shape[-1]
+        n_sup = s["wx"].shape[-1]
+        seen = np.zeros(s["p"].shape + (n_sup, n_sup), dtype=bool)      # [tile, pixel, dy, dx]
         num = np.zeros(s["T"].shape, dtype=np.float64)
         den = np.zeros(s["p"].shape, dtype=np.float64)
         for k in range(members.shape[1]):
@@ -465,8 +471,24 @@ def stf_filter_reuse(textures, uv, filt, seed, frame, footprint, lut=None, tiles
             w = np.where(use, f_c / np.where(use, p_i, 1.0), 0.0)
             den += w
             num += np.where(use[..., None], w[..., None] * np.where(use[..., None], T_i, 0.0), 0.0)
+            if exact_filtering:
+                dx = np.mod(sx_i - (s["i0x"] - s["delta"]), s["tw"])
+                dy = np.mod(sy_i - (s["i0y"] - s["delta"]), s["th"])
+                t_i, p_i2 = np.nonzero(use)
+                seen[t_i, p_i2, dy[t_i, p_i2], dx[t_i, p_i2]] = True
         with np.errstate(invalid="ignore", divide="ignore"):
             val = num / den[..., None]
+        if exact_filtering:
+            positive = (s["wy"][..., :, None] * s["wx"][..., None, :]) > 0          # [tile, pixel, dy, dx]
+            covered = np.all(seen | ~positive, axis=(-2, -1))
+            values = texture_values(tex)
+            exact = np.zeros(s["T"].shape)
+            for b in range(n_sup):
+                yy = np.mod(s["i0y"] - s["delta"] + b, s["th"])
+                for a in range(n_sup):
+                    xx = np.mod(s["i0x"] - s["delta"] + a, s["tw"])
+                    exact += (s["wx"][..., a] * s["wy"][..., b])[..., None] * values[yy, xx]
+            val = np.where(covered[..., None], exact, val)
         val = np.where(s["valid"][..., None], val, 0.0)
         assert C == val.shape[-1]
         out.append((val, np.stack([s["sx"], s["sy"]], -1)))
