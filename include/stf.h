@@ -123,6 +123,12 @@ typedef struct stf_params {
     uint32_t frame;
 } stf_params;
 
+/* Exact filtering (Sec. 4.2): a pixel whose footprint's picks include every
+ * texel of positive weight under its own filter returns the Eq. (3) value
+ * over those texels instead of the estimate. Biased, lower error; practical
+ * for bilinear (4 texels), rare for bicubic (16). */
+#define STF_REUSE_EXACT_FILTERING 1
+
 typedef struct stf_reuse {
     int32_t footprint;      /* stf_footprint */
     int32_t lut_k;          /* STF_FP_LUT only: entries per pixel, 1..64 */
@@ -131,6 +137,8 @@ typedef struct stf_reuse {
                                equal to the pixel itself is ignored, the pixel
                                is always a member; repeated entries count
                                repeatedly. NULL for other footprints. */
+    int32_t flags;          /* 0 or STF_REUSE_EXACT_FILTERING */
+    int32_t reserved;       /* must be 0 */
 } stf_reuse;
 
 /*

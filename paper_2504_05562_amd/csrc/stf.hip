@@ -152,6 +152,44 @@ __device__ __forceinline__ void accumulate(const SelCtx<FILT>& ctx, uint32_t s, 
     }
 }
 
+// Exact filtering (Sec. 4.2): which texels of pixel c's support the shared
+// picks hit (bit dy * N + dx) and the Eq. (3) sum over those texels, each
+// counted once.
+template <int FILT, int C>
+struct Coverage {
+    static constexpr int N = SelCtx<FILT>::N;
+    uint32_t seen = 0u;
+    float sum[C];
+    __device__ __forceinline__ Coverage() {
+#pragma unroll
+        for (int c = 0; c < C; ++c) sum[c] = 0.0f;
+    }
+    __device__ __forceinline__ void add(const SelCtx<FILT>& ctx, uint32_t dx, uint32_t dy, const float* T) {
+        const uint32_t bit = 1u << (dy * N + dx);
+        if (!(seen & bit)) {
+            seen |= bit;
+            const float f = ctx.x.wsel(dx) * ctx.y.wsel(dy);
+#pragma unroll
+            for (int c = 0; c < C; ++c) sum[c] = fmaf(f, T[c], sum[c]);
+        }
+    }
+    __device__ __forceinline__ void add_pick(const SelCtx<FILT>& ctx, uint32_t s, const float* T, uint32_t mx,
+                                             uint32_t my) {
+        uint32_t dx, dy;
+        if (support_offset<N>(s, ctx.x.base, ctx.y.base, mx, my, dx, dy)) add(ctx, dx, dy, T);
+    }
+    // every support texel of positive weight was picked
+    __device__ __forceinline__ bool covered(const SelCtx<FILT>& ctx) const {
+        uint32_t need = 0u;
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+                if (ctx.wxy[b * N + a] > 0.0f) need |= 1u << (b * N + a);
+        return (seen & need) == need;
+    }
+};
+
 // ---------------------------------------------------------------- texel bins
 
 // One bin per texel of a kBinG x kBinG window: N = sum of 1/p over the picks
@@ -194,6 +232,15 @@ template <> struct Bins<kF16x4> {             // record {raw.x, raw.y, N, pad}, 
             acc[3] = fmaf(h2f(q.y >> 16), w, acc[3]);
         }
     }
+    // Eq. (3) term of the bin (zero texel when empty) and its coverage
+    __device__ static void exact(const float* l, int bin, float f, float* ex, bool& cov) {
+        const u3 q = *reinterpret_cast<const u3*>(__builtin_assume_aligned(&l[bin * 4], 16));
+        cov = cov && (f == 0.0f || __uint_as_float(q.z) != 0.0f);
+        ex[0] = fmaf(f, h2f(q.x), ex[0]);
+        ex[1] = fmaf(f, h2f(q.x >> 16), ex[1]);
+        ex[2] = fmaf(f, h2f(q.y), ex[2]);
+        ex[3] = fmaf(f, h2f(q.y >> 16), ex[3]);
+    }
 };
 
 template <> struct Bins<kF16x2> {             // record {raw, N}
@@ -222,6 +269,12 @@ template <> struct Bins<kF16x2> {             // record {raw, N}
             acc[1] = fmaf(h2f(q.x >> 16), w, acc[1]);
         }
     }
+    __device__ static void exact(const float* l, int bin, float f, float* ex, bool& cov) {
+        const uint2 q = reinterpret_cast<const uint2*>(l)[bin];
+        cov = cov && (f == 0.0f || __uint_as_float(q.y) != 0.0f);
+        ex[0] = fmaf(f, h2f(q.x), ex[0]);
+        ex[1] = fmaf(f, h2f(q.x >> 16), ex[1]);
+    }
 };
 
 template <> struct Bins<kF32x1> {             // record {T, N}
@@ -241,6 +294,11 @@ template <> struct Bins<kF32x1> {             // record {T, N}
         const float w = f * q.y;
         B += w;
         acc[0] = EXACT ? fmaf(w, q.x + nTc[0], acc[0]) : fmaf(q.x, w, acc[0]);
+    }
+    __device__ static void exact(const float* l, int bin, float f, float* ex, bool& cov) {
+        const float2 q = reinterpret_cast<const float2*>(l)[bin];
+        cov = cov && (f == 0.0f || q.y != 0.0f);
+        ex[0] = fmaf(f, q.x, ex[0]);
     }
 };
 
@@ -268,6 +326,14 @@ template <> struct Bins<kF32x4> {             // float4 T[kBinRecords], then flo
         const float T[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] = EXACT ? fmaf(w, T[c] + nTc[c], acc[c]) : fmaf(T[c], w, acc[c]);
+    }
+    __device__ static void exact(const float* l, int bin, float f, float* ex, bool& cov) {
+        const float4 q = reinterpret_cast<const float4*>(l)[bin];
+        cov = cov && (f == 0.0f || l[4 * kBinRecords + bin] != 0.0f);
+        ex[0] = fmaf(f, q.x, ex[0]);
+        ex[1] = fmaf(f, q.y, ex[1]);
+        ex[2] = fmaf(f, q.z, ex[2]);
+        ex[3] = fmaf(f, q.w, ex[3]);
     }
 };
 
@@ -374,15 +440,18 @@ __device__ __forceinline__ void update_geom(BinGeom<AxisCtx<FILT>::N>& g, const 
 }
 
 // Receive the pick of quad partner lane^X through DPP and accumulate it.
-template <int X, int FILT, int C>
+template <int X, int FILT, int C, bool EF, int CC>
 __device__ __forceinline__ void quad_step(const SelCtx<FILT>& ctx, uint32_t s, float r, const float* Tv, uint32_t mx,
-                                          uint32_t my, float& B, float* acc) {
+                                          uint32_t my, float& B, float* acc, Coverage<FILT, CC>& cov) {
     float Ti[C];
     const uint32_t si = quad_xor<X>(s);
     const float ri = quad_xor<X>(r);
 #pragma unroll
     for (int c = 0; c < C; ++c) Ti[c] = quad_xor<X>(Tv[c]);
     accumulate<FILT, C>(ctx, si, ri, Ti, mx, my, Tv, B, acc);
+    if constexpr (EF) {
+        if (ri != 0.0f) cov.add_pick(ctx, si, Ti, mx, my);   // off-screen partners carry r = 0
+    }
 }
 
 // The one-tap pick of one texture slot: per-axis offsets, texel, and the
@@ -407,7 +476,9 @@ __device__ __forceinline__ SlotPick pick_slot(const TexArg& t, const SelCtx<FILT
 // Exchange and estimator for one texture slot of one pixel. LAT: the texture
 // holds latents; the picked texel is decoded by the MLP in `dec` (LDS) before
 // it is shared, so every pixel decodes exactly one texel.
-template <int FILT, int MODE, int PL, bool LAT = false>
+// EF: exact filtering (Sec. 4.2) replaces the estimate by the Eq. (3) value
+// whenever the shared picks cover the pixel's support.
+template <int FILT, int MODE, int PL, bool LAT = false, bool EF = false>
 __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int slot, const Pixel& P,
                                           const SelCtx<FILT>& ctx, const BinGeom<AxisCtx<FILT>::N>& geom,
                                           const SlotPick& pk, float* lds, const uint8_t* dec = nullptr) {
@@ -454,11 +525,15 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
         float acc[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+        Coverage<FILT, EF ? C : 1> cov;            // used only with EF
+        bool covered = false;
 
         if constexpr (MODE == kModeQuad) {
-            quad_step<1, FILT, C>(ctx, s, r, Tv, mx, my, B, acc);
-            quad_step<2, FILT, C>(ctx, s, r, Tv, mx, my, B, acc);
-            quad_step<3, FILT, C>(ctx, s, r, Tv, mx, my, B, acc);
+            if constexpr (EF) cov.add(ctx, (uint32_t)kx, (uint32_t)ky, Tv);
+            quad_step<1, FILT, C, EF>(ctx, s, r, Tv, mx, my, B, acc, cov);
+            quad_step<2, FILT, C, EF>(ctx, s, r, Tv, mx, my, B, acc, cov);
+            quad_step<3, FILT, C, EF>(ctx, s, r, Tv, mx, my, B, acc, cov);
+            if constexpr (EF) covered = cov.covered(ctx);
         } else {
             bool use_bins = false;
             if constexpr (MODE == kModeBins) {
@@ -492,15 +567,19 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
                     float nTc[C];
 #pragma unroll
                     for (int c = 0; c < C; ++c) nTc[c] = -Tv[c];
+                    bool all_in = true;
 #pragma unroll
                     for (int b = 0; b < N; ++b) {
                         const float wyb = ctx.y.w(b);
 #pragma unroll
-                        for (int aa = 0; aa < N; ++aa)
-                            Bins<PL>::template gather<kExactDiff>(lds, bin0 + b * kBinStride + aa,
-                                                                  kWeightTable ? ctx.wxy[b * N + aa] : ctx.x.w(aa) * wyb,
-                                                                  nTc, B, acc);
+                        for (int aa = 0; aa < N; ++aa) {
+                            const float f = kWeightTable ? ctx.wxy[b * N + aa] : ctx.x.w(aa) * wyb;
+                            Bins<PL>::template gather<kExactDiff>(lds, bin0 + b * kBinStride + aa, f, nTc, B, acc);
+                            // same weights and order as the Eq. (3) kernel: bit-identical sums
+                            if constexpr (EF) Bins<PL>::exact(lds, bin0 + b * kBinStride + aa, f, cov.sum, all_in);
+                        }
                     }
+                    if constexpr (EF) covered = all_in;
                     if constexpr (!kExactDiff) {
                         // sum_j w_j T_j  ->  sum_j w_j (T_j - T_c), the form the final step expects
 #pragma unroll
@@ -520,6 +599,7 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
                 wave_lds_sync();
                 const int fp = (MODE == kModeBins) ? (int)STF_FP_TILE8X8 : a.footprint;
                 const int K = footprint_size(fp, a.lut_k);
+                if constexpr (EF) cov.add(ctx, (uint32_t)kx, (uint32_t)ky, Tv);
                 for (int m = 0; m < K; ++m) {
                     const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
                     if (j == P.q) continue;          // the own pick is already counted
@@ -527,7 +607,11 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
                     const float4 vj = val[j];
                     const float Ti[4] = {vj.x, vj.y, vj.z, vj.w};
                     accumulate<FILT, C>(ctx, mj.x, __uint_as_float(mj.y), Ti, mx, my, Tv, B, acc);
+                    if constexpr (EF) {
+                        if (__uint_as_float(mj.y) != 0.0f) cov.add_pick(ctx, mj.x, Ti, mx, my);
+                    }
                 }
+                if constexpr (EF) covered = cov.covered(ctx);
                 wave_lds_sync();
             }
         }
@@ -536,6 +620,12 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
             const float inv = fast_rcp(B);
 #pragma unroll
             for (int c = 0; c < C; ++c) o[c] = fmaf(acc[c], inv, Tv[c]);
+            if constexpr (EF) {
+                if (covered) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) o[c] = cov.sum[c];
+                }
+            }
             if (scale_out) {                     // Eq. (14) is linear in the texels
 #pragma unroll
                 for (int c = 0; c < C; ++c) o[c] *= t.scale[c];
@@ -584,7 +674,7 @@ __device__ __forceinline__ int payload_of(int fmt) {
 
 // NT textures, unrolled: descriptors are loaded once, and every pick and
 // texel fetch is issued before the first exchange so their latencies overlap.
-template <int FILT, int MODE, int NT, bool DEC>
+template <int FILT, int MODE, int NT, bool DEC, bool EF>
 __global__ __launch_bounds__(kThreads) void forward_kernel(Args a) {
     __shared__ __align__(16) float lds_all[(MODE == kModeRecords || MODE == kModeBins) ? kWavesPerGroup * kLdsFloatsPerWave : 4];
     __shared__ __align__(16) uint8_t dec[DEC ? kDecBytes : 16];
@@ -614,13 +704,13 @@ __global__ __launch_bounds__(kThreads) void forward_kernel(Args a) {
         ctx.update(P, t[i].w, t[i].h);
         if constexpr (MODE == kModeBins) update_geom<FILT>(geom, P, ctx, t[i].w, t[i].h);
         switch (payload_of(t[i].fmt)) {
-        case kF16x4: slot_pass<FILT, MODE, kF16x4>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
-        case kF16x2: slot_pass<FILT, MODE, kF16x2>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
-        case kF32x1: slot_pass<FILT, MODE, kF32x1>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
+        case kF16x4: slot_pass<FILT, MODE, kF16x4, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
+        case kF16x2: slot_pass<FILT, MODE, kF16x2, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
+        case kF32x1: slot_pass<FILT, MODE, kF32x1, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
         case kLatent:
-            if constexpr (DEC) slot_pass<FILT, MODE, kF32x4, true>(a, t[i], i, P, ctx, geom, pk[i], lds, dec);
+            if constexpr (DEC) slot_pass<FILT, MODE, kF32x4, true, EF>(a, t[i], i, P, ctx, geom, pk[i], lds, dec);
             break;
-        default: slot_pass<FILT, MODE, kF32x4>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
+        default: slot_pass<FILT, MODE, kF32x4, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
         }
     }
 }
@@ -1053,6 +1143,8 @@ int check_reuse(const stf_reuse* r) {
         if (r->lut == nullptr) return fail(STF_EINVAL, "footprint LUT requires a lut pointer");
         if (r->lut_k < 1 || r->lut_k > 64) return fail(STF_EINVAL, "lut_k=%d outside 1..64", r->lut_k);
     }
+    if ((r->flags & ~STF_REUSE_EXACT_FILTERING) != 0) return fail(STF_EINVAL, "unknown reuse flags 0x%x", r->flags);
+    if (r->reserved != 0) return fail(STF_EINVAL, "reuse reserved field must be 0");
     return STF_OK;
 }
 
@@ -1067,23 +1159,26 @@ int finish_launch(const char* what) {
     return STF_OK;
 }
 
+template <int FILT, int MODE, bool DEC, bool EF>
+void launch_nt(const stf::Args& a, hipStream_t s) {
+    const dim3 g = grid_of(a), b(stf::kThreads);
+    switch (a.ntex) {
+    case 1: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 1, DEC, EF>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 2, DEC, EF>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 3, DEC, EF>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 4, DEC, EF>), g, b, 0, s, a); break;
+    }
+}
+
 template <int FILT, int MODE>
 void launch_forward(const stf::Args& a, hipStream_t s) {
-    const dim3 g = grid_of(a), b(stf::kThreads);
-    if (a.dec != nullptr) {
-        switch (a.ntex) {
-        case 1: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 1, true>), g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 2, true>), g, b, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 3, true>), g, b, 0, s, a); break;
-        default: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 4, true>), g, b, 0, s, a); break;
-        }
-        return;
-    }
-    switch (a.ntex) {
-    case 1: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 1, false>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 2, false>), g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 3, false>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 4, false>), g, b, 0, s, a); break;
+    const bool dec = a.dec != nullptr;
+    if constexpr (MODE == stf::kModeStf) {     // one pick: exact filtering changes nothing
+        dec ? launch_nt<FILT, MODE, true, false>(a, s) : launch_nt<FILT, MODE, false, false>(a, s);
+    } else {
+        const bool ef = (a.flags & STF_REUSE_EXACT_FILTERING) != 0;
+        if (dec) ef ? launch_nt<FILT, MODE, true, true>(a, s) : launch_nt<FILT, MODE, true, false>(a, s);
+        else ef ? launch_nt<FILT, MODE, false, true>(a, s) : launch_nt<FILT, MODE, false, false>(a, s);
     }
 }
 
@@ -1101,6 +1196,7 @@ int forward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const s
         a.footprint = r->footprint;
         a.lut = r->lut;
         a.lut_k = r->lut_k;
+        a.flags = r->flags;
         switch (r->footprint) {
         case STF_FP_SELF: mode = stf::kModeStf; break;
         case STF_FP_QUAD2X2: mode = stf::kModeQuad; break;
@@ -1182,6 +1278,8 @@ int stf_backward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, co
     int rc = prepare(tex, ntex, scr, p, false, a);
     if (rc != STF_OK) return rc;
     if ((rc = check_reuse(r)) != STF_OK) return rc;
+    if (r->flags & STF_REUSE_EXACT_FILTERING)
+        return fail(STF_EUNSUPPORTED, "the adjoint does not cover exact filtering");
     if (dout == nullptr || dtex == nullptr) return fail(STF_EINVAL, "dout/dtex arrays are null");
     for (int i = 0; i < ntex; ++i) {
         if (dout[i] == nullptr || dtex[i] == nullptr) return fail(STF_EINVAL, "dout[%d]/dtex[%d] is null", i, i);

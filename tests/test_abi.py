@@ -33,6 +33,7 @@ def test_texture_descriptor_layout():
     assert ctypes.sizeof(stf.Texture) == 48
     assert stf.Texture.scale.offset == 32 and stf.Texture.decoder.offset == 40
     assert ctypes.sizeof(stf.Mlp) == 48
+    assert ctypes.sizeof(stf.Reuse) == 24 and stf.Reuse.flags.offset == 16
 
 
 _NAN_SCALE = (ctypes.c_float * 4)(1.0, float("nan"), 1.0, 1.0)
@@ -89,6 +90,13 @@ def test_validation_counts_and_nulls():
     bad_fp = stf.Reuse(42, 0, None)
     out = (ctypes.c_void_p * 1)(4096)
     assert lib.stf_filter_reuse(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(bad_fp), out, None, None) == -1
+    bad_flags = stf.Reuse(5, 0, None, 2, 0)
+    assert lib.stf_filter_reuse(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(bad_flags), out, None, None) == -1
+    bad_res = stf.Reuse(5, 0, None, 1, 7)
+    assert lib.stf_filter_reuse(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(bad_res), out, None, None) == -1
+    ef = stf.Reuse(5, 0, None, 1, 0)
+    dp = (ctypes.c_void_p * 1)(4096)
+    assert lib.stf_backward(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(ef), dp, dp, None) == -2
     lut_missing = stf.Reuse(6, 4, None)
     assert lib.stf_filter_reuse(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(lut_missing), out, None, None) == -1
     assert b"lut" in lib.stf_last_error()
