@@ -19,6 +19,9 @@ Stochastic Texture Filtering Through Sample Reuse", 2025):
   * the deterministic filtered value, Eq. (3),
   * the adjoint of Eq. (14) with respect to the texels.
 
+footprint_oracle holds the sparse sharing-footprint generator (Sec. 4.3,
+Sec. S5); its header lists the readings it takes.
+
 Parity status: the counter-based hash (pcg4d) has no published test vectors
 available offline; it is pinned by statistical properties only ("parity
 unpinned" against its publication). Footprint placements 2x2w/3x3/4x4 follow
@@ -28,3 +31,4 @@ tests/ that use closed forms, invariants and brute force.
 """
 from .stf_oracle import *  # noqa: F401,F403
 from .stf_oracle import __all__  # noqa: F401
+from . import footprint_oracle  # noqa: F401,E402  (sparse footprint generator, Sec. S5)
