@@ -231,6 +231,45 @@ typedef struct stf_mlp {
  */
 int stf_decoder_pack(const stf_mlp* mlp, void* packed, void* hip_stream);
 
+/*
+ * Pseudorandom sparse sharing footprints (Sec. 4.3, "Pseudorandom Sparse
+ * Footprints"; generator of Sec. S5). Writes a footprint LUT for
+ * STF_FP_LUT: for each of the 64 tile pixels (row-major ids) k-1 distinct
+ * other pixels, drawn around it from a discrete normal distribution of
+ * deviation sigma (widened where draws keep failing, near the tile
+ * borders), chosen among n_cand candidate sets per pixel so that every pixel
+ * is shared about equally often: the best of `trials` random choices, then
+ * coordinate descent, the best of `restarts` runs. The score is the sum of
+ * squared usage counts (ideal 64 (k-1)^2), which orders configurations as
+ * the standard deviation of the counts does. Deterministic in all
+ * parameters; random numbers come from pcg4d(q + 64 j, attempt, restart,
+ * seed ^ 0x5EED0001) for the draws and pcg4d(q, trial, restart,
+ * seed ^ 0x5EED0002) for the trials.
+ */
+typedef struct stf_footprint_params {
+    int32_t k;              /* footprint size including the pixel itself, 2..64 */
+    int32_t n_cand;         /* candidate sets per pixel, 1..64 (the paper: 16-32) */
+    float sigma;            /* deviation of the draws in tile pixels, > 0 (the paper: 1.4) */
+    int32_t trials;         /* random choices per restart, 1..2^24 (the paper: 10 000) */
+    int32_t restarts;       /* 1..4096 (the paper: 30) */
+    uint32_t seed;
+    int32_t reserved;       /* must be 0 */
+} stf_footprint_params;
+
+/* Device workspace stf_footprint_generate needs for `p`, or -1 if p is
+ * invalid (see stf_last_error). */
+int64_t stf_footprint_workspace_bytes(const stf_footprint_params* p);
+
+/*
+ *   workspace  device, >= stf_footprint_workspace_bytes(p) bytes, 256-byte
+ *              aligned, owned by the caller; contents need no initialisation
+ *   lut        device uint8 [64][k-1], written
+ *   score      device int64, nullable: the LUT's score
+ * Enqueued on `hip_stream`; nothing is allocated.
+ */
+int stf_footprint_generate(const stf_footprint_params* p, void* workspace, int64_t workspace_bytes, uint8_t* lut,
+                           int64_t* score, void* hip_stream);
+
 /* Message for the last non-OK status returned on this thread ("" if none).
  * The pointer stays valid until the next call on this thread. */
 const char* stf_last_error(void);

@@ -20,7 +20,8 @@ from typing import Sequence
 
 __all__ = [
     "BILINEAR", "BICUBIC", "FOOTPRINTS", "FORMATS", "library", "lib_path", "version",
-    "filter", "filter_reuse", "filter_reference", "backward", "StfError",
+    "filter", "filter_reuse", "filter_reference", "backward", "StfError", "pack_decoder",
+    "generate_footprints", "footprint_set", "stf_reuse_autograd",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -60,6 +61,12 @@ class Mlp(ctypes.Structure):
 DECODER_BYTES = 14720
 
 
+class FootprintParams(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("n_cand", ctypes.c_int32), ("sigma", ctypes.c_float),
+                ("trials", ctypes.c_int32), ("restarts", ctypes.c_int32), ("seed", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32)]
+
+
 class Screen(ctypes.Structure):
     _fields_ = [("uv", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
 
@@ -79,7 +86,8 @@ EXACT_FILTERING = 1
 
 _lib = None
 _SYMBOLS = ("stf_filter", "stf_filter_reuse", "stf_filter_reference", "stf_backward",
-            "stf_decoder_pack", "stf_last_error", "stf_version")
+            "stf_decoder_pack", "stf_footprint_workspace_bytes", "stf_footprint_generate",
+            "stf_last_error", "stf_version")
 
 
 def library() -> ctypes.CDLL:
@@ -97,6 +105,10 @@ def library() -> ctypes.CDLL:
         lib.stf_filter_reference.argtypes = tex_args + [P(vp), vp]
         lib.stf_backward.argtypes = tex_args + [P(Reuse), P(vp), P(vp), vp]
         lib.stf_decoder_pack.argtypes = [P(Mlp), vp, vp]
+        lib.stf_footprint_workspace_bytes.argtypes = [P(FootprintParams)]
+        lib.stf_footprint_workspace_bytes.restype = ctypes.c_int64
+        lib.stf_footprint_generate.argtypes = [P(FootprintParams), vp, ctypes.c_int64, vp, vp, vp]
+        lib.stf_footprint_generate.restype = ctypes.c_int
         for name in ("stf_filter", "stf_filter_reuse", "stf_filter_reference", "stf_backward",
                      "stf_decoder_pack", "stf_version"):
             getattr(lib, name).restype = ctypes.c_int
@@ -140,6 +152,36 @@ def pack_decoder(layers, stream=None):
     m = Mlp(*[t.data_ptr() for t in flat])
     _check(library().stf_decoder_pack(ctypes.byref(m), ctypes.c_void_p(packed.data_ptr()), _stream_handle(stream)))
     return packed
+
+
+def generate_footprints(k=9, n_cand=32, sigma=1.4, trials=10000, restarts=30, seed=0, device="cuda",
+                        stream=None):
+    """Pseudorandom sparse sharing footprints (stf_footprint_generate):
+    returns (lut uint8 GPU tensor [64, k-1] for footprint='lut', score int64
+    GPU tensor [1])."""
+    import torch
+    lib = library()
+    prm = FootprintParams(int(k), int(n_cand), float(sigma), int(trials), int(restarts), int(seed) & 0xFFFFFFFF, 0)
+    nbytes = lib.stf_footprint_workspace_bytes(ctypes.byref(prm))
+    if nbytes < 0:
+        raise StfError(lib.stf_last_error().decode())
+    ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    lut = torch.empty((64, int(k) - 1), dtype=torch.uint8, device=device)
+    score = torch.empty(1, dtype=torch.int64, device=device)
+    _check(lib.stf_footprint_generate(ctypes.byref(prm), ctypes.c_void_p(ws.data_ptr() + off), ctypes.c_int64(nbytes),
+                                      ctypes.c_void_p(lut.data_ptr()), ctypes.c_void_p(score.data_ptr()),
+                                      _stream_handle(stream)))
+    return lut, score
+
+
+def footprint_set(frames, k=9, n_cand=32, sigma=1.4, trials=10000, restarts=30, seed=0, device="cuda"):
+    """`frames` footprint LUTs with seeds seed, seed + 1, ... (uint8 GPU
+    tensor [frames, 64, k-1]); frame f filters with set[f % frames], which
+    cycles the patterns over frames (Sec. 4.3)."""
+    import torch
+    return torch.stack([generate_footprints(k, n_cand, sigma, trials, restarts, seed + f, device)[0]
+                        for f in range(int(frames))])
 
 
 def _texture_descs(textures: Sequence, need_data: bool = True, scales=None, decoder=None):

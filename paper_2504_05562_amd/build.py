@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libstf.so")
-SOURCES = [os.path.join(CSRC, "stf.hip")]
+SOURCES = [os.path.join(CSRC, "stf.hip"), os.path.join(CSRC, "footprints.hip")]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

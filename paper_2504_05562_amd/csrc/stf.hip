@@ -33,6 +33,7 @@
 
 #include "stf_device.h"
 #include "stf_decoder.h"
+#include "stf_status.h"
 
 namespace stf {
 
@@ -1014,11 +1015,12 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(Args a) {
 // host side of the C ABI
 // ============================================================================
 
+namespace stf_host {
+
 namespace {
-
 thread_local std::string g_last_error;
+}
 
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -1028,6 +1030,16 @@ int fail(int code, const char* fmt, ...) {
     g_last_error = buf;
     return code;
 }
+
+void clear_error() { stf_host::clear_error(); }
+
+const char* last_error() { return g_last_error.c_str(); }
+
+}  // namespace stf_host
+
+namespace {
+
+using stf_host::fail;
 
 // Channels of the stored texel (8 for latent grids) and of the filtered,
 // decoded texel (4 for latent grids).
@@ -1184,7 +1196,7 @@ void launch_forward(const stf::Args& a, hipStream_t s) {
 
 int forward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
             const stf_reuse* r, float* const* out, int32_t* sel, void* hip_stream) {
-    g_last_error.clear();
+    stf_host::clear_error();
     stf::Args a;
     int rc = prepare(tex, ntex, scr, p, true, a, true);
     if (rc != STF_OK) return rc;
@@ -1229,7 +1241,7 @@ int stf_filter(const stf_texture* tex, int32_t ntex, const stf_screen* scr, cons
 int stf_filter_reuse(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
                      const stf_reuse* r, float* const* out, int32_t* sel, void* hip_stream) {
     if (r == nullptr) {
-        g_last_error.clear();
+        stf_host::clear_error();
         return fail(STF_EINVAL, "reuse descriptor is null");
     }
     return forward(tex, ntex, scr, p, r, out, sel, hip_stream);
@@ -1237,7 +1249,7 @@ int stf_filter_reuse(const stf_texture* tex, int32_t ntex, const stf_screen* scr
 
 int stf_filter_reference(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
                          float* const* out, void* hip_stream) {
-    g_last_error.clear();
+    stf_host::clear_error();
     stf::Args a;
     int rc = prepare(tex, ntex, scr, p, true, a, true);
     if (rc != STF_OK) return rc;
@@ -1257,7 +1269,7 @@ int stf_filter_reference(const stf_texture* tex, int32_t ntex, const stf_screen*
 }
 
 int stf_decoder_pack(const stf_mlp* mlp, void* packed, void* hip_stream) {
-    g_last_error.clear();
+    stf_host::clear_error();
     if (mlp == nullptr || packed == nullptr) return fail(STF_EINVAL, "null mlp descriptor or packed buffer");
     const float* ws[6] = {mlp->w1, mlp->b1, mlp->w2, mlp->b2, mlp->w3, mlp->b3};
     for (int i = 0; i < 6; ++i) {
@@ -1273,7 +1285,7 @@ int stf_decoder_pack(const stf_mlp* mlp, void* packed, void* hip_stream) {
 
 int stf_backward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
                  const stf_reuse* r, const float* const* dout, float* const* dtex, void* hip_stream) {
-    g_last_error.clear();
+    stf_host::clear_error();
     stf::Args a;
     int rc = prepare(tex, ntex, scr, p, false, a);
     if (rc != STF_OK) return rc;
@@ -1312,7 +1324,7 @@ int stf_backward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, co
     return finish_launch("backward");
 }
 
-const char* stf_last_error(void) { return g_last_error.c_str(); }
+const char* stf_last_error(void) { return stf_host::last_error(); }
 
 int stf_version(void) { return STF_VERSION; }
 

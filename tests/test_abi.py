@@ -124,3 +124,20 @@ def test_latent_and_decoder_validation():
     m = stf.Mlp(4096, 4096, 4096, 4096, 4096, 4096)
     assert lib.stf_decoder_pack(ctypes.byref(m), ctypes.c_void_p(4104), None) == -1
     assert lib.stf_decoder_pack(None, ctypes.c_void_p(4096), None) == -1
+
+
+def test_footprint_generator_validation():
+    lib = stf.library()
+    good = stf.FootprintParams(9, 32, 1.4, 10000, 30, 0, 0)
+    n = lib.stf_footprint_workspace_bytes(ctypes.byref(good))
+    assert n >= 30 * 64 * 32 * 8 and n % 256 == 0
+    for bad in (stf.FootprintParams(1, 32, 1.4, 10, 3, 0, 0), stf.FootprintParams(9, 0, 1.4, 10, 3, 0, 0),
+                stf.FootprintParams(9, 32, 0.0, 10, 3, 0, 0), stf.FootprintParams(9, 32, 1.4, 0, 3, 0, 0),
+                stf.FootprintParams(9, 32, 1.4, 10, 0, 0, 0), stf.FootprintParams(9, 32, 1.4, 10, 3, 0, 1)):
+        assert lib.stf_footprint_workspace_bytes(ctypes.byref(bad)) == -1
+    assert lib.stf_footprint_generate(ctypes.byref(good), None, n, ctypes.c_void_p(4096), None, None) == -1
+    assert lib.stf_footprint_generate(ctypes.byref(good), ctypes.c_void_p(4096), n - 1, ctypes.c_void_p(4096),
+                                      None, None) == -1
+    assert b"workspace" in lib.stf_last_error()
+    assert lib.stf_footprint_generate(ctypes.byref(good), ctypes.c_void_p(4096 + 64), n, ctypes.c_void_p(4096),
+                                      None, None) == -1

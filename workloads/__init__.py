@@ -74,7 +74,7 @@ def small_texture(seed: int = 0, size: int = 256) -> np.ndarray:
     sq = np.arange(size) // 16
     checker = colours[sq][:, sq]
     tex = 0.5 * noise + 0.5 * checker
-    return np.clip(np.rint(tex * 255.0), 0, 255).astype(np.uint8)
+    return np.ascontiguousarray(np.clip(np.rint(tex * 255.0), 0, 255).astype(np.uint8))
 
 
 def small_screen(width: int = 512, height: int = 512, tex_size: int = 256, mag: float = 8.0,
