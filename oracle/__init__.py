@@ -32,3 +32,4 @@ tests/ that use closed forms, invariants and brute force.
 from .stf_oracle import *  # noqa: F401,F403
 from .stf_oracle import __all__  # noqa: F401
 from . import footprint_oracle  # noqa: F401,E402  (sparse footprint generator, Sec. S5)
+from . import estimators_oracle  # noqa: F401,E402  (comparison estimators, Sec. 4.1)
