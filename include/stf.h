@@ -128,6 +128,29 @@ typedef struct stf_params {
  * over those texels instead of the estimate. Biased, lower error; practical
  * for bilinear (4 texels), rare for bicubic (16). */
 #define STF_REUSE_EXACT_FILTERING 1
+/* Clamp the estimate per channel to the range of the shared texels inside
+ * the pixel's own filter support (Sec. 4.1; biased, bounds the error of the
+ * comparison estimators; Eq. (14) already lies in that range). */
+#define STF_REUSE_CLAMP 2
+
+/* Estimator over the shared picks: the paper's Eq. (14), or one of the
+ * estimators Sec. 4.1 compares it with (comparison only: one generic
+ * kernel, not the optimised path). With w_i = f_c(x_i) / p_i(x_i) and n
+ * shared picks:
+ *   STF_EST_IS             (1/n) sum w_i T_i, Eq. (6)
+ *   STF_EST_MIS            sum f_c(x_i) T_i / sum_j p_j(x_i) (balance heuristic)
+ *   STF_EST_PAIRWISE_MIS   pairwise MIS with the pixel's own technique as the
+ *                          canonical one: m_i = p_i / ((n-1) p_i + p_c),
+ *                          m_c = 1/(n-1) sum_i p_c / (p_c + (n-1) p_i)
+ *   STF_EST_REGRESSION     (1/n) sum [w_i T_i - beta (w_i - 1)], Eq. (7),
+ *                          beta = sum (w_i - wbar) w_i T_i / sum (w_i - wbar)^2 */
+typedef enum stf_estimator {
+    STF_EST_WIS = 0,
+    STF_EST_IS = 1,
+    STF_EST_MIS = 2,
+    STF_EST_PAIRWISE_MIS = 3,
+    STF_EST_REGRESSION = 4
+} stf_estimator;
 
 typedef struct stf_reuse {
     int32_t footprint;      /* stf_footprint */
@@ -137,8 +160,8 @@ typedef struct stf_reuse {
                                equal to the pixel itself is ignored, the pixel
                                is always a member; repeated entries count
                                repeatedly. NULL for other footprints. */
-    int32_t flags;          /* 0 or STF_REUSE_EXACT_FILTERING */
-    int32_t reserved;       /* must be 0 */
+    int32_t flags;          /* STF_REUSE_EXACT_FILTERING (with STF_EST_WIS only) | STF_REUSE_CLAMP */
+    int32_t estimator;      /* stf_estimator; 0 = Eq. (14) */
 } stf_reuse;
 
 /*

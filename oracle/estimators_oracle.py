@@ -57,10 +57,16 @@ def _weight_of(s: dict, pix: np.ndarray, sx: np.ndarray, sy: np.ndarray) -> np.n
 
 
 def stf_filter_estimator(textures, uv, filt, seed, frame, footprint, estimator, clamp=False, lut=None,
-                         tiles=None):
+                         tiles=None, diagnostics=None):
     """Per slot (values [n, 64, C], selections [n, 64, 2]) of the comparison
-    estimator `estimator` over the footprint's shared samples."""
-    if estimator == "wis" and not clamp:
+    estimator `estimator` over the footprint's shared samples.
+
+    diagnostics: an optional list that receives, per slot, a dict with
+    "magnitude" [n, 64, C] (sum of the absolute terms the estimate adds up,
+    the scale of its rounding error) and "spread" [n, 64] (for the
+    regression estimator, sum (w_i - wbar)^2 / sum w_i^2, the conditioning of
+    beta; 1 otherwise)."""
+    if estimator == "wis" and not clamp and diagnostics is None:
         return so.stf_filter_reuse(textures, uv, filt, seed, frame, footprint, lut=lut, tiles=tiles)
     if estimator not in ESTIMATORS:
         raise ValueError(estimator)
@@ -88,49 +94,57 @@ def stf_filter_estimator(textures, uv, filt, seed, frame, footprint, estimator, 
         n = present.sum(-1)                                     # [ntile, 64]
         w = np.where(present, f_c / np.where(present, p_i, 1.0), 0.0)
         C = T.shape[-1]
-        if estimator == "wis":
-            val = np.sum(w[..., None] * np.where(present[..., None], T, 0.0), -2) / np.sum(w, -1)[..., None]
-        elif estimator == "is":
-            val = np.sum(w[..., None] * np.where(present[..., None], T, 0.0), -2) / n[..., None]
-        elif estimator in ("mis", "pmis"):
-            # p_j(x_i) for every pair of members: [ntile, 64, K(i), K(j)]
-            pj = np.zeros(sx.shape + (K,))
-            for jj in range(K):
-                pix_j = np.broadcast_to(mem[..., jj:jj + 1], sx.shape)
-                pj[..., jj] = _weight_of(s, pix_j.reshape(ntile, -1), sx.reshape(ntile, -1),
-                                         sy.reshape(ntile, -1)).reshape(sx.shape)
-            pj = np.where(present[..., None, :] & present[..., :, None], pj, 0.0)
-            if estimator == "mis":
-                den = pj.sum(-1)                                # sum_j p_j(x_i) >= p_i(x_i) > 0
-                coef = np.where(present, f_c / np.where(present, den, 1.0), 0.0)
-            else:
-                # canonical technique: the member that is the pixel itself
-                is_c = present & (mem == own_b)
-                first_c = is_c & (np.cumsum(is_c, -1) == 1)
-                pc_at = np.sum(np.where(first_c[..., None, :], pj, 0.0), -1)          # p_c(x_i)
-                nm1 = np.maximum(n - 1, 1)[..., None]
-                dm = nm1 * p_i + pc_at
-                m_i = np.where(dm > 0, p_i / np.where(dm > 0, dm, 1.0), 0.0)
-                # m_c at x_c: 1/(n-1) sum over the other members j of p_c(x_c) / (p_c(x_c) + (n-1) p_j(x_c))
-                xc_row = np.argmax(first_c, -1)                 # index of the canonical sample
-                pj_at_xc = np.take_along_axis(pj, xc_row[..., None, None], -2)[..., 0, :]  # p_j(x_c) [.., K]
-                pc_xc = np.take_along_axis(p_i, xc_row[..., None], -1)[..., 0]            # p_c(x_c)
-                others = present & ~first_c
-                m_c = np.sum(np.where(others, pc_xc[..., None] / (pc_xc[..., None] + nm1 * pj_at_xc), 0.0), -1) \
-                    / nm1[..., 0]
-                m_c = np.where(n == 1, 1.0, m_c)
-                m = np.where(first_c, m_c[..., None], np.where(others, m_i, 0.0))
-                coef = np.where(present, m * f_c / np.where(present, p_i, 1.0), 0.0)
-            val = np.sum(coef[..., None] * np.where(present[..., None], T, 0.0), -2)
-        else:                                                   # regression
-            nn = n[..., None]
-            wbar = np.sum(w, -1, keepdims=True) / nn
-            dw = np.where(present, w - wbar, 0.0)
-            wT = w[..., None] * np.where(present[..., None], T, 0.0)
-            den = np.sum(dw * dw, -1)[..., None]
-            beta = np.where(den > 0, np.sum(dw[..., None] * wT, -2) / np.where(den > 0, den, 1.0), 0.0)
-            cv = np.sum(np.where(present, w - 1.0, 0.0), -1)[..., None]
-            val = (np.sum(wT, -2) - beta * cv) / nn
+        aT = np.abs(np.where(present[..., None], T, 0.0))
+        spread = np.ones(n.shape)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            if estimator == "wis":
+                val = np.sum(w[..., None] * np.where(present[..., None], T, 0.0), -2) / np.sum(w, -1)[..., None]
+                mag = np.sum(w[..., None] * aT, -2) / np.sum(w, -1)[..., None]
+            elif estimator == "is":
+                val = np.sum(w[..., None] * np.where(present[..., None], T, 0.0), -2) / n[..., None]
+                mag = np.sum(w[..., None] * aT, -2) / n[..., None]
+            elif estimator in ("mis", "pmis"):
+                # p_j(x_i) for every pair of members: [ntile, 64, K(i), K(j)]
+                pj = np.zeros(sx.shape + (K,))
+                for jj in range(K):
+                    pix_j = np.broadcast_to(mem[..., jj:jj + 1], sx.shape)
+                    pj[..., jj] = _weight_of(s, pix_j.reshape(ntile, -1), sx.reshape(ntile, -1),
+                                             sy.reshape(ntile, -1)).reshape(sx.shape)
+                pj = np.where(present[..., None, :] & present[..., :, None], pj, 0.0)
+                if estimator == "mis":
+                    den = pj.sum(-1)                                # sum_j p_j(x_i) >= p_i(x_i) > 0
+                    coef = np.where(present, f_c / np.where(present, den, 1.0), 0.0)
+                else:
+                    # canonical technique: the member that is the pixel itself
+                    is_c = present & (mem == own_b)
+                    first_c = is_c & (np.cumsum(is_c, -1) == 1)
+                    pc_at = np.sum(np.where(first_c[..., None, :], pj, 0.0), -1)          # p_c(x_i)
+                    nm1 = np.maximum(n - 1, 1)[..., None]
+                    dm = nm1 * p_i + pc_at
+                    m_i = np.where(dm > 0, p_i / np.where(dm > 0, dm, 1.0), 0.0)
+                    # m_c at x_c: 1/(n-1) sum over the other members j of p_c(x_c) / (p_c(x_c) + (n-1) p_j(x_c))
+                    xc_row = np.argmax(first_c, -1)                 # index of the canonical sample
+                    pj_at_xc = np.take_along_axis(pj, xc_row[..., None, None], -2)[..., 0, :]  # p_j(x_c) [.., K]
+                    pc_xc = np.take_along_axis(p_i, xc_row[..., None], -1)[..., 0]            # p_c(x_c)
+                    others = present & ~first_c
+                    m_c = np.sum(np.where(others, pc_xc[..., None] / (pc_xc[..., None] + nm1 * pj_at_xc), 0.0), -1) \
+                        / nm1[..., 0]
+                    m_c = np.where(n == 1, 1.0, m_c)
+                    m = np.where(first_c, m_c[..., None], np.where(others, m_i, 0.0))
+                    coef = np.where(present, m * f_c / np.where(present, p_i, 1.0), 0.0)
+                val = np.sum(coef[..., None] * np.where(present[..., None], T, 0.0), -2)
+                mag = np.sum(np.abs(coef)[..., None] * aT, -2)
+            else:                                                   # regression
+                nn = n[..., None]
+                wbar = np.sum(w, -1, keepdims=True) / nn
+                dw = np.where(present, w - wbar, 0.0)
+                wT = w[..., None] * np.where(present[..., None], T, 0.0)
+                den = np.sum(dw * dw, -1)[..., None]
+                beta = np.where(den > 0, np.sum(dw[..., None] * wT, -2) / np.where(den > 0, den, 1.0), 0.0)
+                cv = np.sum(np.where(present, w - 1.0, 0.0), -1)[..., None]
+                val = (np.sum(wT, -2) - beta * cv) / nn
+                mag = (np.sum(np.abs(wT), -2) + np.abs(beta) * np.sum(np.abs(np.where(present, w - 1.0, 0.0)), -1)[..., None]) / nn
+                spread = den[..., 0] / np.maximum(np.sum(w * w, -1), 1e-300)
         if clamp:
             used = present & (f_c > 0)
             big = np.where(used[..., None], T, np.inf).min(-2)
@@ -138,5 +152,7 @@ def stf_filter_estimator(textures, uv, filt, seed, frame, footprint, estimator, 
             val = np.minimum(np.maximum(val, big), small)
         val = np.where(s["valid"][..., None], val, 0.0)
         assert val.shape[-1] == C
+        if diagnostics is not None:
+            diagnostics.append({"magnitude": np.where(s["valid"][..., None], mag, 0.0), "spread": spread})
         out.append((val, np.stack([s["sx"], s["sy"]], -1)))
     return out

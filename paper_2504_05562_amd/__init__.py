@@ -78,10 +78,12 @@ class Params(ctypes.Structure):
 
 class Reuse(ctypes.Structure):
     _fields_ = [("footprint", ctypes.c_int32), ("lut_k", ctypes.c_int32), ("lut", ctypes.c_void_p),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("estimator", ctypes.c_int32)]
 
 
 EXACT_FILTERING = 1
+CLAMP = 2
+ESTIMATORS = {"wis": 0, "is": 1, "mis": 2, "pmis": 3, "regression": 4}
 
 
 _lib = None
@@ -254,14 +256,15 @@ def _outputs(uv, chans, out=None):
     return out, ptrs
 
 
-def _reuse(footprint, lut, exact_filtering=False):
+def _reuse(footprint, lut, exact_filtering=False, estimator="wis", clamp=False):
     fp = FOOTPRINTS[footprint] if isinstance(footprint, str) else int(footprint)
-    flags = EXACT_FILTERING if exact_filtering else 0
+    flags = (EXACT_FILTERING if exact_filtering else 0) | (CLAMP if clamp else 0)
+    est = ESTIMATORS[estimator] if isinstance(estimator, str) else int(estimator)
     if lut is None:
-        return Reuse(fp, 0, None, flags, 0)
+        return Reuse(fp, 0, None, flags, est)
     if lut.dtype != __import__("torch").uint8 or lut.dim() != 2 or lut.shape[0] != 64 or not lut.is_contiguous():
         raise ValueError("lut must be a contiguous uint8 GPU tensor [64, K]")
-    return Reuse(fp, int(lut.shape[1]), lut.data_ptr(), flags, 0)
+    return Reuse(fp, int(lut.shape[1]), lut.data_ptr(), flags, est)
 
 
 def filter(textures, uv, filter="bicubic", seed=0, frame=0, sel=False, out=None, stream=None, scales=None, decoder=None):
@@ -281,16 +284,18 @@ def filter(textures, uv, filter="bicubic", seed=0, frame=0, sel=False, out=None,
 
 
 def filter_reuse(textures, uv, footprint="tile8x8", filter="bicubic", seed=0, frame=0, lut=None,
-                 sel=False, out=None, stream=None, scales=None, decoder=None, exact_filtering=False):
+                 sel=False, out=None, stream=None, scales=None, decoder=None, exact_filtering=False,
+                 estimator="wis", clamp=False):
     """STF with sample reuse (stf_filter_reuse). `lut` is a uint8 GPU tensor
     [64, K] of tile pixel ids for footprint='lut'; exact_filtering selects
-    STF_REUSE_EXACT_FILTERING."""
+    STF_REUSE_EXACT_FILTERING; estimator ('wis' = Eq. (14), 'is', 'mis',
+    'pmis', 'regression') and clamp select the comparison estimators."""
     import torch
     lib = library()
     descs, chans, _keep = _texture_descs(textures, scales=scales, decoder=decoder)
     scr = _screen(uv)
     prm = _params(filter, seed, frame)
-    r = _reuse(footprint, lut, exact_filtering)
+    r = _reuse(footprint, lut, exact_filtering, estimator, clamp)
     out, ptrs = _outputs(uv, chans, out)
     s = torch.empty((len(textures),) + tuple(uv.shape[:2]) + (2,), dtype=torch.int32, device=uv.device) if sel else None
     _check(lib.stf_filter_reuse(descs, len(textures), ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(r), ptrs,

@@ -716,6 +716,215 @@ __global__ __launch_bounds__(kThreads) void forward_kernel(Args a) {
     }
 }
 
+// ---------------------------------------------------------------- comparison estimators
+//
+// The estimators Sec. 4.1 evaluates before proposing Eq. (14), over the same
+// shared picks: pixel c holds the picks x_i of its footprint's on-screen
+// members i (itself included), each drawn from member i's PMF p_i = f_i.
+// With w_i = f_c(x_i) / p_i(x_i) and n the number of picks:
+//   IS          (1/n) sum_i w_i T_i                                   Eq. (6)
+//   MIS         sum_i f_c(x_i) T_i / sum_j p_j(x_i)   (balance heuristic, n^2 PMFs)
+//   pairwise    sum_i m_i(x_i) w_i T_i, canonical c:  (2n PMFs)
+//     m_i(x) = p_i(x) / ((n-1) p_i(x) + p_c(x)),  m_c(x) = 1/(n-1) sum_{i!=c} p_c(x) / (p_c(x) + (n-1) p_i(x))
+//   regression  (1/n) sum_i [w_i T_i - beta (w_i - 1)],
+//     beta = sum_i (w_i - wbar) w_i T_i / sum_i (w_i - wbar)^2   (0 when all w_i are equal)   Eq. (7)
+//   WIS         Eq. (14) written out plainly (used for its clamped form)
+// Clamping limits the result per channel to the range of the texels with
+// f_c(x_i) > 0. One wave per tile; each lane publishes its pick, PMF,
+// support start, per-axis weights and decoded texel in LDS and every pixel
+// walks its members. Comparison only: not the optimised path.
+
+template <int N>
+struct PickRecord {                  // LDS record of one lane, 16-byte aligned
+    uint32_t s;                      // texel sx | sy << 16
+    float p;                         // own PMF at the pick; 0 for off-screen pixels
+    int bx, by;                      // support start
+    float T[4];
+    float wx[N], wy[N];
+};
+
+template <int N>
+__device__ __forceinline__ float pmf_at(const PickRecord<N>& r, uint32_t s, uint32_t mx, uint32_t my) {
+    uint32_t dx, dy;
+    if (!support_offset<N>(s, r.bx, r.by, mx, my, dx, dy)) return 0.0f;
+    return r.wx[dx] * r.wy[dy];
+}
+
+// Texel of any non-latent format as four floats (zero-padded).
+__device__ __forceinline__ void texel_f4(const TexArg& t, uint4 raw, float* T) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) T[c] = 0.0f;
+    switch (payload_of(t.fmt)) {
+    case kF16x4: { const Texel<kF16x4> x = decode<kF16x4>(raw, t.fmt); for (int c = 0; c < 4; ++c) T[c] = x.ch(c); break; }
+    case kF16x2: { const Texel<kF16x2> x = decode<kF16x2>(raw, t.fmt); T[0] = x.ch(0); T[1] = x.ch(1); break; }
+    case kF32x1: { const Texel<kF32x1> x = decode<kF32x1>(raw, t.fmt); T[0] = x.ch(0); break; }
+    default: { const Texel<kF32x4> x = decode<kF32x4>(raw, t.fmt); for (int c = 0; c < 4; ++c) T[c] = x.ch(c); break; }
+    }
+}
+
+template <int FILT>
+__device__ __forceinline__ void estimator_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
+                                               uint32_t hx, uint32_t hy, float* lds) {
+    constexpr int N = SelCtx<FILT>::N;
+    const TexArg t = a.tex[slot];
+    const uint32_t mx = (uint32_t)t.w - 1u, my = (uint32_t)t.h - 1u;
+    const SlotPick pk = pick_slot<FILT>(t, ctx, hx, hy);
+    PickRecord<N>* rec = reinterpret_cast<PickRecord<N>*>(lds);
+    PickRecord<N> mine;
+    mine.s = pk.sx | (pk.sy << 16);
+    mine.p = P.valid ? ctx.x.wsel(pk.kx) * ctx.y.wsel(pk.ky) : 0.0f;
+    mine.bx = ctx.x.base;
+    mine.by = ctx.y.base;
+    texel_f4(t, block_texel(pk.raw, pk.sx, format_bytes(t.fmt)), mine.T);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        mine.wx[i] = ctx.x.w(i);
+        mine.wy[i] = ctx.y.w(i);
+    }
+    const int64_t pix = (int64_t)P.py * a.sw + P.px;
+    if (a.sel != nullptr && P.valid) {
+        int2* sp = reinterpret_cast<int2*>(a.sel) + ((int64_t)slot * a.sh * a.sw + pix);
+        *sp = make_int2((int)pk.sx, (int)pk.sy);
+    }
+    rec[P.q] = mine;
+    wave_lds_sync();
+
+    const int fp = a.footprint;
+    const int K = fp == STF_FP_SELF ? 0 : footprint_size(fp, a.lut_k);
+    const int est = a.estimator;
+    // member iteration: the pixel itself first, then the others
+    auto member = [&](int m) -> int {                     // m = -1: the pixel itself; -2: skip
+        if (m < 0) return P.q;
+        const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
+        return j == P.q ? -2 : j;
+    };
+    // pass 1: n, sum of w, clamp range
+    float n = 0.0f, sw = 0.0f;
+    float lo[4], hi[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        lo[c] = __builtin_huge_valf();
+        hi[c] = -__builtin_huge_valf();
+    }
+    for (int m = -1; m < K; ++m) {
+        const int j = member(m);
+        if (j < 0) continue;
+        const PickRecord<N>& r = rec[j];
+        if (r.p == 0.0f) continue;                        // off-screen member
+        n += 1.0f;
+        uint32_t dx, dy;
+        if (support_offset<N>(r.s, ctx.x.base, ctx.y.base, mx, my, dx, dy)) {
+            const float f = ctx.x.wsel(dx) * ctx.y.wsel(dy);
+            sw += f / r.p;
+            if (f > 0.0f) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    lo[c] = fminf(lo[c], r.T[c]);
+                    hi[c] = fmaxf(hi[c], r.T[c]);
+                }
+            }
+        }
+    }
+    const float wbar = sw / fmaxf(n, 1.0f);
+    const float nm1 = fmaxf(n - 1.0f, 1.0f);
+    // pairwise MIS: canonical weight m_c(x_c)
+    float m_c = 1.0f;
+    if (est == STF_EST_PAIRWISE_MIS && n > 1.0f) {
+        m_c = 0.0f;
+        for (int m = 0; m < K; ++m) {
+            const int j = member(m);
+            if (j < 0 || rec[j].p == 0.0f) continue;
+            m_c += mine.p / (mine.p + nm1 * pmf_at<N>(rec[j], mine.s, mx, my));
+        }
+        m_c /= nm1;
+    }
+    // pass 2
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    float dw2 = 0.0f, cv = 0.0f;
+    float dwt[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int m = -1; m < K; ++m) {
+        const int j = member(m);
+        if (j < 0) continue;
+        const PickRecord<N>& r = rec[j];
+        if (r.p == 0.0f) continue;
+        uint32_t dx, dy;
+        const float f = support_offset<N>(r.s, ctx.x.base, ctx.y.base, mx, my, dx, dy)
+                            ? ctx.x.wsel(dx) * ctx.y.wsel(dy) : 0.0f;
+        const float w = f / r.p;
+        float coef;
+        switch (est) {
+        case STF_EST_IS: coef = w; break;
+        case STF_EST_MIS: {
+            float den = 0.0f;                              // sum over all members k of p_k(x_i)
+            for (int mm = -1; mm < K; ++mm) {
+                const int k = member(mm);
+                if (k < 0 || rec[k].p == 0.0f) continue;
+                den += pmf_at<N>(rec[k], r.s, mx, my);
+            }
+            coef = f / den;                                // den >= p_i(x_i) > 0
+            break;
+        }
+        case STF_EST_PAIRWISE_MIS:
+            coef = (m < 0 ? m_c : r.p / (nm1 * r.p + f)) * w;
+            break;
+        case STF_EST_REGRESSION: {
+            const float d = w - wbar;
+            dw2 = fmaf(d, d, dw2);
+            cv += w - 1.0f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) dwt[c] = fmaf(d * w, r.T[c], dwt[c]);
+            coef = w;
+            break;
+        }
+        default: coef = w; break;                          // WIS numerator
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = fmaf(coef, r.T[c], acc[c]);
+    }
+    float o[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        switch (est) {
+        case STF_EST_IS: o[c] = acc[c] / n; break;
+        case STF_EST_MIS: case STF_EST_PAIRWISE_MIS: o[c] = acc[c]; break;
+        case STF_EST_REGRESSION: {
+            const float beta = dw2 > 0.0f ? dwt[c] / dw2 : 0.0f;
+            o[c] = fmaf(-beta, cv, acc[c]) / n;
+            break;
+        }
+        default: o[c] = acc[c] / sw; break;
+        }
+        if (a.flags & STF_REUSE_CLAMP) o[c] = fminf(fmaxf(o[c], lo[c]), hi[c]);
+        if (t.has_scale) o[c] *= t.scale[c];
+    }
+    wave_lds_sync();                                       // records read before the next slot
+    if (P.valid) {
+        switch (t.ch) {
+        case 4: store_out<4>(a.out[slot], pix, o); break;
+        case 2: store_out<2>(a.out[slot], pix, o); break;
+        default: store_out<1>(a.out[slot], pix, o); break;
+        }
+    }
+}
+
+template <int FILT>
+__global__ __launch_bounds__(kThreads) void estimator_kernel(Args a) {
+    __shared__ __align__(16) float lds_all[kWavesPerGroup * kLdsFloatsPerWave];
+    static_assert(64 * sizeof(PickRecord<SelCtx<FILT>::N>) <= kLdsFloatsPerWave * sizeof(float),
+                  "pick records exceed the wave's LDS");
+    Pixel P;
+    if (!setup_pixel(a, P)) return;
+    float* lds = lds_all + (threadIdx.x >> 6) * kLdsFloatsPerWave;
+    SelCtx<FILT> ctx;
+    uint4 hq;
+    for (int slot = 0; slot < a.ntex; ++slot) {
+        uint32_t hx, hy;
+        slot_uniforms(a, P, slot, hq, hx, hy);
+        ctx.update(P, a.tex[slot].w, a.tex[slot].h);
+        estimator_slot<FILT>(a, slot, P, ctx, hx, hy, lds);
+    }
+}
+
 // Deterministic filter, Eq. (3): sum over the support of f_c * T.
 template <int FILT, int PL, bool LAT = false>
 __device__ __forceinline__ void reference_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
@@ -1155,8 +1364,12 @@ int check_reuse(const stf_reuse* r) {
         if (r->lut == nullptr) return fail(STF_EINVAL, "footprint LUT requires a lut pointer");
         if (r->lut_k < 1 || r->lut_k > 64) return fail(STF_EINVAL, "lut_k=%d outside 1..64", r->lut_k);
     }
-    if ((r->flags & ~STF_REUSE_EXACT_FILTERING) != 0) return fail(STF_EINVAL, "unknown reuse flags 0x%x", r->flags);
-    if (r->reserved != 0) return fail(STF_EINVAL, "reuse reserved field must be 0");
+    if ((r->flags & ~(STF_REUSE_EXACT_FILTERING | STF_REUSE_CLAMP)) != 0)
+        return fail(STF_EINVAL, "unknown reuse flags 0x%x", r->flags);
+    if (r->estimator < STF_EST_WIS || r->estimator > STF_EST_REGRESSION)
+        return fail(STF_EINVAL, "unknown estimator %d", r->estimator);
+    if ((r->flags & STF_REUSE_EXACT_FILTERING) && (r->estimator != STF_EST_WIS || (r->flags & STF_REUSE_CLAMP)))
+        return fail(STF_EUNSUPPORTED, "exact filtering combines with the plain Eq. (14) estimator only");
     return STF_OK;
 }
 
@@ -1220,6 +1433,13 @@ int forward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const s
     a.sel = sel;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const bool cubic = p->filter == STF_BICUBIC_BSPLINE;
+    if (r != nullptr && (r->estimator != STF_EST_WIS || (r->flags & STF_REUSE_CLAMP))) {
+        if (a.dec != nullptr) return fail(STF_EUNSUPPORTED, "comparison estimators do not decode latent textures");
+        a.estimator = r->estimator;
+        if (cubic) hipLaunchKernelGGL((stf::estimator_kernel<1>), grid_of(a), dim3(stf::kThreads), 0, s, a);
+        else hipLaunchKernelGGL((stf::estimator_kernel<0>), grid_of(a), dim3(stf::kThreads), 0, s, a);
+        return finish_launch("estimator");
+    }
     switch (mode) {
     case stf::kModeStf: cubic ? launch_forward<1, stf::kModeStf>(a, s) : launch_forward<0, stf::kModeStf>(a, s); break;
     case stf::kModeQuad: cubic ? launch_forward<1, stf::kModeQuad>(a, s) : launch_forward<0, stf::kModeQuad>(a, s); break;
@@ -1290,8 +1510,8 @@ int stf_backward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, co
     int rc = prepare(tex, ntex, scr, p, false, a);
     if (rc != STF_OK) return rc;
     if ((rc = check_reuse(r)) != STF_OK) return rc;
-    if (r->flags & STF_REUSE_EXACT_FILTERING)
-        return fail(STF_EUNSUPPORTED, "the adjoint does not cover exact filtering");
+    if (r->flags & (STF_REUSE_EXACT_FILTERING | STF_REUSE_CLAMP) || r->estimator != STF_EST_WIS)
+        return fail(STF_EUNSUPPORTED, "the adjoint covers the plain Eq. (14) estimator only");
     if (dout == nullptr || dtex == nullptr) return fail(STF_EINVAL, "dout/dtex arrays are null");
     for (int i = 0; i < ntex; ++i) {
         if (dout[i] == nullptr || dtex[i] == nullptr) return fail(STF_EINVAL, "dout[%d]/dtex[%d] is null", i, i);

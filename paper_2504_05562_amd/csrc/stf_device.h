@@ -43,7 +43,7 @@ struct Args {
     int32_t* sel;
     const uint8_t* lut;
     const uint8_t* dec;      // packed latent decoder (device), shared by the latent textures
-    int32_t ntex, sw, sh, lut_k, footprint, flags;
+    int32_t ntex, sw, sh, lut_k, footprint, flags, estimator;
     uint32_t seed, frame;
 };
 

@@ -90,10 +90,15 @@ def test_validation_counts_and_nulls():
     bad_fp = stf.Reuse(42, 0, None)
     out = (ctypes.c_void_p * 1)(4096)
     assert lib.stf_filter_reuse(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(bad_fp), out, None, None) == -1
-    bad_flags = stf.Reuse(5, 0, None, 2, 0)
+    bad_flags = stf.Reuse(5, 0, None, 4, 0)
     assert lib.stf_filter_reuse(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(bad_flags), out, None, None) == -1
-    bad_res = stf.Reuse(5, 0, None, 1, 7)
-    assert lib.stf_filter_reuse(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(bad_res), out, None, None) == -1
+    bad_est = stf.Reuse(5, 0, None, 0, 7)
+    assert lib.stf_filter_reuse(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(bad_est), out, None, None) == -1
+    ef_is = stf.Reuse(5, 0, None, 1, 1)
+    assert lib.stf_filter_reuse(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(ef_is), out, None, None) == -2
+    clamp_bwd = stf.Reuse(5, 0, None, 2, 0)
+    dq = (ctypes.c_void_p * 1)(4096)
+    assert lib.stf_backward(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(clamp_bwd), dq, dq, None) == -2
     ef = stf.Reuse(5, 0, None, 1, 0)
     dp = (ctypes.c_void_p * 1)(4096)
     assert lib.stf_backward(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(ef), dp, dp, None) == -2
