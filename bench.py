@@ -30,7 +30,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpixel/s filtered (reuse vs 1-sample STF) @1080p bicubic, %HBM peak, PSNR dB"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2504_05562_amd/csrc/stf.hip", "paper_2504_05562_amd/csrc/stf_device.h"]
+KERNEL_SOURCES = ["paper_2504_05562_amd/csrc/stf.hip", "paper_2504_05562_amd/csrc/stf_device.h",
+                  "paper_2504_05562_amd/csrc/stf_decoder.h"]
+BENCH_KERNEL = "forward_kernel<1, 3, 2, false, false>"     # bicubic, whole-tile bins, 2 textures
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "reuse_tile8x8_plane1080p_traffic.json")
 
 
@@ -69,7 +71,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str, out_path: str = TRAFFIC_FILE) 
                 if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= 131072]
         big = max(copy)
         ref = [v for v in copy if v > 0.9 * big]
-        kern = [float(r["Counter_Value"]) for r in rows if "forward_kernel<1, 3, 2>" in r["Kernel_Name"]]
+        kern = [float(r["Counter_Value"]) for r in rows if BENCH_KERNEL in r["Kernel_Name"]]
         return sum(ref) / len(ref), kern
 
     f_copy, f_k = per_kernel(fetch_csv, "FETCH_SIZE")

@@ -1134,19 +1134,23 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                     const uint32_t eq = wave_max(__float_as_uint(gmax) >> 23) + 1u;
                     if (P.valid) {
                         const float inv = fast_rcp(B);
+                        // lanes visit their support in rotated orders, so one atomic
+                        // instruction mostly hits N*N different bins even where every
+                        // pixel of the tile has the same support (high magnification)
+                        const int rot = lane % (N * N);
 #pragma unroll
-                        for (int b = 0; b < N; ++b)
+                        for (int k = 0; k < N * N; ++k) {
+                            const int kk = (k + rot) % (N * N);
+                            const int aa = kk % N, b = kk / N;
+                            const int idx = bin0 + b * kBinG + aa;
+                            if (Nb[idx] != 0.0f) {
+                                const float f = ctx.x.wsel((uint32_t)aa) * ctx.y.wsel((uint32_t)b) * inv;
 #pragma unroll
-                            for (int aa = 0; aa < N; ++aa) {
-                                const int idx = bin0 + b * kBinG + aa;
-                                if (Nb[idx] != 0.0f) {
-                                    const float f = ctx.wxy[b * N + aa] * inv;
-#pragma unroll
-                                    for (int c = 0; c < C; ++c)
-                                        atomicAdd(reinterpret_cast<unsigned long long*>(&Q64[idx * C + c]),
-                                                  (unsigned long long)signed_fixed_of(f * g[c], eq));
-                                }
+                                for (int c = 0; c < C; ++c)
+                                    atomicAdd(reinterpret_cast<unsigned long long*>(&Q64[idx * C + c]),
+                                              (unsigned long long)signed_fixed_of(f * g[c], eq));
                             }
+                        }
                     }
                     wave_lds_sync();
                     // flush: lane handles bins lane, lane + 64, ...
