@@ -116,11 +116,21 @@ typedef struct stf_screen {
     int32_t height;         /* pixels, 1..STF_MAX_SCREEN */
 } stf_screen;
 
+/* Shared selection (Sec. 4.5: textures with the same UV and resolution can
+ * share one selection loop): every slot uses the random numbers, hence the
+ * texel positions, of the first slot of the same texture size. Each slot's
+ * output is still a reuse estimate of that texture; their errors become
+ * correlated. */
+#define STF_SHARE_SELECTION 1
+
 typedef struct stf_params {
     int32_t filter;         /* stf_filter_kind */
     int32_t address;        /* stf_address */
-    uint32_t seed;          /* random stream: pcg4d(px, py, frame, seed + (slot>>1)*0x9E3779B9) */
+    uint32_t seed;          /* random stream: pcg4d(px, py, frame, seed + (k>>1)*0x9E3779B9), k the slot
+                               (or with STF_SHARE_SELECTION the first slot of the same size) */
     uint32_t frame;
+    int32_t flags;          /* 0 or STF_SHARE_SELECTION */
+    int32_t reserved;       /* must be 0 */
 } stf_params;
 
 /* Exact filtering (Sec. 4.2): a pixel whose footprint's picks include every

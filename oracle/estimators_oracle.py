@@ -57,7 +57,7 @@ def _weight_of(s: dict, pix: np.ndarray, sx: np.ndarray, sy: np.ndarray) -> np.n
 
 
 def stf_filter_estimator(textures, uv, filt, seed, frame, footprint, estimator, clamp=False, lut=None,
-                         tiles=None, diagnostics=None):
+                         tiles=None, diagnostics=None, share_selection=False):
     """Per slot (values [n, 64, C], selections [n, 64, 2]) of the comparison
     estimator `estimator` over the footprint's shared samples.
 
@@ -67,16 +67,18 @@ def stf_filter_estimator(textures, uv, filt, seed, frame, footprint, estimator, 
     regression estimator, sum (w_i - wbar)^2 / sum w_i^2, the conditioning of
     beta; 1 otherwise)."""
     if estimator == "wis" and not clamp and diagnostics is None:
-        return so.stf_filter_reuse(textures, uv, filt, seed, frame, footprint, lut=lut, tiles=tiles)
+        return so.stf_filter_reuse(textures, uv, filt, seed, frame, footprint, lut=lut, tiles=tiles,
+                                   share_selection=share_selection)
     if estimator not in ESTIMATORS:
         raise ValueError(estimator)
     if tiles is None:
         tiles = so.all_tiles(uv.shape[1], uv.shape[0])
     members = so.footprint_members(footprint, lut)
     K = members.shape[1]
+    keys = so.selection_slots(textures, share_selection)
     out = []
     for slot, tex in enumerate(textures):
-        s = so.stf_samples(tex, uv, tiles, slot, filt, seed, frame)
+        s = so.stf_samples(tex, uv, tiles, keys[slot], filt, seed, frame)
         ntile = s["p"].shape[0]
         own = np.tile(np.arange(64)[None, :], (ntile, 1))
         # member tables [ntile, 64, K]

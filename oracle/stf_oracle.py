@@ -32,7 +32,7 @@ __all__ = [
     "stf_filter", "stf_filter_reuse", "reference_filter", "stf_adjoint",
     "tiles_to_image", "all_tiles", "psnr",
     "fp8e4m3_value", "bf16_value", "dequantize", "mlp_decode", "decode_latent_texture",
-    "texture_values",
+    "texture_values", "selection_slots",
 ]
 
 BILINEAR = "bilinear"
@@ -360,6 +360,20 @@ def _texture_scale(tex, channels: int) -> np.ndarray:
 # one-tap STF samples for a batch of tiles
 # --------------------------------------------------------------------------
 
+def selection_slots(textures, share_selection: bool) -> list:
+    """Slot whose random numbers each slot uses: itself, or with shared
+    selection (Sec. 4.5: textures of the same UV and resolution may share
+    one selection) the first slot of the same texture size."""
+    keys = []
+    sizes = [texture_values(t).shape[:2] for t in textures] if share_selection else None
+    for i in range(len(textures)):
+        k = i
+        if share_selection:
+            k = next(j for j in range(i + 1) if sizes[j] == sizes[i])
+        keys.append(k)
+    return keys
+
+
 def stf_samples(tex: np.ndarray, uv: np.ndarray, tiles: np.ndarray, slot: int,
                 filt: str, seed: int, frame: int) -> dict:
     """Per pixel of each tile: own coordinate split, own per-axis weights,
@@ -397,14 +411,15 @@ def stf_samples(tex: np.ndarray, uv: np.ndarray, tiles: np.ndarray, slot: int,
                 kx=kx, ky=ky, sx=sx, sy=sy, p=p, T=T, delta=delta, tw=tw, th=th)
 
 
-def stf_filter(textures, uv, filt, seed, frame, tiles=None):
+def stf_filter(textures, uv, filt, seed, frame, tiles=None, share_selection=False):
     """One-tap STF (Sec. 2.2): each pixel returns its one sampled texel.
     Returns per slot (values [n, 64, C], selections [n, 64, 2] as (x, y))."""
     if tiles is None:
         tiles = all_tiles(uv.shape[1], uv.shape[0])
+    keys = selection_slots(textures, share_selection)
     out = []
     for slot, tex in enumerate(textures):
-        s = stf_samples(tex, uv, tiles, slot, filt, seed, frame)
+        s = stf_samples(tex, uv, tiles, keys[slot], filt, seed, frame)
         out.append((s["T"], np.stack([s["sx"], s["sy"]], -1)))
     return out
 
@@ -429,7 +444,8 @@ def _own_weight_at(s: dict, sx_i: np.ndarray, sy_i: np.ndarray):
     return np.where(inside, f, 0.0), inside
 
 
-def stf_filter_reuse(textures, uv, filt, seed, frame, footprint, lut=None, tiles=None, exact_filtering=False):
+def stf_filter_reuse(textures, uv, filt, seed, frame, footprint, lut=None, tiles=None, exact_filtering=False,
+                     share_selection=False):
     """STF with sample reuse (Sec. 4), per slot.
 
     Pixel c combines the samples of the members i of its sharing footprint
@@ -449,9 +465,10 @@ def stf_filter_reuse(textures, uv, filt, seed, frame, footprint, lut=None, tiles
     if tiles is None:
         tiles = all_tiles(uv.shape[1], uv.shape[0])
     members = footprint_members(footprint, lut)
+    keys = selection_slots(textures, share_selection)
     out = []
     for slot, tex in enumerate(textures):
-        s = stf_samples(tex, uv, tiles, slot, filt, seed, frame)
+        s = stf_samples(tex, uv, tiles, keys[slot], filt, seed, frame)
         C = s["T"].shape[-1]
         n_sup = s["wx"].shape[-1]
         seen = np.zeros(s["p"].shape + (n_sup, n_sup), dtype=bool)      # [tile, pixel, dy, dx]
@@ -524,7 +541,7 @@ def reference_filter(textures, uv, filt, tiles=None):
 # adjoint of Eq. (14) with respect to the texels
 # --------------------------------------------------------------------------
 
-def stf_adjoint(textures, uv, filt, seed, frame, footprint, grads, lut=None, tiles=None):
+def stf_adjoint(textures, uv, filt, seed, frame, footprint, grads, lut=None, tiles=None, share_selection=False):
     """Gradient of L with respect to every texel, given dL/dout per pixel.
 
     The weights of Eq. (14) depend only on positions and random numbers, so
@@ -536,9 +553,10 @@ def stf_adjoint(textures, uv, filt, seed, frame, footprint, grads, lut=None, til
     if tiles is None:
         tiles = all_tiles(uv.shape[1], uv.shape[0])
     members = footprint_members(footprint, lut)
+    keys = selection_slots(textures, share_selection)
     res = []
     for slot, (tex, g) in enumerate(zip(textures, grads)):
-        s = stf_samples(tex, uv, tiles, slot, filt, seed, frame)
+        s = stf_samples(tex, uv, tiles, keys[slot], filt, seed, frame)
         C = s["T"].shape[-1]
         ws, ids = [], []
         den = np.zeros(s["p"].shape)

@@ -73,7 +73,11 @@ class Screen(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("filter", ctypes.c_int32), ("address", ctypes.c_int32),
-                ("seed", ctypes.c_uint32), ("frame", ctypes.c_uint32)]
+                ("seed", ctypes.c_uint32), ("frame", ctypes.c_uint32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+SHARE_SELECTION = 1
 
 
 class Reuse(ctypes.Structure):
@@ -242,9 +246,10 @@ def _screen(uv):
     return Screen(uv.data_ptr(), int(uv.shape[1]), int(uv.shape[0]))
 
 
-def _params(filter, seed, frame):
+def _params(filter, seed, frame, share_selection=False):
     f = FILTERS[filter] if isinstance(filter, str) else int(filter)
-    return Params(f, 0, int(seed) & 0xFFFFFFFF, int(frame) & 0xFFFFFFFF)
+    return Params(f, 0, int(seed) & 0xFFFFFFFF, int(frame) & 0xFFFFFFFF,
+                  SHARE_SELECTION if share_selection else 0, 0)
 
 
 def _outputs(uv, chans, out=None):
@@ -267,7 +272,8 @@ def _reuse(footprint, lut, exact_filtering=False, estimator="wis", clamp=False):
     return Reuse(fp, int(lut.shape[1]), lut.data_ptr(), flags, est)
 
 
-def filter(textures, uv, filter="bicubic", seed=0, frame=0, sel=False, out=None, stream=None, scales=None, decoder=None):
+def filter(textures, uv, filter="bicubic", seed=0, frame=0, sel=False, out=None, stream=None, scales=None, decoder=None,
+           share_selection=False):
     """One-tap STF (stf_filter). Returns a list of outputs, plus the int32
     selection tensor [ntex, H, W, 2] if sel=True. `scales` holds, per
     texture, None or one dequantization scale per channel."""
@@ -275,7 +281,7 @@ def filter(textures, uv, filter="bicubic", seed=0, frame=0, sel=False, out=None,
     lib = library()
     descs, chans, _keep = _texture_descs(textures, scales=scales, decoder=decoder)
     scr = _screen(uv)
-    prm = _params(filter, seed, frame)
+    prm = _params(filter, seed, frame, share_selection)
     out, ptrs = _outputs(uv, chans, out)
     s = torch.empty((len(textures),) + tuple(uv.shape[:2]) + (2,), dtype=torch.int32, device=uv.device) if sel else None
     _check(lib.stf_filter(descs, len(textures), ctypes.byref(scr), ctypes.byref(prm), ptrs,
@@ -285,7 +291,7 @@ def filter(textures, uv, filter="bicubic", seed=0, frame=0, sel=False, out=None,
 
 def filter_reuse(textures, uv, footprint="tile8x8", filter="bicubic", seed=0, frame=0, lut=None,
                  sel=False, out=None, stream=None, scales=None, decoder=None, exact_filtering=False,
-                 estimator="wis", clamp=False):
+                 estimator="wis", clamp=False, share_selection=False):
     """STF with sample reuse (stf_filter_reuse). `lut` is a uint8 GPU tensor
     [64, K] of tile pixel ids for footprint='lut'; exact_filtering selects
     STF_REUSE_EXACT_FILTERING; estimator ('wis' = Eq. (14), 'is', 'mis',
@@ -294,7 +300,7 @@ def filter_reuse(textures, uv, footprint="tile8x8", filter="bicubic", seed=0, fr
     lib = library()
     descs, chans, _keep = _texture_descs(textures, scales=scales, decoder=decoder)
     scr = _screen(uv)
-    prm = _params(filter, seed, frame)
+    prm = _params(filter, seed, frame, share_selection)
     r = _reuse(footprint, lut, exact_filtering, estimator, clamp)
     out, ptrs = _outputs(uv, chans, out)
     s = torch.empty((len(textures),) + tuple(uv.shape[:2]) + (2,), dtype=torch.int32, device=uv.device) if sel else None
@@ -316,14 +322,14 @@ def filter_reference(textures, uv, filter="bicubic", out=None, stream=None, scal
 
 
 def backward(textures, uv, grads, footprint="tile8x8", filter="bicubic", seed=0, frame=0, lut=None,
-             dtex=None, stream=None, scales=None):
+             dtex=None, stream=None, scales=None, share_selection=False):
     """Adjoint of filter_reuse (stf_backward): accumulates dL/dT into `dtex`
     (float32 [H_t, W_t, C] per texture; zero-initialised if not given)."""
     import torch
     lib = library()
     descs, chans, _keep = _texture_descs(textures, scales=scales)
     scr = _screen(uv)
-    prm = _params(filter, seed, frame)
+    prm = _params(filter, seed, frame, share_selection)
     r = _reuse(footprint, lut)
     if dtex is None:
         dtex = [torch.zeros((int(t.shape[0]), int(t.shape[1]), c), dtype=torch.float32, device=uv.device)

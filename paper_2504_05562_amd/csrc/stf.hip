@@ -653,6 +653,16 @@ __device__ __forceinline__ bool setup_pixel(const Args& a, Pixel& P) {
     return true;
 }
 
+// Random numbers of the slot whose selection slot `slot` uses (itself, or
+// with shared selection the first slot of the same texture size), computed
+// on their own.
+__device__ __forceinline__ void keyed_uniforms(const Args& a, const Pixel& P, int slot, uint32_t& hx, uint32_t& hy) {
+    const int key = a.leader[slot];
+    const uint4 h = pcg4d(make_uint4((uint32_t)P.px, (uint32_t)P.py, a.frame, a.seed + (uint32_t)(key >> 1) * kGolden));
+    hx = (key & 1) ? h.z : h.x;
+    hy = (key & 1) ? h.w : h.y;
+}
+
 // Random numbers of texture slot `slot`: slots 2q and 2q+1 share one pcg4d
 // evaluation keyed with seed + q * golden (first / last two outputs).
 __device__ __forceinline__ void slot_uniforms(const Args& a, const Pixel& P, int slot, uint4& hq, uint32_t& hx,
@@ -697,7 +707,14 @@ __global__ __launch_bounds__(kThreads) void forward_kernel(Args a) {
         uint32_t hx, hy;
         slot_uniforms(a, P, i, hq, hx, hy);
         ctx.update(P, t[i].w, t[i].h);
-        pk[i] = pick_slot<FILT>(t[i], ctx, hx, hy);
+        if (a.leader[i] == i) {
+            pk[i] = pick_slot<FILT>(t[i], ctx, hx, hy);
+        } else {                               // shared selection: the leader's texel of this texture
+#pragma unroll
+            for (int j = 0; j < i; ++j)
+                if (a.leader[i] == j) pk[i] = pk[j];
+            pk[i].raw = fetch_block(t[i], pk[i].sx, pk[i].sy, format_bytes(t[i].fmt));
+        }
     }
     BinGeom<AxisCtx<FILT>::N> geom;
 #pragma unroll
@@ -916,10 +933,9 @@ __global__ __launch_bounds__(kThreads) void estimator_kernel(Args a) {
     if (!setup_pixel(a, P)) return;
     float* lds = lds_all + (threadIdx.x >> 6) * kLdsFloatsPerWave;
     SelCtx<FILT> ctx;
-    uint4 hq;
     for (int slot = 0; slot < a.ntex; ++slot) {
         uint32_t hx, hy;
-        slot_uniforms(a, P, slot, hq, hx, hy);
+        keyed_uniforms(a, P, slot, hx, hy);
         ctx.update(P, a.tex[slot].w, a.tex[slot].h);
         estimator_slot<FILT>(a, slot, P, ctx, hx, hy, lds);
     }
@@ -1210,10 +1226,9 @@ __global__ __launch_bounds__(kThreads) void backward_kernel(Args a) {
     if (!setup_pixel(a, P)) return;
     float* lds = lds_all + (threadIdx.x >> 6) * kPerWave;
     SelCtx<FILT> ctx;
-    uint4 hq;
     for (int slot = 0; slot < a.ntex; ++slot) {
         uint32_t hx, hy;
-        slot_uniforms(a, P, slot, hq, hx, hy);
+        keyed_uniforms(a, P, slot, hx, hy);
         ctx.update(P, a.tex[slot].w, a.tex[slot].h);
         const int ch = a.tex[slot].ch;
         if (ch == 4) backward_slot<FILT, MODE, 4>(a, slot, P, ctx, hx, hy, lds);
@@ -1348,6 +1363,17 @@ int prepare(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const s
     a.sh = scr->height;
     a.seed = p->seed;
     a.frame = p->frame;
+    if ((p->flags & ~STF_SHARE_SELECTION) != 0) return fail(STF_EINVAL, "unknown params flags 0x%x", p->flags);
+    if (p->reserved != 0) return fail(STF_EINVAL, "params reserved field must be 0");
+    for (int i = 0; i < ntex; ++i) {
+        a.leader[i] = i;
+        if (p->flags & STF_SHARE_SELECTION)
+            for (int j = 0; j < i; ++j)
+                if (tex[j].width == tex[i].width && tex[j].height == tex[i].height) {
+                    a.leader[i] = j;
+                    break;
+                }
+    }
     return STF_OK;
 }
 

@@ -44,6 +44,7 @@ struct Args {
     const uint8_t* lut;
     const uint8_t* dec;      // packed latent decoder (device), shared by the latent textures
     int32_t ntex, sw, sh, lut_k, footprint, flags, estimator;
+    int32_t leader[STF_MAX_TEXTURES];   // slot whose selection each slot uses
     uint32_t seed, frame;
 };
 

@@ -146,3 +146,12 @@ def test_footprint_generator_validation():
     assert b"workspace" in lib.stf_last_error()
     assert lib.stf_footprint_generate(ctypes.byref(good), ctypes.c_void_p(4096 + 64), n, ctypes.c_void_p(4096),
                                       None, None) == -1
+
+
+def test_params_layout_and_flags():
+    assert ctypes.sizeof(stf.Params) == 24
+    tex, scr, prm = _good()
+    prm.flags = 2
+    assert _call_filter(tex, 1, ctypes.byref(scr), ctypes.byref(prm)) == -1
+    prm.flags, prm.reserved = 1, 3
+    assert _call_filter(tex, 1, ctypes.byref(scr), ctypes.byref(prm)) == -1

@@ -1,0 +1,79 @@
+"""Shared selection (Sec. 4.5; STF_SHARE_SELECTION) on the GPU against the
+oracle: every slot uses the picks of the first slot of its texture size.
+Selection bit-exact; colours within 1e-5 relative (as the other parity
+tests); the adjoint and the comparison estimators follow the same picks."""
+import numpy as np
+import pytest
+
+import oracle as o
+from oracle import estimators_oracle as eo
+import workloads as w
+
+torch = pytest.importorskip("torch")
+stf = pytest.importorskip("paper_2504_05562_amd")
+
+pytestmark = pytest.mark.gpu
+REL = 1e-5
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def image(vals, uv):
+    return o.tiles_to_image(vals, o.all_tiles(uv.shape[1], uv.shape[0]), uv.shape[1], uv.shape[0])
+
+
+def textures():
+    rng = np.random.default_rng(12)
+    return [rng.random((64, 64, 4)).astype(np.float16), (rng.random((64, 64, 2)) * 2 - 1).astype(np.float16),
+            rng.integers(0, 256, (32, 32, 1), dtype=np.uint8), rng.random((64, 64, 4)).astype(np.float32)]
+
+
+def close(got, want, tex, uv, filt):
+    T = np.abs(o.texture_values(tex))
+    scale = np.full(want.shape, T.max())
+    tol = REL * np.maximum(np.abs(want), scale) + 1e-30
+    return np.all(np.abs(got.astype(np.float64) - want) <= tol)
+
+
+@pytest.mark.parametrize("fp", [None, "quad2x2", "square3x3", "tile8x8"])
+@pytest.mark.parametrize("filt", ["bilinear", "bicubic"])
+def test_shared_selection_parity(fp, filt):
+    texs = textures()
+    uv = w.small_screen(88, 56, 64, 5.0, offset_seed=8)
+    ftag = o.BICUBIC if filt == "bicubic" else o.BILINEAR
+    dt, duv = [dev(t) for t in texs], dev(uv)
+    if fp is None:
+        outs, sel = stf.filter(dt, duv, filt, 6, 2, sel=True, share_selection=True)
+        ref = o.stf_filter(texs, uv, ftag, 6, 2, share_selection=True)
+    else:
+        outs, sel = stf.filter_reuse(dt, duv, fp, filt, 6, 2, sel=True, share_selection=True)
+        ref = o.stf_filter_reuse(texs, uv, ftag, 6, 2, fp, share_selection=True)
+    s = sel.cpu().numpy()
+    assert np.array_equal(s[0], s[1]) and np.array_equal(s[0], s[3])
+    for k, (tex, (rv, rs)) in enumerate(zip(texs, ref)):
+        assert np.array_equal(s[k], image(rs, uv)), k
+        assert close(outs[k].cpu().numpy(), image(rv, uv), tex, uv, ftag), k
+
+
+def test_shared_selection_adjoint_and_estimators():
+    texs = textures()[:2]
+    uv = w.small_screen(48, 40, 64, 4.0, offset_seed=1)
+    H, W = uv.shape[:2]
+    rng = np.random.default_rng(3)
+    grads = [rng.standard_normal((H, W, t.shape[2])).astype(np.float32) for t in texs]
+    got = stf.backward([dev(t) for t in texs], dev(uv), [dev(g) for g in grads], "tile8x8", "bicubic", 4, 0,
+                       share_selection=True)
+    tiles = o.all_tiles(W, H)
+    px = tiles[:, 0:1] * 8 + (np.arange(64) % 8)[None]
+    py = tiles[:, 1:2] * 8 + (np.arange(64) // 8)[None]
+    gt = [g[np.minimum(py, H - 1), np.minimum(px, W - 1)] * ((px < W) & (py < H))[..., None] for g in grads]
+    want = o.stf_adjoint(texs, uv, o.BICUBIC, 4, 0, "tile8x8", gt, share_selection=True)
+    for gg, ww in zip(got, want):
+        assert np.max(np.abs(gg.cpu().numpy() - ww)) <= 1e-5 * np.abs(ww).max()
+    outs = stf.filter_reuse([dev(t) for t in texs], dev(uv), "square3x3", "bicubic", 4, 0, estimator="mis",
+                            share_selection=True)
+    ref = eo.stf_filter_estimator(texs, uv, o.BICUBIC, 4, 0, "square3x3", "mis", share_selection=True)
+    for k in range(2):
+        assert close(outs[k].cpu().numpy(), image(ref[k][0], uv), texs[k], uv, o.BICUBIC)

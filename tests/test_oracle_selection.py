@@ -97,3 +97,21 @@ def test_hash_streams_differ():
         slot, seed, frame = args
         other = o.slot_hash(px, py, slot, seed, frame)[0]
         assert np.mean(other == base) < 0.01
+
+
+def test_shared_selection_follows_the_first_slot_of_each_size():
+    # Sec. 4.5: textures with the same UV and resolution may share one
+    # selection; the leader of each size keeps its own random stream
+    rng = np.random.default_rng(0)
+    a = rng.random((32, 32, 4)); b = rng.random((32, 32, 2)); c = rng.random((16, 16, 1)); d = rng.random((16, 16, 1))
+    uv = (rng.random((16, 24, 2)) * 0.8 + 0.1).astype(np.float32)
+    assert o.selection_slots([a, b, c, d], True) == [0, 0, 2, 2]
+    assert o.selection_slots([a, b, c, d], False) == [0, 1, 2, 3]
+    shared = o.stf_filter([a, b, c, d], uv, o.BICUBIC, 3, 1, share_selection=True)
+    plain = o.stf_filter([a, b, c, d], uv, o.BICUBIC, 3, 1)
+    assert np.array_equal(shared[1][1], shared[0][1]) and np.array_equal(shared[3][1], shared[2][1])
+    assert np.array_equal(shared[0][1], plain[0][1]) and np.array_equal(shared[2][1], plain[2][1])
+    assert not np.array_equal(plain[1][1], plain[0][1])
+    # the follower of slot 0 equals slot 0's stream applied to its texture
+    (tb, sb), = o.stf_filter([b], uv, o.BICUBIC, 3, 1)
+    assert np.array_equal(shared[1][1], sb) and np.array_equal(shared[1][0], tb)
