@@ -193,6 +193,58 @@ def backward_form(torch, stf, texs, uv, steps, warmup):
             "textures": "RGBA16F + RG16F 2048^2, FP32 gradients"}
 
 
+def shared_selection_form(torch, stf, texs, uv, ref, steps, warmup):
+    """The benchmark launch with STF_SHARE_SELECTION (both textures are
+    2048^2, so the normal map reuses the albedo's picks, Sec. 4.5)."""
+    H, W = uv.shape[:2]
+    outs = [torch.empty((H, W, int(t.shape[2])), dtype=torch.float32, device=uv.device) for t in texs]
+    dt = launch_time(torch, lambda: stf.filter_reuse(texs, uv, "tile8x8", "bicubic", 0, 0, out=outs,
+                                                    share_selection=True), steps, warmup)
+    o = stf.filter_reuse(texs[:1], uv, "tile8x8", "bicubic", 0, 0, share_selection=True)[0]
+    return {"avg_launch_us": round(dt * 1e6, 2), "Mpixel_s": round(H * W / dt / 1e6, 1),
+            "psnr_albedo_db": round(psnr_rgb(torch, o, ref), 2)}
+
+
+def estimator_sweep(torch, stf, w, frames=4):
+    """PSNR against Eq. (3) versus magnification for one-tap STF, the
+    comparison estimators of Sec. 4.1 (with and without clamping), Eq. (14)
+    and Eq. (14) with exact filtering: 512x512 fronto-parallel views of the
+    256^2 RGBA8 texture, bilinear, 3x3 footprint, `frames` seeds averaged."""
+    tex = [torch.from_numpy(w.small_texture(0, 256)).cuda()]
+    rows = {}
+    for mag in (1, 2, 4, 8, 16, 32):
+        uv = torch.from_numpy(w.small_screen(512, 512, 256, float(mag), offset_seed=mag)).cuda()
+        ref = stf.filter_reference(tex, uv, "bilinear")[0]
+        row = {}
+        variants = [("stf", None, {}), ("wis", "wis", {}), ("wis_ef", "wis", {"exact_filtering": True})]
+        for e in ("is", "mis", "pmis", "regression"):
+            variants += [(e, e, {}), (e + "_clamp", e, {"clamp": True})]
+        for name, est, kw in variants:
+            mse = 0.0
+            for f in range(frames):
+                if est is None:
+                    out = stf.filter(tex, uv, "bilinear", 0, f)[0]
+                else:
+                    out = stf.filter_reuse(tex, uv, "square3x3", "bilinear", 0, f, estimator=est, **kw)[0]
+                d = out[..., :3].double() - ref[..., :3].double()
+                mse += float(torch.mean(d * d)) / frames
+            row[name] = round(10 * np.log10(1.0 / mse), 2) if mse > 0 else None
+        rows[str(mag)] = row
+    return {"psnr_db_by_magnification": rows, "footprint": "square3x3", "filter": "bilinear", "frames": frames}
+
+
+def footprint_generator_form(torch, stf):
+    """GPU time of the sparse footprint generator at the paper's settings
+    (K = 9, 32 candidates, sigma 1.4, 10 000 trials, 30 restarts)."""
+    stf.generate_footprints(9, 32, 1.4, 10000, 30, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lut, score = stf.generate_footprints(9, 32, 1.4, 10000, 30, 1)
+    torch.cuda.synchronize()
+    return {"ms": round((time.perf_counter() - t0) * 1e3, 2), "score": int(score.item()), "ideal_score": 64 * 8 * 8,
+            "settings": "K=9, 32 candidates, sigma 1.4, 10000 trials, 30 restarts"}
+
+
 DECODE_FLOPS_PER_TEXEL = 2 * (8 * 64 + 64 * 64 + 64 * 4)     # useful MLP flops (biases aside)
 
 
@@ -237,6 +289,32 @@ def latent_form(torch, stf, w, steps, warmup):
             "mfma_bf16_peak_tflops": 2500.0}
 
 
+def profile_launches(torch, stf, w, which, n=5):
+    """n launches of one secondary workload, for kernel traces and counters."""
+    dev = torch.device("cuda:0")
+    if which == "backward":
+        uv = torch.from_numpy(w.perspective_plane(1920, 1080, 2048, 2.0, 32.0)[0]).to(dev)
+        texs = [torch.from_numpy(w.plane_albedo(0, 2048)).to(dev), torch.from_numpy(w.plane_normal(0, 2048)).to(dev)]
+        g = [torch.randn((1080, 1920, int(t.shape[2])), device=dev) for t in texs]
+        dtex = [torch.zeros((2048, 2048, int(t.shape[2])), device=dev) for t in texs]
+        for _ in range(n):
+            stf.backward(texs, uv, g, "tile8x8", "bicubic", 0, 0, dtex=dtex)
+    else:
+        uv = torch.from_numpy(w.perspective_plane(1920, 1080, 1024, 4.0, 16.0)[0]).to(dev)
+        lat = w.latent_grid(0, 1024).astype(np.float64)
+        sc = w.amax_scale(lat, "fp8")
+        tex = [torch.from_numpy(w.quantize(lat, "fp8", sc)).view(torch.float8_e4m3fn).to(dev)]
+        dec = stf.pack_decoder([(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev))
+                                for a, b in w.decoder_weights(0)])
+        out = torch.empty((1080, 1920, 4), device=dev)
+        for _ in range(n):
+            stf.filter(tex, uv, "bicubic", 0, 0, out=[out], scales=[list(sc)], decoder=dec)
+            stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, out=[out], scales=[list(sc)], decoder=dec)
+        stf.filter_reference(tex, uv, "bicubic", out=[out], scales=[list(sc)], decoder=dec)
+    torch.cuda.synchronize()
+    print(f"{which}: {n} launches done", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +324,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision, backward and latent-decoder comparisons")
+    ap.add_argument("--profile", choices=["latent", "backward"],
+                    help="only run 5 launches of the latent-decoder or backward workload (for rocprofv3) and exit")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the per-launch traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -266,6 +346,9 @@ def main():
         sys.exit(1)
     stf.library()
     dev = torch.device("cuda:0")
+    if args.profile:
+        profile_launches(torch, stf, w, args.profile)
+        return
 
     uv_np, _, _, info = w.perspective_plane(1920, 1080, 2048, 2.0, 32.0)
     texs_np = [w.plane_albedo(0, 2048), w.plane_normal(0, 2048)]
@@ -370,6 +453,9 @@ def main():
         res["precision_forms"] = precision_forms(torch, stf, w, uv0, args.steps // 2, args.warmup)
         res["backward"] = backward_form(torch, stf, texs, uv0, args.steps // 4, args.warmup // 2)
         res["latent_decoder"] = latent_form(torch, stf, w, args.steps // 2, args.warmup)
+        res["shared_selection"] = shared_selection_form(torch, stf, texs, uv0, ref, args.steps // 2, args.warmup)
+        res["estimators"] = estimator_sweep(torch, stf, w)
+        res["footprint_generator"] = footprint_generator_form(torch, stf)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(texs_np, uv_np)
     print(json.dumps(res), flush=True)
