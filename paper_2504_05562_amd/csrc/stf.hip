@@ -492,7 +492,8 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
     const uint32_t sx = pk.sx, sy = pk.sy;
     Texel<PL> T;
     if constexpr (LAT)
-        decode_latent(dec, latent_bf16(block_texel(pk.raw, sx, format_bytes(t.fmt)), t), T.v);
+        decode_latent_dedup(dec, latent_bf16(block_texel(pk.raw, sx, format_bytes(t.fmt)), t), sx, sy, mx, my,
+                            reinterpret_cast<uint8_t*>(lds), T.v);
     else
         T = decode<PL>(block_texel(pk.raw, sx, format_bytes(t.fmt)), t.fmt);
     const bool scale_out = !LAT && t.has_scale;       // a latent scale precedes the decoder
@@ -687,7 +688,10 @@ __device__ __forceinline__ int payload_of(int fmt) {
 // texel fetch is issued before the first exchange so their latencies overlap.
 template <int FILT, int MODE, int NT, bool DEC, bool EF>
 __global__ __launch_bounds__(kThreads) void forward_kernel(Args a) {
-    __shared__ __align__(16) float lds_all[(MODE == kModeRecords || MODE == kModeBins) ? kWavesPerGroup * kLdsFloatsPerWave : 4];
+    // per-wave LDS: records or bins; with a decoder also the deduplicating decode's scratch
+    constexpr bool kLds = MODE == kModeRecords || MODE == kModeBins || DEC;
+    static_assert(kDedupBytes <= kLdsFloatsPerWave * 4, "decode scratch exceeds the wave's LDS");
+    __shared__ __align__(16) float lds_all[kLds ? kWavesPerGroup * kLdsFloatsPerWave : 4];
     __shared__ __align__(16) uint8_t dec[DEC ? kDecBytes : 16];
     if constexpr (DEC) {                       // before any wave of the group can leave
         stage_decoder(a.dec, dec);
@@ -695,7 +699,7 @@ __global__ __launch_bounds__(kThreads) void forward_kernel(Args a) {
     }
     Pixel P;
     if (!setup_pixel(a, P)) return;
-    float* lds = lds_all + ((MODE == kModeRecords || MODE == kModeBins) ? (threadIdx.x >> 6) * kLdsFloatsPerWave : 0);
+    float* lds = lds_all + (kLds ? (threadIdx.x >> 6) * kLdsFloatsPerWave : 0);
     TexArg t[NT];
 #pragma unroll
     for (int i = 0; i < NT; ++i) t[i] = a.tex[i];
@@ -944,7 +948,7 @@ __global__ __launch_bounds__(kThreads) void estimator_kernel(Args a) {
 // Deterministic filter, Eq. (3): sum over the support of f_c * T.
 template <int FILT, int PL, bool LAT = false>
 __device__ __forceinline__ void reference_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
-                                               const uint8_t* dec = nullptr) {
+                                               const uint8_t* dec = nullptr, uint8_t* scratch = nullptr) {
     constexpr int N = SelCtx<FILT>::N;
     constexpr int C = Texel<PL>::C;
     const TexArg t = a.tex[slot];
@@ -961,7 +965,8 @@ __device__ __forceinline__ void reference_slot(const Args& a, int slot, const Pi
             const uint32_t x = (uint32_t)(ctx.x.base + aa) & mx;
             Texel<PL> T;
             if constexpr (LAT)                       // every tap decodes (the full-filter cost)
-                decode_latent(dec, latent_bf16(block_texel(fetch_block(t, x, y, bpp), x, bpp), t), T.v);
+                decode_latent_dedup(dec, latent_bf16(block_texel(fetch_block(t, x, y, bpp), x, bpp), t), x, y, mx, my,
+                                    scratch, T.v);
             else
                 T = decode<PL>(block_texel(fetch_block(t, x, y, bpp), x, bpp), t.fmt);
             const float w = ctx.wxy[b * N + aa];
@@ -981,6 +986,7 @@ __device__ __forceinline__ void reference_slot(const Args& a, int slot, const Pi
 template <int FILT, bool DEC>
 __global__ __launch_bounds__(kThreads) void reference_kernel(Args a) {
     __shared__ __align__(16) uint8_t dec[DEC ? kDecBytes : 16];
+    __shared__ __align__(16) uint8_t dscratch[DEC ? kWavesPerGroup * kDedupBytes : 16];
     if constexpr (DEC) {
         stage_decoder(a.dec, dec);
         __syncthreads();
@@ -995,7 +1001,8 @@ __global__ __launch_bounds__(kThreads) void reference_kernel(Args a) {
         case kF16x2: reference_slot<FILT, kF16x2>(a, slot, P, ctx); break;
         case kF32x1: reference_slot<FILT, kF32x1>(a, slot, P, ctx); break;
         case kLatent:
-            if constexpr (DEC) reference_slot<FILT, kF32x4, true>(a, slot, P, ctx, dec);
+            if constexpr (DEC)
+                reference_slot<FILT, kF32x4, true>(a, slot, P, ctx, dec, dscratch + (threadIdx.x >> 6) * kDedupBytes);
             break;
         default: reference_slot<FILT, kF32x4>(a, slot, P, ctx); break;
         }

@@ -154,6 +154,54 @@ __device__ __forceinline__ void decode_latent(const uint8_t* dec, u32x4 lat, flo
     }
 }
 
+// LDS the deduplicating decode needs per wavefront (bytes).
+constexpr int kDedupBytes = 256 * 4 + 32 * 16 + 32 * 16;
+
+// Decode with duplicates removed: the texels picked by the wave usually
+// repeat (a magnified tile picks from a few texels), and each distinct
+// texel decodes alike in any column. When the picks lie within 16x16
+// texels of lane 0's pick and at most 32 are distinct, one lane per distinct
+// texel hands its latents to a compact column tile, the wave runs one column
+// tile through the MLP instead of two, and every lane takes the result of its
+// texel. Otherwise it falls back to decode_latent. The outputs are identical
+// either way. `scratch` is kDedupBytes of the wave's LDS; all 64 lanes call
+// in uniform control flow.
+__device__ __forceinline__ void decode_latent_dedup(const uint8_t* dec, u32x4 lat, uint32_t sx, uint32_t sy,
+                                                    uint32_t mx, uint32_t my, uint8_t* scratch, float out[4]) {
+    const int lane = threadIdx.x & 63;
+    const bool hi = lane >= 32;
+    const uint32_t sx0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)sx);
+    const uint32_t sy0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)sy);
+    const uint32_t rx = (sx - sx0 + 8u) & mx, ry = (sy - sy0 + 8u) & my;
+    if (__builtin_amdgcn_ballot_w64(rx >= 16u || ry >= 16u) == 0) {
+        int* owner = reinterpret_cast<int*>(scratch);                         // [256]
+        u32x4* latbuf = reinterpret_cast<u32x4*>(scratch + 256 * 4);          // [32]
+        float4* rgba = reinterpret_cast<float4*>(scratch + 256 * 4 + 32 * 16); // [32]
+        const int key = (int)(rx | (ry << 4));                                // injective on the texels
+        owner[key] = lane;                                                    // any writer wins
+        wave_lds_sync();
+        const int o = owner[key];
+        const uint64_t reps = __builtin_amdgcn_ballot_w64(o == lane);
+        const int n = __popcll(reps);
+        if (n <= 32) {
+            if (o == lane) latbuf[__popcll(reps & ((1ull << lane) - 1ull))] = lat;
+            wave_lds_sync();
+            const u32x4 one = {0x3F80u, 0u, 0u, 0u};
+            const u32x4 zero4 = {0u, 0u, 0u, 0u};
+            const u32x4 x = hi ? one : (lane < n ? latbuf[lane] : zero4);
+            const f32x16 y = decode_columns(dec, x, lane, hi);
+            if (!hi && lane < n) rgba[lane] = make_float4(y[0], y[1], y[2], y[3]);
+            wave_lds_sync();
+            const float4 v = rgba[__popcll(reps & ((1ull << o) - 1ull))];
+            out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+            wave_lds_sync();                                                  // scratch free again
+            return;
+        }
+        wave_lds_sync();
+    }
+    decode_latent(dec, lat, out);
+}
+
 // The lane's 8 latents as BF16 from the raw texel payload (16 bytes for
 // F16/BF16 latents, the low 8 bytes for FP8), times the optional
 // per-channel scale (in FP32, then RN to BF16).
