@@ -236,3 +236,33 @@ def test_reuse_psnr_gain_on_plane(plane):
     r = host(stf.filter_reuse(dt, duv, "tile8x8", "bicubic", 0)[0])
     gain = o.psnr(r[..., :3], ref[..., :3]) - o.psnr(s[..., :3], ref[..., :3])
     assert gain >= 10.0, gain
+
+
+# --------------------------------------------------------------- maximum sizes
+
+def test_maximum_texture_extents_and_seams():
+    """Textures at the largest extent per axis (32768 texels), sampled across
+    the wrap seam, whole-tile reuse and quads."""
+    rng = np.random.default_rng(21)
+    wide = rng.integers(0, 256, (4, 32768, 4), dtype=np.uint8)
+    tall = rng.integers(0, 256, (32768, 16, 1), dtype=np.uint8)     # rows of 16 bytes (pitch rule)
+    py, px = np.mgrid[0:24, 0:72].astype(np.float64)
+    uv = np.empty((24, 72, 2), np.float32)
+    uv[..., 0] = 1.0 + (px - 36) * 0.3 / 32768        # u crosses 1.0: texel 32767 next to texel 0
+    uv[..., 1] = (py + 0.5) / 24 * 0.9 + 0.05
+    run_case([wide], uv, "bicubic", "tile8x8", seed=2)
+    run_case([wide], uv, "bilinear", "quad2x2", seed=3)
+    uvt = uv[..., ::-1].copy()
+    run_case([tall], uvt, "bicubic", "tile8x8", seed=4)
+
+
+@pytest.mark.parametrize("shape", [(8, 32768), (32768, 8)])
+def test_maximum_screen_extents(shape):
+    """Screens at the largest extent per axis (32768 pixels)."""
+    H, W = shape
+    tex = w.small_texture(5, 64)
+    py, px = np.mgrid[0:H, 0:W].astype(np.float64)
+    uv = np.empty((H, W, 2), np.float32)
+    uv[..., 0] = ((px + 0.5) / 6.0 / 64) % 1.0
+    uv[..., 1] = ((py + 0.5) / 6.0 / 64) % 1.0
+    run_case([tex], uv, "bilinear", "tile8x8", seed=9)
