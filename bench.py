@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpixel/s filtered (reuse vs 1-sample STF) @1080p bicubic, %HBM peak, PSNR dB"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2504_05562_amd/csrc/stf.hip", "paper_2504_05562_amd/csrc/stf_device.h",
+KERNEL_SOURCES = ["paper_2504_05562_amd/csrc/stf_kernels.h", "paper_2504_05562_amd/csrc/stf_device.h",
                   "paper_2504_05562_amd/csrc/stf_decoder.h"]
 BENCH_KERNEL = "forward_kernel<1, 3, 2, false, false>"     # bicubic, whole-tile bins, 2 textures
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "reuse_tile8x8_plane1080p_traffic.json")

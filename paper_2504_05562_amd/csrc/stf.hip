@@ -1,1013 +1,18 @@
-// STF with sample reuse on gfx950: forward, reference and adjoint kernels
-// plus the host side of the C ABI declared in include/stf.h.
-//
-// One wavefront processes one 8x8 screen tile; a 256-thread workgroup holds
-// four tiles side by side (32x8 pixels), so every UV row segment a group
-// reads is 256 contiguous bytes. Per pixel and texture slot a kernel:
-//   1. loads UV once (shared by all slots),
-//   2. splits the texel-space coordinate and forms per-axis weights,
-//   3. draws two uniforms from the pcg4d hash and picks one texel per axis
-//      by exact integer CDF inversion (one-tap STF),
-//   4. fetches and decodes that single texel,
-//   5. (reuse) exchanges picks inside the tile and evaluates Eq. (14) in the
-//      difference form  out = T_c + sum_i w_i (T_i - T_c) / sum_i w_i,
-//      which equals Eq. (14) and keeps constant regions and the no-overlap
-//      fallback exact in FP32,
-//   6. stores FP32 colours with non-temporal stores.
-// Exchange strategies:
-//   quad2x2  DPP quad_perm moves, no LDS;
-//   tile8x8  texel bins in LDS: every lane adds its 1/p to the bin of its
-//            texel (N_j = sum over picks of texel j of 1/p_i), then each
-//            pixel visits only the N x N bins of its own support:
-//            sum_i w_i (T_i - T_c) = sum_j f_c(j) N_j (T_j - T_c);
-//   others   per-lane records in LDS read through the footprint member
-//            table (windows computed, or the caller's LUT).
+// Host side of the C ABI declared in include/stf.h: argument validation,
+// kernel selection and launches. The kernels live in stf_kernels.h.
 #include <hip/hip_runtime.h>
-#include <hip/hip_fp16.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
 
-#include "stf_device.h"
-#include "stf_decoder.h"
+#include "stf_kernels.h"
 #include "stf_status.h"
 
 namespace stf {
-
-enum Mode { kModeStf = 0, kModeQuad = 1, kModeRecords = 2, kModeBins = 3 };
-
-// Whole-tile gather arithmetic: true accumulates w_j (T_j - T_c) (exact zero
-// for constant regions and the one-tap fallback in FP32); false accumulates
-// w_j T_j (one operation less per channel and bin; within a few ulp).
-#ifndef STF_EXACT_DIFF
-#define STF_EXACT_DIFF 1
-#endif
-constexpr bool kExactDiff = STF_EXACT_DIFF != 0;
-// 2D weights f_c = wx * wy from a per-pixel table (16 registers for the
-// B-spline) or formed per bin (one multiply more, fewer live registers).
-#ifndef STF_WEIGHT_TABLE
-#define STF_WEIGHT_TABLE 0
-#endif
-constexpr bool kWeightTable = STF_WEIGHT_TABLE != 0;
-
-// LDS per wavefront: bins (kBinRecords x 16 B records, or kBinRecords floats
-// of N plus kBinRecords x 16 B of decoded texels) followed by kBinRecords
-// 64-bit fixed-point accumulators, or records (64 x {s, r} + 64 x 16 B).
-constexpr int kAccFloatOffset = kBinRecords * 5;
-constexpr int kLdsFloatsPerWave = kAccFloatOffset + kBinRecords * 2;
-// backward bins: Nb float [kBins], then (8-byte aligned) u64 [kBins] + u64 [kBins][4]
-constexpr int kBwdN64Offset = (kBins + 1) & ~1;
-constexpr int kBwdLdsFloatsPerWave = kBwdN64Offset + kBins * (1 + 4) * 2;
-static_assert(kBwdLdsFloatsPerWave >= kLdsFloatsPerWave / 2, "backward LDS layout");
-
-struct Pixel {
-    int px, py;          // screen pixel
-    int lx, ly;          // pixel inside the tile
-    int q;               // row-major tile pixel id ly*8+lx
-    bool valid;          // inside the screen
-    float u, v;
-};
-
-// Per-pixel selection state for one texture size: both axes plus the
-// products of their weights (the 2D filter weights f_c over the support).
-template <int FILT>
-struct SelCtx {
-    static constexpr int N = AxisCtx<FILT>::N;
-    AxisCtx<FILT> x, y;
-    float wxy[N * N];
-    int tw = 0, th = 0;
-    __device__ __forceinline__ void update(const Pixel& P, int w, int h) {
-        if (w == tw && h == th) return;                  // wave-uniform
-        if (w != tw) x.init(P.u, w);
-        if (h != th) y.init(P.v, h);
-        tw = w;
-        th = h;
-#pragma unroll
-        for (int b = 0; b < N; ++b)
-#pragma unroll
-            for (int a = 0; a < N; ++a) wxy[b * N + a] = x.w(a) * y.w(b);
-    }
-};
-
-// Footprint member m of tile pixel (lx, ly) as a row-major tile pixel id.
-__device__ __forceinline__ int member_id(int fp, int lx, int ly, int m, const uint8_t* lut, int lut_k, int q) {
-    switch (fp) {
-    case STF_FP_QUAD2X2:
-        return ((ly & ~1) + (m >> 1)) * 8 + (lx & ~1) + (m & 1);
-    case STF_FP_WAVE2X2: {
-        const int ox = min(max(lx - ((ly + (lx >> 1)) & 1), 0), 6);
-        const int oy = min(max(ly - ((lx + (ly >> 1)) & 1), 0), 6);
-        return (oy + (m >> 1)) * 8 + ox + (m & 1);
-    }
-    case STF_FP_SQUARE3X3: {
-        const int ox = min(max(lx - 1, 0), 5), oy = min(max(ly - 1, 0), 5);
-        const int my = m / 3;
-        return (oy + my) * 8 + ox + (m - 3 * my);
-    }
-    case STF_FP_SQUARE4X4: {
-        const int ox = min(max(lx - 1, 0), 4), oy = min(max(ly - 1, 0), 4);
-        return (oy + (m >> 2)) * 8 + ox + (m & 3);
-    }
-    case STF_FP_LUT:
-        return lut[q * lut_k + m] & 63;
-    default:  // STF_FP_TILE8X8
-        return m;
-    }
-}
-
-__device__ __forceinline__ int footprint_size(int fp, int lut_k) {
-    switch (fp) {
-    case STF_FP_QUAD2X2: case STF_FP_WAVE2X2: return 4;
-    case STF_FP_SQUARE3X3: return 9;
-    case STF_FP_SQUARE4X4: return 16;
-    case STF_FP_LUT: return lut_k;
-    default: return 64;
-    }
-}
-
-// Offset of texel s (packed sx | sy << 16) inside the support starting at
-// (bx, by), modulo the texture size; inside iff both offsets are < N.
-template <int N>
-__device__ __forceinline__ bool support_offset(uint32_t s, int bx, int by, uint32_t mx, uint32_t my,
-                                               uint32_t& dx, uint32_t& dy) {
-    dx = ((s & 0xFFFFu) - (uint32_t)bx) & mx;
-    dy = ((s >> 16) - (uint32_t)by) & my;
-    return dx < (uint32_t)N && dy < (uint32_t)N;
-}
-
-// Accumulate one shared pick (texel s, reciprocal PMF r, decoded texel Ti)
-// into pixel c's sums; picks outside c's support are skipped.
-template <int FILT, int C>
-__device__ __forceinline__ void accumulate(const SelCtx<FILT>& ctx, uint32_t s, float r, const float* Ti,
-                                           uint32_t mx, uint32_t my, const float* Tc, float& B, float* acc) {
-    constexpr int N = SelCtx<FILT>::N;
-    uint32_t dx, dy;
-    if (support_offset<N>(s, ctx.x.base, ctx.y.base, mx, my, dx, dy)) {
-        const float w = ctx.x.wsel(dx) * ctx.y.wsel(dy) * r;
-        B += w;
-#pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] = fmaf(w, Ti[c] - Tc[c], acc[c]);
-    }
-}
-
-// Exact filtering (Sec. 4.2): which texels of pixel c's support the shared
-// picks hit (bit dy * N + dx) and the Eq. (3) sum over those texels, each
-// counted once.
-template <int FILT, int C>
-struct Coverage {
-    static constexpr int N = SelCtx<FILT>::N;
-    uint32_t seen = 0u;
-    float sum[C];
-    __device__ __forceinline__ Coverage() {
-#pragma unroll
-        for (int c = 0; c < C; ++c) sum[c] = 0.0f;
-    }
-    __device__ __forceinline__ void add(const SelCtx<FILT>& ctx, uint32_t dx, uint32_t dy, const float* T) {
-        const uint32_t bit = 1u << (dy * N + dx);
-        if (!(seen & bit)) {
-            seen |= bit;
-            const float f = ctx.x.wsel(dx) * ctx.y.wsel(dy);
-#pragma unroll
-            for (int c = 0; c < C; ++c) sum[c] = fmaf(f, T[c], sum[c]);
-        }
-    }
-    __device__ __forceinline__ void add_pick(const SelCtx<FILT>& ctx, uint32_t s, const float* T, uint32_t mx,
-                                             uint32_t my) {
-        uint32_t dx, dy;
-        if (support_offset<N>(s, ctx.x.base, ctx.y.base, mx, my, dx, dy)) add(ctx, dx, dy, T);
-    }
-    // every support texel of positive weight was picked
-    __device__ __forceinline__ bool covered(const SelCtx<FILT>& ctx) const {
-        uint32_t need = 0u;
-#pragma unroll
-        for (int b = 0; b < N; ++b)
-#pragma unroll
-            for (int a = 0; a < N; ++a)
-                if (ctx.wxy[b * N + a] > 0.0f) need |= 1u << (b * N + a);
-        return (seen & need) == need;
-    }
-};
-
-// ---------------------------------------------------------------- texel bins
-
-// One bin per texel of a kBinG x kBinG window: N = sum of 1/p over the picks
-// of that texel, plus the texel itself (raw half bits or decoded floats).
-// gather() adds one bin's term of  sum_j f_c(j) N_j (T_j - T_c)  (EXACT) or
-// of  sum_j f_c(j) N_j T_j , and f_c(j) N_j to B.
-template <int P> struct Bins;
-
-typedef unsigned int u3 __attribute__((ext_vector_type(3)));
-
-template <> struct Bins<kF16x4> {             // record {raw.x, raw.y, N, pad}, 16-byte aligned
-    __device__ static void clear_one(float* l, int rec) {
-        *reinterpret_cast<u3*>(__builtin_assume_aligned(&l[rec * 4], 16)) = u3{0u, 0u, 0u};
-    }
-    __device__ static void put(float* l, int bin, float r, const Texel<kF16x4>& T) {
-        atomicAdd(&l[bin * 4 + 2], r);
-        *reinterpret_cast<uint2*>(&l[bin * 4]) = T.raw;
-    }
-    __device__ static void put_texel(float* l, int bin, const Texel<kF16x4>& T) {
-        *reinterpret_cast<uint2*>(&l[bin * 4]) = T.raw;
-    }
-    __device__ static void finalize(float* l, int rec, float n) {
-        if (n == 0.0f) clear_one(l, rec);
-        else l[rec * 4 + 2] = n;
-    }
-    template <bool EXACT>
-    __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
-        const u3 q = *reinterpret_cast<const u3*>(__builtin_assume_aligned(&l[bin * 4], 16));   // 12 of 16 bytes
-        const float w = f * __uint_as_float(q.z);
-        B += w;
-        if constexpr (EXACT) {
-            acc[0] = fmaf(w, half_minus<0>(q.x, nTc[0]), acc[0]);
-            acc[1] = fmaf(w, half_minus<1>(q.x, nTc[1]), acc[1]);
-            acc[2] = fmaf(w, half_minus<0>(q.y, nTc[2]), acc[2]);
-            acc[3] = fmaf(w, half_minus<1>(q.y, nTc[3]), acc[3]);
-        } else {
-            acc[0] = fmaf(h2f(q.x), w, acc[0]);
-            acc[1] = fmaf(h2f(q.x >> 16), w, acc[1]);
-            acc[2] = fmaf(h2f(q.y), w, acc[2]);
-            acc[3] = fmaf(h2f(q.y >> 16), w, acc[3]);
-        }
-    }
-    // Eq. (3) term of the bin (zero texel when empty) and its coverage
-    __device__ static void exact(const float* l, int bin, float f, float* ex, bool& cov) {
-        const u3 q = *reinterpret_cast<const u3*>(__builtin_assume_aligned(&l[bin * 4], 16));
-        cov = cov && (f == 0.0f || __uint_as_float(q.z) != 0.0f);
-        ex[0] = fmaf(f, h2f(q.x), ex[0]);
-        ex[1] = fmaf(f, h2f(q.x >> 16), ex[1]);
-        ex[2] = fmaf(f, h2f(q.y), ex[2]);
-        ex[3] = fmaf(f, h2f(q.y >> 16), ex[3]);
-    }
-};
-
-template <> struct Bins<kF16x2> {             // record {raw, N}
-    __device__ static void clear_one(float* l, int rec) { reinterpret_cast<uint2*>(l)[rec] = make_uint2(0u, 0u); }
-    __device__ static void put(float* l, int bin, float r, const Texel<kF16x2>& T) {
-        atomicAdd(&l[bin * 2 + 1], r);
-        reinterpret_cast<uint32_t*>(l)[bin * 2] = T.raw;
-    }
-    __device__ static void put_texel(float* l, int bin, const Texel<kF16x2>& T) {
-        reinterpret_cast<uint32_t*>(l)[bin * 2] = T.raw;
-    }
-    __device__ static void finalize(float* l, int rec, float n) {
-        if (n == 0.0f) clear_one(l, rec);
-        else l[rec * 2 + 1] = n;
-    }
-    template <bool EXACT>
-    __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
-        const uint2 q = reinterpret_cast<const uint2*>(l)[bin];
-        const float w = f * __uint_as_float(q.y);
-        B += w;
-        if constexpr (EXACT) {
-            acc[0] = fmaf(w, half_minus<0>(q.x, nTc[0]), acc[0]);
-            acc[1] = fmaf(w, half_minus<1>(q.x, nTc[1]), acc[1]);
-        } else {
-            acc[0] = fmaf(h2f(q.x), w, acc[0]);
-            acc[1] = fmaf(h2f(q.x >> 16), w, acc[1]);
-        }
-    }
-    __device__ static void exact(const float* l, int bin, float f, float* ex, bool& cov) {
-        const uint2 q = reinterpret_cast<const uint2*>(l)[bin];
-        cov = cov && (f == 0.0f || __uint_as_float(q.y) != 0.0f);
-        ex[0] = fmaf(f, h2f(q.x), ex[0]);
-        ex[1] = fmaf(f, h2f(q.x >> 16), ex[1]);
-    }
-};
-
-template <> struct Bins<kF32x1> {             // record {T, N}
-    __device__ static void clear_one(float* l, int rec) { reinterpret_cast<uint2*>(l)[rec] = make_uint2(0u, 0u); }
-    __device__ static void put(float* l, int bin, float r, const Texel<kF32x1>& T) {
-        atomicAdd(&l[bin * 2 + 1], r);
-        l[bin * 2] = T.v[0];
-    }
-    __device__ static void put_texel(float* l, int bin, const Texel<kF32x1>& T) { l[bin * 2] = T.v[0]; }
-    __device__ static void finalize(float* l, int rec, float n) {
-        if (n == 0.0f) clear_one(l, rec);
-        else l[rec * 2 + 1] = n;
-    }
-    template <bool EXACT>
-    __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
-        const float2 q = reinterpret_cast<const float2*>(l)[bin];
-        const float w = f * q.y;
-        B += w;
-        acc[0] = EXACT ? fmaf(w, q.x + nTc[0], acc[0]) : fmaf(q.x, w, acc[0]);
-    }
-    __device__ static void exact(const float* l, int bin, float f, float* ex, bool& cov) {
-        const float2 q = reinterpret_cast<const float2*>(l)[bin];
-        cov = cov && (f == 0.0f || q.y != 0.0f);
-        ex[0] = fmaf(f, q.x, ex[0]);
-    }
-};
-
-template <> struct Bins<kF32x4> {             // float4 T[kBinRecords], then float N[kBinRecords]
-    __device__ static void clear_one(float* l, int rec) {
-        reinterpret_cast<uint4*>(l)[rec] = make_uint4(0u, 0u, 0u, 0u);
-        l[4 * kBinRecords + rec] = 0.0f;
-    }
-    __device__ static void put(float* l, int bin, float r, const Texel<kF32x4>& T) {
-        atomicAdd(&l[4 * kBinRecords + bin], r);
-        reinterpret_cast<float4*>(l)[bin] = make_float4(T.v[0], T.v[1], T.v[2], T.v[3]);
-    }
-    __device__ static void put_texel(float* l, int bin, const Texel<kF32x4>& T) {
-        reinterpret_cast<float4*>(l)[bin] = make_float4(T.v[0], T.v[1], T.v[2], T.v[3]);
-    }
-    __device__ static void finalize(float* l, int rec, float n) {
-        if (n == 0.0f) clear_one(l, rec);
-        else l[4 * kBinRecords + rec] = n;
-    }
-    template <bool EXACT>
-    __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
-        const float4 q = reinterpret_cast<const float4*>(l)[bin];
-        const float w = f * l[4 * kBinRecords + bin];
-        B += w;
-        const float T[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = EXACT ? fmaf(w, T[c] + nTc[c], acc[c]) : fmaf(T[c], w, acc[c]);
-    }
-    __device__ static void exact(const float* l, int bin, float f, float* ex, bool& cov) {
-        const float4 q = reinterpret_cast<const float4*>(l)[bin];
-        cov = cov && (f == 0.0f || l[4 * kBinRecords + bin] != 0.0f);
-        ex[0] = fmaf(f, q.x, ex[0]);
-        ex[1] = fmaf(f, q.y, ex[1]);
-        ex[2] = fmaf(f, q.z, ex[2]);
-        ex[3] = fmaf(f, q.w, ex[3]);
-    }
-};
-
-// Bin window of the wave: kBinG x kBinG texels whose corner sits `margin`
-// texels before lane 0's support. Returns false (wave-uniformly) when some
-// on-screen pixel's support leaves the window.
-template <int N>
-__device__ __forceinline__ bool bin_window(const Pixel& P, int bx, int by, uint32_t mx, uint32_t my, int tw, int th,
-                                           int& base_x, int& base_y, uint32_t& rx, uint32_t& ry) {
-    constexpr int margin = (kBinG - N) / 2;
-    base_x = __builtin_amdgcn_readfirstlane(bx) - margin;
-    base_y = __builtin_amdgcn_readfirstlane(by) - margin;
-    rx = (uint32_t)(bx - base_x) & mx;
-    ry = (uint32_t)(by - base_y) & my;
-    const bool fits = !P.valid || (rx <= (uint32_t)(kBinG - N) && ry <= (uint32_t)(kBinG - N));
-    return (tw >= kBinG) && (th >= kBinG) && (__builtin_amdgcn_ballot_w64(!fits) == 0);
-}
-
-// Bounding box, in window coordinates, of every on-screen pixel's support:
-// one bit per support start column / row, OR-reduced over the wave.
-struct BinBox {
-    int x0, x1, y0, y1;
-};
-
-template <int N>
-__device__ __forceinline__ BinBox support_box(const Pixel& P, uint32_t rx, uint32_t ry) {
-    const uint32_t bits = wave_or(P.valid ? ((1u << rx) | (1u << (16u + ry))) : 0u);
-    BinBox b;
-    b.x0 = __builtin_ctz(bits & 0xFFFFu);
-    b.x1 = 31 - __builtin_clz(bits & 0xFFFFu) + N - 1;
-    b.y0 = __builtin_ctz(bits >> 16);
-    b.y1 = 31 - __builtin_clz(bits >> 16) + N - 1;
-    return b;
-}
-
-// Calls f(record) for every bin of the box, one 8x8 block of bins per step
-// (lane -> (lane & 7, lane >> 3)); wave-uniform trip counts.
-template <typename F>
-__device__ __forceinline__ void for_box(const BinBox& b, int lane, F f) {
-    for (int by = b.y0; by <= b.y1; by += 8)
-        for (int bx = b.x0; bx <= b.x1; bx += 8) {
-            const int x = bx + (lane & 7), y = by + (lane >> 3);
-            if (x <= b.x1 && y <= b.y1) f(y * kBinStride + x);
-        }
-}
-
-// Exact sums of 1/p per bin. With e_max the largest biased exponent of the
-// wave's reciprocal PMFs, every r whose exponent is at least e_max - 33 is
-// the integer m * 2^(e - e_max + 33) times 2^(e_max - 183) (m = 24-bit
-// significand), and at most 64 of them stay below 2^63: the 64-bit integer
-// sums are exact and independent of the order of the atomic adds; each bin
-// is then converted to FP32 (within 2 ulp, deterministically). Waves whose
-// exponents span more than 33 fall back to FP32 atomics.
-__device__ __forceinline__ uint64_t fixed_of(float r, uint32_t e_max) {
-    const uint32_t b = __float_as_uint(r);
-    const uint32_t m = (b & 0x7FFFFFu) | 0x800000u;
-    return (uint64_t)m << ((b >> 23) - e_max + 33u);
-}
-
-__device__ __forceinline__ float float_of(uint64_t n, uint32_t e_max) {
-    const float f = fmaf((float)(uint32_t)(n >> 32), 4294967296.0f, (float)(uint32_t)n);   // within 2 ulp
-    return ldexpf(f, (int)e_max - 183);
-}
-
-// Signed values in the same fixed point (two's complement; wrap-around
-// addition is exact). Magnitudes below 2^(e_ref - 183) truncate toward zero:
-// the absolute error per term is below 2^-57 of the largest term allowed.
-__device__ __forceinline__ uint64_t signed_fixed_of(float v, uint32_t e_ref) {
-    const uint32_t b = __float_as_uint(v);
-    const uint32_t e = (b >> 23) & 0xFFu;
-    const uint64_t m = (uint64_t)((b & 0x7FFFFFu) | (e != 0u ? 0x800000u : 0u));
-    const int sh = (int)e - (int)e_ref + 33;
-    const uint64_t a = sh >= 0 ? (m << (sh > 39 ? 39 : sh)) : (sh > -25 ? (m >> -sh) : 0ull);
-    return (b >> 31) ? (0ull - a) : a;
-}
-
-__device__ __forceinline__ float signed_float_of(uint64_t n, uint32_t e_ref) {
-    const bool neg = (int64_t)n < 0;
-    const float f = float_of(neg ? 0ull - n : n, e_ref);
-    return neg ? -f : f;
-}
-
-// Bin window and support box of the wave for one texture size (shared by
-// every texture of that size).
-template <int N>
-struct BinGeom {
-    bool ok = false;         // every on-screen support fits the window
-    uint32_t rx = 0, ry = 0; // this pixel's support start inside the window
-    BinBox box;
-    int tw = 0, th = 0;
-};
-
-template <int FILT>
-__device__ __forceinline__ void update_geom(BinGeom<AxisCtx<FILT>::N>& g, const Pixel& P, const SelCtx<FILT>& ctx,
-                                            int tw, int th) {
-    constexpr int N = AxisCtx<FILT>::N;
-    if (g.tw == tw && g.th == th) return;                // wave-uniform
-    int base_x, base_y;
-    g.ok = bin_window<N>(P, ctx.x.base, ctx.y.base, (uint32_t)tw - 1u, (uint32_t)th - 1u, tw, th, base_x, base_y,
-                         g.rx, g.ry);
-    if (g.ok) g.box = support_box<N>(P, g.rx, g.ry);
-    g.tw = tw;
-    g.th = th;
-}
-
-// Receive the pick of quad partner lane^X through DPP and accumulate it.
-template <int X, int FILT, int C, bool EF, int CC>
-__device__ __forceinline__ void quad_step(const SelCtx<FILT>& ctx, uint32_t s, float r, const float* Tv, uint32_t mx,
-                                          uint32_t my, float& B, float* acc, Coverage<FILT, CC>& cov) {
-    float Ti[C];
-    const uint32_t si = quad_xor<X>(s);
-    const float ri = quad_xor<X>(r);
-#pragma unroll
-    for (int c = 0; c < C; ++c) Ti[c] = quad_xor<X>(Tv[c]);
-    accumulate<FILT, C>(ctx, si, ri, Ti, mx, my, Tv, B, acc);
-    if constexpr (EF) {
-        if (ri != 0.0f) cov.add_pick(ctx, si, Ti, mx, my);   // off-screen partners carry r = 0
-    }
-}
-
-// The one-tap pick of one texture slot: per-axis offsets, texel, and the
-// 16-byte block holding the texel (extracted after every load is issued).
-struct SlotPick {
-    int kx, ky;
-    uint32_t sx, sy;
-    uint4 raw;
-};
-
-template <int FILT>
-__device__ __forceinline__ SlotPick pick_slot(const TexArg& t, const SelCtx<FILT>& ctx, uint32_t hx, uint32_t hy) {
-    SlotPick k;
-    k.kx = ctx.x.pick(hx);
-    k.ky = ctx.y.pick(hy);
-    k.sx = (uint32_t)(ctx.x.base + k.kx) & ((uint32_t)t.w - 1u);
-    k.sy = (uint32_t)(ctx.y.base + k.ky) & ((uint32_t)t.h - 1u);
-    k.raw = fetch_block(t, k.sx, k.sy, format_bytes(t.fmt));
-    return k;
-}
-
-// Exchange and estimator for one texture slot of one pixel. LAT: the texture
-// holds latents; the picked texel is decoded by the MLP in `dec` (LDS) before
-// it is shared, so every pixel decodes exactly one texel.
-// EF: exact filtering (Sec. 4.2) replaces the estimate by the Eq. (3) value
-// whenever the shared picks cover the pixel's support.
-template <int FILT, int MODE, int PL, bool LAT = false, bool EF = false>
-__device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int slot, const Pixel& P,
-                                          const SelCtx<FILT>& ctx, const BinGeom<AxisCtx<FILT>::N>& geom,
-                                          const SlotPick& pk, float* lds, const uint8_t* dec = nullptr) {
-    static_assert(!LAT || PL == kF32x4, "decoded latents are RGBA FP32");
-    constexpr int N = SelCtx<FILT>::N;
-    constexpr int C = Texel<PL>::C;
-    const int lane = lane_id();
-    const int kx = pk.kx, ky = pk.ky;
-    const uint32_t mx = (uint32_t)t.w - 1u, my = (uint32_t)t.h - 1u;
-    const uint32_t sx = pk.sx, sy = pk.sy;
-    Texel<PL> T;
-    if constexpr (LAT)
-        decode_latent_dedup(dec, latent_bf16(block_texel(pk.raw, sx, format_bytes(t.fmt)), t), sx, sy, mx, my,
-                            reinterpret_cast<uint8_t*>(lds), T.v);
-    else
-        T = decode<PL>(block_texel(pk.raw, sx, format_bytes(t.fmt)), t.fmt);
-    const bool scale_out = !LAT && t.has_scale;       // a latent scale precedes the decoder
-    const int64_t pix = (int64_t)P.py * a.sw + P.px;
-
-    if (a.sel != nullptr && P.valid) {
-        int2* sp = reinterpret_cast<int2*>(a.sel) + ((int64_t)slot * a.sh * a.sw + pix);
-        *sp = make_int2((int)sx, (int)sy);
-    }
-    float Tv[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) Tv[c] = T.ch(c);
-    if constexpr (MODE == kModeStf) {
-        if (P.valid) {
-            if (scale_out) {
-#pragma unroll
-                for (int c = 0; c < C; ++c) Tv[c] *= t.scale[c];
-            }
-            store_out<C>(a.out[slot], pix, Tv);
-        }
-        return;
-    } else {
-        // 1/p of the own pick; off-screen pixels share a pick of weight zero
-        const float r = P.valid ? fast_rcp(ctx.x.wsel(kx) * ctx.y.wsel(ky)) : 0.0f;
-        if (!P.valid) {
-#pragma unroll
-            for (int c = 0; c < C; ++c) Tv[c] = 0.0f;
-        }
-        const uint32_t s = sx | (sy << 16);
-        float B = 1.0f;            // own pick: w_c = f_c / p_c = 1 (Sec. 4.5)
-        float acc[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] = 0.0f;
-        Coverage<FILT, EF ? C : 1> cov;            // used only with EF
-        bool covered = false;
-
-        if constexpr (MODE == kModeQuad) {
-            if constexpr (EF) cov.add(ctx, (uint32_t)kx, (uint32_t)ky, Tv);
-            quad_step<1, FILT, C, EF>(ctx, s, r, Tv, mx, my, B, acc, cov);
-            quad_step<2, FILT, C, EF>(ctx, s, r, Tv, mx, my, B, acc, cov);
-            quad_step<3, FILT, C, EF>(ctx, s, r, Tv, mx, my, B, acc, cov);
-            if constexpr (EF) covered = cov.covered(ctx);
-        } else {
-            bool use_bins = false;
-            if constexpr (MODE == kModeBins) {
-                use_bins = geom.ok;
-                if (use_bins) {
-                    const uint32_t rx = geom.rx, ry = geom.ry;
-                    const BinBox& box = geom.box;
-                    const int my_bin = (int)(ry + ky) * kBinStride + (int)(rx + kx);
-                    const uint32_t e = P.valid ? (__float_as_uint(r) >> 23) : 0u;
-                    const uint32_t e_max = wave_max(e);
-                    const bool fixed = __builtin_amdgcn_ballot_w64(P.valid && e + 33u < e_max) == 0;
-                    if (fixed) {
-                        uint64_t* acc64 = reinterpret_cast<uint64_t*>(lds + kAccFloatOffset);
-                        for_box(box, lane, [&](int rec) { acc64[rec] = 0ull; });
-                        wave_lds_sync();
-                        if (P.valid) {
-                            atomicAdd(reinterpret_cast<unsigned long long*>(&acc64[my_bin]),
-                                      (unsigned long long)fixed_of(r, e_max));
-                            Bins<PL>::put_texel(lds, my_bin, T);
-                        }
-                        wave_lds_sync();
-                        for_box(box, lane, [&](int rec) { Bins<PL>::finalize(lds, rec, float_of(acc64[rec], e_max)); });
-                    } else {
-                        for_box(box, lane, [&](int rec) { Bins<PL>::clear_one(lds, rec); });
-                        wave_lds_sync();
-                        if (P.valid) Bins<PL>::put(lds, my_bin, r, T);
-                    }
-                    wave_lds_sync();
-                    B = 0.0f;                        // the own pick is in the bins
-                    const int bin0 = (int)ry * kBinStride + (int)rx;
-                    float nTc[C];
-#pragma unroll
-                    for (int c = 0; c < C; ++c) nTc[c] = -Tv[c];
-                    bool all_in = true;
-#pragma unroll
-                    for (int b = 0; b < N; ++b) {
-                        const float wyb = ctx.y.w(b);
-#pragma unroll
-                        for (int aa = 0; aa < N; ++aa) {
-                            const float f = kWeightTable ? ctx.wxy[b * N + aa] : ctx.x.w(aa) * wyb;
-                            Bins<PL>::template gather<kExactDiff>(lds, bin0 + b * kBinStride + aa, f, nTc, B, acc);
-                            // same weights and order as the Eq. (3) kernel: bit-identical sums
-                            if constexpr (EF) Bins<PL>::exact(lds, bin0 + b * kBinStride + aa, f, cov.sum, all_in);
-                        }
-                    }
-                    if constexpr (EF) covered = all_in;
-                    if constexpr (!kExactDiff) {
-                        // sum_j w_j T_j  ->  sum_j w_j (T_j - T_c), the form the final step expects
-#pragma unroll
-                        for (int c = 0; c < C; ++c) acc[c] = fmaf(-B, Tv[c], acc[c]);
-                    }
-                    wave_lds_sync();                 // reads done before the next slot reuses LDS
-                }
-            }
-            if (!use_bins) {
-                uint2* meta = reinterpret_cast<uint2*>(lds);        // [64] {s, r}
-                float4* val = reinterpret_cast<float4*>(lds + 128);  // [64] texel
-                meta[P.q] = make_uint2(s, __float_as_uint(r));
-                float pad[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int c = 0; c < C; ++c) pad[c] = Tv[c];
-                val[P.q] = make_float4(pad[0], pad[1], pad[2], pad[3]);
-                wave_lds_sync();
-                const int fp = (MODE == kModeBins) ? (int)STF_FP_TILE8X8 : a.footprint;
-                const int K = footprint_size(fp, a.lut_k);
-                if constexpr (EF) cov.add(ctx, (uint32_t)kx, (uint32_t)ky, Tv);
-                for (int m = 0; m < K; ++m) {
-                    const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
-                    if (j == P.q) continue;          // the own pick is already counted
-                    const uint2 mj = meta[j];
-                    const float4 vj = val[j];
-                    const float Ti[4] = {vj.x, vj.y, vj.z, vj.w};
-                    accumulate<FILT, C>(ctx, mj.x, __uint_as_float(mj.y), Ti, mx, my, Tv, B, acc);
-                    if constexpr (EF) {
-                        if (__uint_as_float(mj.y) != 0.0f) cov.add_pick(ctx, mj.x, Ti, mx, my);
-                    }
-                }
-                if constexpr (EF) covered = cov.covered(ctx);
-                wave_lds_sync();
-            }
-        }
-        if (P.valid) {
-            float o[C];
-            const float inv = fast_rcp(B);
-#pragma unroll
-            for (int c = 0; c < C; ++c) o[c] = fmaf(acc[c], inv, Tv[c]);
-            if constexpr (EF) {
-                if (covered) {
-#pragma unroll
-                    for (int c = 0; c < C; ++c) o[c] = cov.sum[c];
-                }
-            }
-            if (scale_out) {                     // Eq. (14) is linear in the texels
-#pragma unroll
-                for (int c = 0; c < C; ++c) o[c] *= t.scale[c];
-            }
-            store_out<C>(a.out[slot], pix, o);
-        }
-    }
-}
-
-__device__ __forceinline__ bool setup_pixel(const Args& a, Pixel& P) {
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    lane_pixel(lane, P.lx, P.ly);
-    P.q = P.ly * 8 + P.lx;
-    const int tx = blockIdx.x * kWavesPerGroup + wave;
-    if (tx * kTile >= a.sw) return false;                    // whole tile off screen
-    P.px = tx * kTile + P.lx;
-    P.py = blockIdx.y * kTile + P.ly;
-    P.valid = (P.px < a.sw) && (P.py < a.sh);
-    const int cx = min(P.px, a.sw - 1), cy = min(P.py, a.sh - 1);
-    const v2f uv = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(a.uv) + ((int64_t)cy * a.sw + cx));
-    P.u = uv.x;
-    P.v = uv.y;
-    return true;
-}
-
-// Random numbers of the slot whose selection slot `slot` uses (itself, or
-// with shared selection the first slot of the same texture size), computed
-// on their own.
-__device__ __forceinline__ void keyed_uniforms(const Args& a, const Pixel& P, int slot, uint32_t& hx, uint32_t& hy) {
-    const int key = a.leader[slot];
-    const uint4 h = pcg4d(make_uint4((uint32_t)P.px, (uint32_t)P.py, a.frame, a.seed + (uint32_t)(key >> 1) * kGolden));
-    hx = (key & 1) ? h.z : h.x;
-    hy = (key & 1) ? h.w : h.y;
-}
-
-// Random numbers of texture slot `slot`: slots 2q and 2q+1 share one pcg4d
-// evaluation keyed with seed + q * golden (first / last two outputs).
-__device__ __forceinline__ void slot_uniforms(const Args& a, const Pixel& P, int slot, uint4& hq, uint32_t& hx,
-                                              uint32_t& hy) {
-    if ((slot & 1) == 0)
-        hq = pcg4d(make_uint4((uint32_t)P.px, (uint32_t)P.py, a.frame, a.seed + (uint32_t)(slot >> 1) * kGolden));
-    hx = (slot & 1) ? hq.z : hq.x;
-    hy = (slot & 1) ? hq.w : hq.y;
-}
-
-__device__ __forceinline__ int payload_of(int fmt) {
-    switch (fmt) {
-    case STF_RGBA16F: return kF16x4;
-    case STF_RG16F: return kF16x2;
-    case STF_R8_UNORM: case STF_R32F: return kF32x1;
-    case STF_LATENT8_F16: case STF_LATENT8_BF16: case STF_LATENT8_FP8: return kLatent;
-    default: return kF32x4;          // RGBA8, RGBA32F, RGBA BF16, RGBA FP8
-    }
-}
-
-// NT textures, unrolled: descriptors are loaded once, and every pick and
-// texel fetch is issued before the first exchange so their latencies overlap.
-template <int FILT, int MODE, int NT, bool DEC, bool EF>
-__global__ __launch_bounds__(kThreads) void forward_kernel(Args a) {
-    // per-wave LDS: records or bins; with a decoder also the deduplicating decode's scratch
-    constexpr bool kLds = MODE == kModeRecords || MODE == kModeBins || DEC;
-    static_assert(kDedupBytes <= kLdsFloatsPerWave * 4, "decode scratch exceeds the wave's LDS");
-    __shared__ __align__(16) float lds_all[kLds ? kWavesPerGroup * kLdsFloatsPerWave : 4];
-    __shared__ __align__(16) uint8_t dec[DEC ? kDecBytes : 16];
-    if constexpr (DEC) {                       // before any wave of the group can leave
-        stage_decoder(a.dec, dec);
-        __syncthreads();
-    }
-    Pixel P;
-    if (!setup_pixel(a, P)) return;
-    float* lds = lds_all + (kLds ? (threadIdx.x >> 6) * kLdsFloatsPerWave : 0);
-    TexArg t[NT];
-#pragma unroll
-    for (int i = 0; i < NT; ++i) t[i] = a.tex[i];
-    SelCtx<FILT> ctx;
-    SlotPick pk[NT];
-    uint4 hq;
-#pragma unroll
-    for (int i = 0; i < NT; ++i) {
-        uint32_t hx, hy;
-        slot_uniforms(a, P, i, hq, hx, hy);
-        ctx.update(P, t[i].w, t[i].h);
-        if (a.leader[i] == i) {
-            pk[i] = pick_slot<FILT>(t[i], ctx, hx, hy);
-        } else {                               // shared selection: the leader's texel of this texture
-#pragma unroll
-            for (int j = 0; j < i; ++j)
-                if (a.leader[i] == j) pk[i] = pk[j];
-            pk[i].raw = fetch_block(t[i], pk[i].sx, pk[i].sy, format_bytes(t[i].fmt));
-        }
-    }
-    BinGeom<AxisCtx<FILT>::N> geom;
-#pragma unroll
-    for (int i = 0; i < NT; ++i) {
-        ctx.update(P, t[i].w, t[i].h);
-        if constexpr (MODE == kModeBins) update_geom<FILT>(geom, P, ctx, t[i].w, t[i].h);
-        switch (payload_of(t[i].fmt)) {
-        case kF16x4: slot_pass<FILT, MODE, kF16x4, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
-        case kF16x2: slot_pass<FILT, MODE, kF16x2, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
-        case kF32x1: slot_pass<FILT, MODE, kF32x1, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
-        case kLatent:
-            if constexpr (DEC) slot_pass<FILT, MODE, kF32x4, true, EF>(a, t[i], i, P, ctx, geom, pk[i], lds, dec);
-            break;
-        default: slot_pass<FILT, MODE, kF32x4, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
-        }
-    }
-}
-
-// ---------------------------------------------------------------- comparison estimators
-//
-// The estimators Sec. 4.1 evaluates before proposing Eq. (14), over the same
-// shared picks: pixel c holds the picks x_i of its footprint's on-screen
-// members i (itself included), each drawn from member i's PMF p_i = f_i.
-// With w_i = f_c(x_i) / p_i(x_i) and n the number of picks:
-//   IS          (1/n) sum_i w_i T_i                                   Eq. (6)
-//   MIS         sum_i f_c(x_i) T_i / sum_j p_j(x_i)   (balance heuristic, n^2 PMFs)
-//   pairwise    sum_i m_i(x_i) w_i T_i, canonical c:  (2n PMFs)
-//     m_i(x) = p_i(x) / ((n-1) p_i(x) + p_c(x)),  m_c(x) = 1/(n-1) sum_{i!=c} p_c(x) / (p_c(x) + (n-1) p_i(x))
-//   regression  (1/n) sum_i [w_i T_i - beta (w_i - 1)],
-//     beta = sum_i (w_i - wbar) w_i T_i / sum_i (w_i - wbar)^2   (0 when all w_i are equal)   Eq. (7)
-//   WIS         Eq. (14) written out plainly (used for its clamped form)
-// Clamping limits the result per channel to the range of the texels with
-// f_c(x_i) > 0. One wave per tile; each lane publishes its pick, PMF,
-// support start, per-axis weights and decoded texel in LDS and every pixel
-// walks its members. Comparison only: not the optimised path.
-
-template <int N>
-struct PickRecord {                  // LDS record of one lane, 16-byte aligned
-    uint32_t s;                      // texel sx | sy << 16
-    float p;                         // own PMF at the pick; 0 for off-screen pixels
-    int bx, by;                      // support start
-    float T[4];
-    float wx[N], wy[N];
-};
-
-template <int N>
-__device__ __forceinline__ float pmf_at(const PickRecord<N>& r, uint32_t s, uint32_t mx, uint32_t my) {
-    uint32_t dx, dy;
-    if (!support_offset<N>(s, r.bx, r.by, mx, my, dx, dy)) return 0.0f;
-    return r.wx[dx] * r.wy[dy];
-}
-
-// Texel of any non-latent format as four floats (zero-padded).
-__device__ __forceinline__ void texel_f4(const TexArg& t, uint4 raw, float* T) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) T[c] = 0.0f;
-    switch (payload_of(t.fmt)) {
-    case kF16x4: { const Texel<kF16x4> x = decode<kF16x4>(raw, t.fmt); for (int c = 0; c < 4; ++c) T[c] = x.ch(c); break; }
-    case kF16x2: { const Texel<kF16x2> x = decode<kF16x2>(raw, t.fmt); T[0] = x.ch(0); T[1] = x.ch(1); break; }
-    case kF32x1: { const Texel<kF32x1> x = decode<kF32x1>(raw, t.fmt); T[0] = x.ch(0); break; }
-    default: { const Texel<kF32x4> x = decode<kF32x4>(raw, t.fmt); for (int c = 0; c < 4; ++c) T[c] = x.ch(c); break; }
-    }
-}
-
-template <int FILT>
-__device__ __forceinline__ void estimator_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
-                                               uint32_t hx, uint32_t hy, float* lds) {
-    constexpr int N = SelCtx<FILT>::N;
-    const TexArg t = a.tex[slot];
-    const uint32_t mx = (uint32_t)t.w - 1u, my = (uint32_t)t.h - 1u;
-    const SlotPick pk = pick_slot<FILT>(t, ctx, hx, hy);
-    PickRecord<N>* rec = reinterpret_cast<PickRecord<N>*>(lds);
-    PickRecord<N> mine;
-    mine.s = pk.sx | (pk.sy << 16);
-    mine.p = P.valid ? ctx.x.wsel(pk.kx) * ctx.y.wsel(pk.ky) : 0.0f;
-    mine.bx = ctx.x.base;
-    mine.by = ctx.y.base;
-    texel_f4(t, block_texel(pk.raw, pk.sx, format_bytes(t.fmt)), mine.T);
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        mine.wx[i] = ctx.x.w(i);
-        mine.wy[i] = ctx.y.w(i);
-    }
-    const int64_t pix = (int64_t)P.py * a.sw + P.px;
-    if (a.sel != nullptr && P.valid) {
-        int2* sp = reinterpret_cast<int2*>(a.sel) + ((int64_t)slot * a.sh * a.sw + pix);
-        *sp = make_int2((int)pk.sx, (int)pk.sy);
-    }
-    rec[P.q] = mine;
-    wave_lds_sync();
-
-    const int fp = a.footprint;
-    const int K = fp == STF_FP_SELF ? 0 : footprint_size(fp, a.lut_k);
-    const int est = a.estimator;
-    // member iteration: the pixel itself first, then the others
-    auto member = [&](int m) -> int {                     // m = -1: the pixel itself; -2: skip
-        if (m < 0) return P.q;
-        const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
-        return j == P.q ? -2 : j;
-    };
-    // pass 1: n, sum of w, clamp range
-    float n = 0.0f, sw = 0.0f;
-    float lo[4], hi[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        lo[c] = __builtin_huge_valf();
-        hi[c] = -__builtin_huge_valf();
-    }
-    for (int m = -1; m < K; ++m) {
-        const int j = member(m);
-        if (j < 0) continue;
-        const PickRecord<N>& r = rec[j];
-        if (r.p == 0.0f) continue;                        // off-screen member
-        n += 1.0f;
-        uint32_t dx, dy;
-        if (support_offset<N>(r.s, ctx.x.base, ctx.y.base, mx, my, dx, dy)) {
-            const float f = ctx.x.wsel(dx) * ctx.y.wsel(dy);
-            sw += f / r.p;
-            if (f > 0.0f) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    lo[c] = fminf(lo[c], r.T[c]);
-                    hi[c] = fmaxf(hi[c], r.T[c]);
-                }
-            }
-        }
-    }
-    const float wbar = sw / fmaxf(n, 1.0f);
-    const float nm1 = fmaxf(n - 1.0f, 1.0f);
-    // pairwise MIS: canonical weight m_c(x_c)
-    float m_c = 1.0f;
-    if (est == STF_EST_PAIRWISE_MIS && n > 1.0f) {
-        m_c = 0.0f;
-        for (int m = 0; m < K; ++m) {
-            const int j = member(m);
-            if (j < 0 || rec[j].p == 0.0f) continue;
-            m_c += mine.p / (mine.p + nm1 * pmf_at<N>(rec[j], mine.s, mx, my));
-        }
-        m_c /= nm1;
-    }
-    // pass 2
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
-    float dw2 = 0.0f, cv = 0.0f;
-    float dwt[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int m = -1; m < K; ++m) {
-        const int j = member(m);
-        if (j < 0) continue;
-        const PickRecord<N>& r = rec[j];
-        if (r.p == 0.0f) continue;
-        uint32_t dx, dy;
-        const float f = support_offset<N>(r.s, ctx.x.base, ctx.y.base, mx, my, dx, dy)
-                            ? ctx.x.wsel(dx) * ctx.y.wsel(dy) : 0.0f;
-        const float w = f / r.p;
-        float coef;
-        switch (est) {
-        case STF_EST_IS: coef = w; break;
-        case STF_EST_MIS: {
-            float den = 0.0f;                              // sum over all members k of p_k(x_i)
-            for (int mm = -1; mm < K; ++mm) {
-                const int k = member(mm);
-                if (k < 0 || rec[k].p == 0.0f) continue;
-                den += pmf_at<N>(rec[k], r.s, mx, my);
-            }
-            coef = f / den;                                // den >= p_i(x_i) > 0
-            break;
-        }
-        case STF_EST_PAIRWISE_MIS:
-            coef = (m < 0 ? m_c : r.p / (nm1 * r.p + f)) * w;
-            break;
-        case STF_EST_REGRESSION: {
-            const float d = w - wbar;
-            dw2 = fmaf(d, d, dw2);
-            cv += w - 1.0f;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) dwt[c] = fmaf(d * w, r.T[c], dwt[c]);
-            coef = w;
-            break;
-        }
-        default: coef = w; break;                          // WIS numerator
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = fmaf(coef, r.T[c], acc[c]);
-    }
-    float o[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        switch (est) {
-        case STF_EST_IS: o[c] = acc[c] / n; break;
-        case STF_EST_MIS: case STF_EST_PAIRWISE_MIS: o[c] = acc[c]; break;
-        case STF_EST_REGRESSION: {
-            const float beta = dw2 > 0.0f ? dwt[c] / dw2 : 0.0f;
-            o[c] = fmaf(-beta, cv, acc[c]) / n;
-            break;
-        }
-        default: o[c] = acc[c] / sw; break;
-        }
-        if (a.flags & STF_REUSE_CLAMP) o[c] = fminf(fmaxf(o[c], lo[c]), hi[c]);
-        if (t.has_scale) o[c] *= t.scale[c];
-    }
-    wave_lds_sync();                                       // records read before the next slot
-    if (P.valid) {
-        switch (t.ch) {
-        case 4: store_out<4>(a.out[slot], pix, o); break;
-        case 2: store_out<2>(a.out[slot], pix, o); break;
-        default: store_out<1>(a.out[slot], pix, o); break;
-        }
-    }
-}
-
-template <int FILT>
-__global__ __launch_bounds__(kThreads) void estimator_kernel(Args a) {
-    __shared__ __align__(16) float lds_all[kWavesPerGroup * kLdsFloatsPerWave];
-    static_assert(64 * sizeof(PickRecord<SelCtx<FILT>::N>) <= kLdsFloatsPerWave * sizeof(float),
-                  "pick records exceed the wave's LDS");
-    Pixel P;
-    if (!setup_pixel(a, P)) return;
-    float* lds = lds_all + (threadIdx.x >> 6) * kLdsFloatsPerWave;
-    SelCtx<FILT> ctx;
-    for (int slot = 0; slot < a.ntex; ++slot) {
-        uint32_t hx, hy;
-        keyed_uniforms(a, P, slot, hx, hy);
-        ctx.update(P, a.tex[slot].w, a.tex[slot].h);
-        estimator_slot<FILT>(a, slot, P, ctx, hx, hy, lds);
-    }
-}
-
-// Deterministic filter, Eq. (3): sum over the support of f_c * T.
-template <int FILT, int PL, bool LAT = false>
-__device__ __forceinline__ void reference_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
-                                               const uint8_t* dec = nullptr, uint8_t* scratch = nullptr) {
-    constexpr int N = SelCtx<FILT>::N;
-    constexpr int C = Texel<PL>::C;
-    const TexArg t = a.tex[slot];
-    const uint32_t mx = (uint32_t)t.w - 1u, my = (uint32_t)t.h - 1u;
-    const int bpp = format_bytes(t.fmt);
-    float acc[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = 0.0f;
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-        const uint32_t y = (uint32_t)(ctx.y.base + b) & my;
-#pragma unroll
-        for (int aa = 0; aa < N; ++aa) {
-            const uint32_t x = (uint32_t)(ctx.x.base + aa) & mx;
-            Texel<PL> T;
-            if constexpr (LAT)                       // every tap decodes (the full-filter cost)
-                decode_latent_dedup(dec, latent_bf16(block_texel(fetch_block(t, x, y, bpp), x, bpp), t), x, y, mx, my,
-                                    scratch, T.v);
-            else
-                T = decode<PL>(block_texel(fetch_block(t, x, y, bpp), x, bpp), t.fmt);
-            const float w = ctx.wxy[b * N + aa];
-#pragma unroll
-            for (int c = 0; c < C; ++c) acc[c] = fmaf(w, T.ch(c), acc[c]);
-        }
-    }
-    if (P.valid) {
-        if (!LAT && t.has_scale) {
-#pragma unroll
-            for (int c = 0; c < C; ++c) acc[c] *= t.scale[c];
-        }
-        store_out<C>(a.out[slot], (int64_t)P.py * a.sw + P.px, acc);
-    }
-}
-
-template <int FILT, bool DEC>
-__global__ __launch_bounds__(kThreads) void reference_kernel(Args a) {
-    __shared__ __align__(16) uint8_t dec[DEC ? kDecBytes : 16];
-    __shared__ __align__(16) uint8_t dscratch[DEC ? kWavesPerGroup * kDedupBytes : 16];
-    if constexpr (DEC) {
-        stage_decoder(a.dec, dec);
-        __syncthreads();
-    }
-    Pixel P;
-    if (!setup_pixel(a, P)) return;
-    SelCtx<FILT> ctx;
-    for (int slot = 0; slot < a.ntex; ++slot) {
-        ctx.update(P, a.tex[slot].w, a.tex[slot].h);
-        switch (payload_of(a.tex[slot].fmt)) {
-        case kF16x4: reference_slot<FILT, kF16x4>(a, slot, P, ctx); break;
-        case kF16x2: reference_slot<FILT, kF16x2>(a, slot, P, ctx); break;
-        case kF32x1: reference_slot<FILT, kF32x1>(a, slot, P, ctx); break;
-        case kLatent:
-            if constexpr (DEC)
-                reference_slot<FILT, kF32x4, true>(a, slot, P, ctx, dec, dscratch + (threadIdx.x >> 6) * kDedupBytes);
-            break;
-        default: reference_slot<FILT, kF32x4>(a, slot, P, ctx); break;
-        }
-    }
-}
 
 // Pack the decoder MLP for decode_latent: BF16 A operands in lane order with
 // the K permutation of dec_unit, b1 folded into layer 1 as K index 8, b2 and
@@ -1044,203 +49,6 @@ __global__ __launch_bounds__(256) void decoder_pack_kernel(stf_mlp m, uint8_t* o
     for (int idx = threadIdx.x; idx < 32; idx += blockDim.x) {
         const int h = idx >> 4, j = idx & 15, r = acc_row(j, h);
         C3[idx] = r < 4 ? m.b3[r] : 0.0f;
-    }
-}
-
-// ============================================================================
-// adjoint of Eq. (14)
-// ============================================================================
-//
-// out_c = sum_i a_ci T[x_i] with a_ci = w_ci / B_c, w_ci = f_c(x_i) r_i and
-// B_c = sum_i w_ci; the weights depend on UVs and random numbers only, so
-// dL/dT[x] += sum_c sum_{i in S(c), x_i = x} a_ci dL/dout_c. The kernel
-// recomputes every pick exactly as the forward pass does, recomputes B_c,
-// and scatters. For the whole tile the sum over i collapses per texel:
-// dL/dT[x] = N_x sum_c f_c(x) q_c with N_x = sum_{i: x_i = x} r_i and
-// q_c = dL/dout_c / B_c, which is accumulated in LDS bins and flushed with
-// one global atomic per populated bin and channel.
-
-template <int C>
-__device__ __forceinline__ void atomic_texel(float* g, int tw, uint32_t s, const float* v, float scale) {
-    float* p = g + ((int64_t)(s >> 16) * tw + (s & 0xFFFFu)) * C;
-#pragma unroll
-    for (int c = 0; c < C; ++c) unsafeAtomicAdd(p + c, v[c] * scale);
-}
-
-template <int FILT, int MODE, int C>
-__device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
-                                              uint32_t hx, uint32_t hy, float* lds) {
-    constexpr int N = SelCtx<FILT>::N;
-    const TexArg t = a.tex[slot];
-    const int lane = lane_id();
-    const int kx = ctx.x.pick(hx);
-    const int ky = ctx.y.pick(hy);
-    const uint32_t mx = (uint32_t)t.w - 1u, my = (uint32_t)t.h - 1u;
-    const uint32_t sx = (uint32_t)(ctx.x.base + kx) & mx;
-    const uint32_t sy = (uint32_t)(ctx.y.base + ky) & my;
-    const uint32_t s = sx | (sy << 16);
-    float* grad = a.out[slot];                              // dL/dT, [th][tw][C]
-    const int64_t pix = (int64_t)P.py * a.sw + P.px;
-    float g[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) g[c] = P.valid ? a.dout[slot][pix * C + c] * t.scale[c] : 0.0f;
-
-    if constexpr (MODE == kModeStf) {
-        if (P.valid) atomic_texel<C>(grad, t.w, s, g, 1.0f);
-        return;
-    } else {
-        const float r = P.valid ? fast_rcp(ctx.x.wsel(kx) * ctx.y.wsel(ky)) : 0.0f;
-        if constexpr (MODE == kModeQuad) {
-            uint32_t si[3];
-            float ri[3];
-            si[0] = quad_xor<1>(s); ri[0] = quad_xor<1>(r);
-            si[1] = quad_xor<2>(s); ri[1] = quad_xor<2>(r);
-            si[2] = quad_xor<3>(s); ri[2] = quad_xor<3>(r);
-            float B = 1.0f, f[3];
-            bool in[3];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                uint32_t dx, dy;
-                in[m] = support_offset<N>(si[m], ctx.x.base, ctx.y.base, mx, my, dx, dy);
-                f[m] = ctx.x.wsel(dx) * ctx.y.wsel(dy);
-                if (in[m]) B += f[m] * ri[m];
-            }
-            if (P.valid) {
-                const float inv = fast_rcp(B);
-                atomic_texel<C>(grad, t.w, s, g, inv);
-#pragma unroll
-                for (int m = 0; m < 3; ++m)
-                    if (in[m] && ri[m] != 0.0f) atomic_texel<C>(grad, t.w, si[m], g, f[m] * ri[m] * inv);
-            }
-        } else {
-            bool use_bins = false;
-            if constexpr (MODE == kModeBins) {
-                int base_x, base_y;
-                uint32_t rx, ry;
-                use_bins = bin_window<N>(P, ctx.x.base, ctx.y.base, mx, my, t.w, t.h, base_x, base_y, rx, ry);
-                if (use_bins) {
-                    // LDS: Nb float [kBins] (sum of 1/p per texel), N64 u64 [kBins]
-                    // (its fixed-point accumulator), Q64 i64 [kBins][C] (sum of
-                    // f_c(x) q_c in fixed point). Integer LDS atomics do not
-                    // serialise on shared addresses the way FP32 ones do.
-                    float* Nb = lds;
-                    uint64_t* N64 = reinterpret_cast<uint64_t*>(lds + kBwdN64Offset);
-                    uint64_t* Q64 = N64 + kBins;
-                    for (int i = lane; i < kBins * (1 + C); i += 64) N64[i] = 0ull;
-                    for (int i = lane; i < kBins; i += 64) Nb[i] = 0.0f;
-                    const int my_bin = (int)(ry + ky) * kBinG + (int)(rx + kx);
-                    const uint32_t e = P.valid ? (__float_as_uint(r) >> 23) : 0u;
-                    const uint32_t e_max = wave_max(e);
-                    const bool fixed = __builtin_amdgcn_ballot_w64(P.valid && e + 33u < e_max) == 0;
-                    wave_lds_sync();
-                    if (fixed) {
-                        if (P.valid) atomicAdd(reinterpret_cast<unsigned long long*>(&N64[my_bin]),
-                                               (unsigned long long)fixed_of(r, e_max));
-                        wave_lds_sync();
-                        for (int i = lane; i < kBins; i += 64) Nb[i] = float_of(N64[i], e_max);
-                    } else {
-                        if (P.valid) atomicAdd(&Nb[my_bin], r);
-                    }
-                    wave_lds_sync();
-                    const int bin0 = (int)ry * kBinG + (int)rx;
-                    float B = 0.0f;
-#pragma unroll
-                    for (int b = 0; b < N; ++b)
-#pragma unroll
-                        for (int aa = 0; aa < N; ++aa) B += ctx.wxy[b * N + aa] * Nb[bin0 + b * kBinG + aa];
-                    // |f_c(x) q_c| <= |dL/dout_c| (B >= 1: the own pick contributes
-                    // f_c / p_c = 1), so the wave's largest gradient exponent fixes
-                    // the scale; 64 terms of at most 2^58 units fit in 64 bits
-                    float gmax = 0.0f;
-#pragma unroll
-                    for (int c = 0; c < C; ++c) gmax = fmaxf(gmax, fabsf(g[c]));
-                    const uint32_t eq = wave_max(__float_as_uint(gmax) >> 23) + 1u;
-                    if (P.valid) {
-                        const float inv = fast_rcp(B);
-                        // lanes visit their support in rotated orders, so one atomic
-                        // instruction mostly hits N*N different bins even where every
-                        // pixel of the tile has the same support (high magnification)
-                        const int rot = lane % (N * N);
-#pragma unroll
-                        for (int k = 0; k < N * N; ++k) {
-                            const int kk = (k + rot) % (N * N);
-                            const int aa = kk % N, b = kk / N;
-                            const int idx = bin0 + b * kBinG + aa;
-                            if (Nb[idx] != 0.0f) {
-                                const float f = ctx.x.wsel((uint32_t)aa) * ctx.y.wsel((uint32_t)b) * inv;
-#pragma unroll
-                                for (int c = 0; c < C; ++c)
-                                    atomicAdd(reinterpret_cast<unsigned long long*>(&Q64[idx * C + c]),
-                                              (unsigned long long)signed_fixed_of(f * g[c], eq));
-                            }
-                        }
-                    }
-                    wave_lds_sync();
-                    // flush: lane handles bins lane, lane + 64, ...
-                    for (int idx = lane; idx < kBins; idx += 64) {
-                        const float nx = Nb[idx];
-                        if (nx != 0.0f) {
-                            const uint32_t tx = (uint32_t)(base_x + (idx % kBinG)) & mx;
-                            const uint32_t ty = (uint32_t)(base_y + (idx / kBinG)) & my;
-                            float q[C];
-#pragma unroll
-                            for (int c = 0; c < C; ++c) q[c] = signed_float_of(Q64[idx * C + c], eq);
-                            atomic_texel<C>(grad, t.w, tx | (ty << 16), q, nx);
-                        }
-                    }
-                    wave_lds_sync();
-                }
-            }
-            if (!use_bins) {
-                uint2* meta = reinterpret_cast<uint2*>(lds);
-                meta[P.q] = make_uint2(s, __float_as_uint(r));
-                wave_lds_sync();
-                const int fp = (MODE == kModeBins) ? (int)STF_FP_TILE8X8 : a.footprint;
-                const int K = footprint_size(fp, a.lut_k);
-                float B = 1.0f;
-                for (int m = 0; m < K; ++m) {
-                    const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
-                    if (j == P.q) continue;
-                    const uint2 mj = meta[j];
-                    uint32_t dx, dy;
-                    if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy))
-                        B += ctx.x.wsel(dx) * ctx.y.wsel(dy) * __uint_as_float(mj.y);
-                }
-                if (P.valid) {
-                    const float inv = fast_rcp(B);
-                    atomic_texel<C>(grad, t.w, s, g, inv);
-                    for (int m = 0; m < K; ++m) {
-                        const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
-                        if (j == P.q) continue;
-                        const uint2 mj = meta[j];
-                        const float rj = __uint_as_float(mj.y);
-                        uint32_t dx, dy;
-                        if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy) && rj != 0.0f)
-                            atomic_texel<C>(grad, t.w, mj.x, g, ctx.x.wsel(dx) * ctx.y.wsel(dy) * rj * inv);
-                    }
-                }
-                wave_lds_sync();
-            }
-        }
-    }
-}
-
-template <int FILT, int MODE>
-__global__ __launch_bounds__(kThreads) void backward_kernel(Args a) {
-    constexpr int kPerWave = kBwdLdsFloatsPerWave > kLdsFloatsPerWave ? kBwdLdsFloatsPerWave : kLdsFloatsPerWave;
-    __shared__ __align__(16) float lds_all[kWavesPerGroup * kPerWave];
-    Pixel P;
-    if (!setup_pixel(a, P)) return;
-    float* lds = lds_all + (threadIdx.x >> 6) * kPerWave;
-    SelCtx<FILT> ctx;
-    for (int slot = 0; slot < a.ntex; ++slot) {
-        uint32_t hx, hy;
-        keyed_uniforms(a, P, slot, hx, hy);
-        ctx.update(P, a.tex[slot].w, a.tex[slot].h);
-        const int ch = a.tex[slot].ch;
-        if (ch == 4) backward_slot<FILT, MODE, 4>(a, slot, P, ctx, hx, hy, lds);
-        else if (ch == 2) backward_slot<FILT, MODE, 2>(a, slot, P, ctx, hx, hy, lds);
-        else backward_slot<FILT, MODE, 1>(a, slot, P, ctx, hx, hy, lds);
     }
 }
 
@@ -1410,38 +218,11 @@ int check_reuse(const stf_reuse* r) {
     return STF_OK;
 }
 
-dim3 grid_of(const stf::Args& a) {
-    return dim3((unsigned)((a.sw + stf::kTile * stf::kWavesPerGroup - 1) / (stf::kTile * stf::kWavesPerGroup)),
-                (unsigned)((a.sh + stf::kTile - 1) / stf::kTile));
-}
 
 int finish_launch(const char* what) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(STF_EHIP, "%s launch failed: %s", what, hipGetErrorString(e));
     return STF_OK;
-}
-
-template <int FILT, int MODE, bool DEC, bool EF>
-void launch_nt(const stf::Args& a, hipStream_t s) {
-    const dim3 g = grid_of(a), b(stf::kThreads);
-    switch (a.ntex) {
-    case 1: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 1, DEC, EF>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 2, DEC, EF>), g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 3, DEC, EF>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((stf::forward_kernel<FILT, MODE, 4, DEC, EF>), g, b, 0, s, a); break;
-    }
-}
-
-template <int FILT, int MODE>
-void launch_forward(const stf::Args& a, hipStream_t s) {
-    const bool dec = a.dec != nullptr;
-    if constexpr (MODE == stf::kModeStf) {     // one pick: exact filtering changes nothing
-        dec ? launch_nt<FILT, MODE, true, false>(a, s) : launch_nt<FILT, MODE, false, false>(a, s);
-    } else {
-        const bool ef = (a.flags & STF_REUSE_EXACT_FILTERING) != 0;
-        if (dec) ef ? launch_nt<FILT, MODE, true, true>(a, s) : launch_nt<FILT, MODE, true, false>(a, s);
-        else ef ? launch_nt<FILT, MODE, false, true>(a, s) : launch_nt<FILT, MODE, false, false>(a, s);
-    }
 }
 
 int forward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
@@ -1473,15 +254,15 @@ int forward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const s
     if (r != nullptr && (r->estimator != STF_EST_WIS || (r->flags & STF_REUSE_CLAMP))) {
         if (a.dec != nullptr) return fail(STF_EUNSUPPORTED, "comparison estimators do not decode latent textures");
         a.estimator = r->estimator;
-        if (cubic) hipLaunchKernelGGL((stf::estimator_kernel<1>), grid_of(a), dim3(stf::kThreads), 0, s, a);
-        else hipLaunchKernelGGL((stf::estimator_kernel<0>), grid_of(a), dim3(stf::kThreads), 0, s, a);
+        if (cubic) hipLaunchKernelGGL((stf::estimator_kernel<1>), stf::grid_of(a), dim3(stf::kThreads), 0, s, a);
+        else hipLaunchKernelGGL((stf::estimator_kernel<0>), stf::grid_of(a), dim3(stf::kThreads), 0, s, a);
         return finish_launch("estimator");
     }
     switch (mode) {
-    case stf::kModeStf: cubic ? launch_forward<1, stf::kModeStf>(a, s) : launch_forward<0, stf::kModeStf>(a, s); break;
-    case stf::kModeQuad: cubic ? launch_forward<1, stf::kModeQuad>(a, s) : launch_forward<0, stf::kModeQuad>(a, s); break;
-    case stf::kModeRecords: cubic ? launch_forward<1, stf::kModeRecords>(a, s) : launch_forward<0, stf::kModeRecords>(a, s); break;
-    default: cubic ? launch_forward<1, stf::kModeBins>(a, s) : launch_forward<0, stf::kModeBins>(a, s); break;
+    case stf::kModeStf: cubic ? stf::launch_forward<1, stf::kModeStf>(a, s) : stf::launch_forward<0, stf::kModeStf>(a, s); break;
+    case stf::kModeQuad: cubic ? stf::launch_forward<1, stf::kModeQuad>(a, s) : stf::launch_forward<0, stf::kModeQuad>(a, s); break;
+    case stf::kModeRecords: cubic ? stf::launch_forward<1, stf::kModeRecords>(a, s) : stf::launch_forward<0, stf::kModeRecords>(a, s); break;
+    default: cubic ? stf::launch_forward<1, stf::kModeBins>(a, s) : stf::launch_forward<0, stf::kModeBins>(a, s); break;
     }
     return finish_launch("forward");
 }
@@ -1513,7 +294,7 @@ int stf_filter_reference(const stf_texture* tex, int32_t ntex, const stf_screen*
     if ((rc = check_outputs(out, ntex)) != STF_OK) return rc;
     for (int i = 0; i < ntex; ++i) a.out[i] = out[i];
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    const dim3 g = grid_of(a), b(stf::kThreads);
+    const dim3 g = stf::grid_of(a), b(stf::kThreads);
     const bool cubic = p->filter == STF_BICUBIC_BSPLINE;
     if (a.dec != nullptr) {
         if (cubic) hipLaunchKernelGGL((stf::reference_kernel<1, true>), g, b, 0, s, a);
@@ -1569,7 +350,7 @@ int stf_backward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, co
     }
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     const bool cubic = p->filter == STF_BICUBIC_BSPLINE;
-    const dim3 g = grid_of(a), b(stf::kThreads);
+    const dim3 g = stf::grid_of(a), b(stf::kThreads);
 #define STF_BW(F, M) hipLaunchKernelGGL((stf::backward_kernel<F, M>), g, b, 0, s, a)
     switch (mode) {
     case stf::kModeStf: if (cubic) STF_BW(1, stf::kModeStf); else STF_BW(0, stf::kModeStf); break;
