@@ -261,6 +261,7 @@ def latent_form(torch, stf, w, steps, warmup):
     tex = [torch.from_numpy(w.quantize(lat, "fp8", sc)).view(torch.float8_e4m3fn).cuda()]
     layers = [(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for a, b in w.decoder_weights(0)]
     dec = stf.pack_decoder(layers)
+    dec8 = stf.pack_decoder(layers, precision="fp8")
     scales = [list(sc)]
     out = torch.empty((H, W, 4), dtype=torch.float32, device=uv.device)
     t_r = launch_time(torch, lambda: stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, out=[out], scales=scales,
@@ -279,8 +280,16 @@ def latent_form(torch, stf, w, steps, warmup):
         return {"avg_launch_us": round(t * 1e6, 2), "Mpixel_s": round(px / t / 1e6, 1),
                 "decode_tflops": round(px * decodes * DECODE_FLOPS_PER_TEXEL / t / 1e12, 1)}
 
+    t_r8 = launch_time(torch, lambda: stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, out=[out], scales=scales,
+                                                       decoder=dec8), steps, warmup)
+    t_s8 = launch_time(torch, lambda: stf.filter(tex, uv, "bicubic", 0, 0, out=[out], scales=scales, decoder=dec8),
+                       steps, warmup)
+    o_r8 = stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, scales=scales, decoder=dec8)[0]
+    fp8 = {"reuse_tile8x8": row(t_r8, 1), "stf_1sample": row(t_s8, 1),
+           "psnr_reuse_db": round(psnr_rgb(torch, o_r8, ref, peak), 2),
+           "against": "the BF16 decoder's deterministic filter"}
     return {"workload": "1024^2x8 FP8 E4M3 latents + per-channel scales, MLP 8-64-64-4 BF16 on MFMA, "
-                        "1920x1080 plane 4x-16x, bicubic",
+                        "1920x1080 plane 4x-16x, bicubic", "fp8_decoder": fp8,
             "magnification": info["mag_min_axis"],
             "reuse_tile8x8": row(t_r, 1), "stf_1sample": row(t_s, 1), "full_filter_16_decodes": row(t_f, 16),
             "psnr_reuse_db": round(psnr_rgb(torch, o_r, ref, peak), 2),

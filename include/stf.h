@@ -239,11 +239,21 @@ int stf_backward(const stf_texture* tex, int32_t ntex, const stf_screen* scr,
  * Latent decoder MLP of the neural-texture setting (Sec. 1, Sec. 5.6):
  *     RGBA = W3 ReLU(W2 ReLU(W1 x + b1) + b2) + b3,   x = 8 latent channels.
  * Arrays are device FP32, row-major [out][in]. Latent textures are decoded
- * per picked texel on the matrix cores with BF16 operands and FP32
- * accumulation: w1, b1, w2 and w3 are rounded to BF16 (round to nearest
- * even) when packed, b2 and b3 stay FP32, the latents (times their scale)
- * and the hidden activations are rounded to BF16.
+ * per picked texel on the matrix cores with FP32 accumulation, in BF16 or
+ * FP8 operands (precision below).
  */
+/* Decoder arithmetic (stf_mlp.precision):
+ *   STF_DECODER_BF16  v_mfma_f32_32x32x16_bf16: w1, b1, w2, w3 rounded to BF16,
+ *                     b2, b3 FP32; latents (times their scale) and hidden
+ *                     activations rounded to BF16 (RN).
+ *   STF_DECODER_FP8   v_mfma_f32_32x32x16_fp8_fp8: each W_l stored as FP8 E4M3
+ *                     of W_l / s_l with s_l = max|W_l| / 448, biases FP32;
+ *                     latents (times their scale) and hidden activations
+ *                     rounded to FP8 E4M3 (RN). Twice the matrix-core rate,
+ *                     about 2^-4 relative rounding per value. */
+#define STF_DECODER_BF16 0
+#define STF_DECODER_FP8 1
+
 typedef struct stf_mlp {
     const float* w1;        /* [64][8] */
     const float* b1;        /* [64] */
@@ -251,9 +261,11 @@ typedef struct stf_mlp {
     const float* b2;        /* [64] */
     const float* w3;        /* [4][64] */
     const float* b3;        /* [4] */
+    int32_t precision;      /* STF_DECODER_BF16 or STF_DECODER_FP8 */
+    int32_t reserved;       /* must be 0 */
 } stf_mlp;
 
-#define STF_DECODER_BYTES 14720
+#define STF_DECODER_BYTES 14736
 
 /*
  * Pack `mlp` into the device buffer `packed` (STF_DECODER_BYTES, 16-byte

@@ -55,10 +55,12 @@ class Texture(ctypes.Structure):
 
 
 class Mlp(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_void_p) for n in ("w1", "b1", "w2", "b2", "w3", "b3")]
+    _fields_ = [(n, ctypes.c_void_p) for n in ("w1", "b1", "w2", "b2", "w3", "b3")] + \
+               [("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
-DECODER_BYTES = 14720
+DECODER_BYTES = 14736
+DECODER_PRECISIONS = {"bf16": 0, "fp8": 1}
 
 
 class FootprintParams(ctypes.Structure):
@@ -140,10 +142,11 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def pack_decoder(layers, stream=None):
+def pack_decoder(layers, stream=None, precision="bf16"):
     """Pack the latent decoder MLP [(W1 [64,8], b1), (W2 [64,64], b2),
-    (W3 [4,64], b3)] (float32 GPU tensors) with stf_decoder_pack. Returns
-    the packed uint8 GPU tensor to pass as `decoder=`."""
+    (W3 [4,64], b3)] (float32 GPU tensors) with stf_decoder_pack for BF16 or
+    FP8 matrix-core arithmetic. Returns the packed uint8 GPU tensor to pass
+    as `decoder=`."""
     import torch
     shapes = [((64, 8), (64,)), ((64, 64), (64,)), ((4, 64), (4,))]
     if len(layers) != 3:
@@ -155,7 +158,7 @@ def pack_decoder(layers, stream=None):
                 raise ValueError(f"decoder arrays must be contiguous float32 GPU tensors of shape {sh}")
             flat.append(t)
     packed = torch.empty(DECODER_BYTES, dtype=torch.uint8, device=flat[0].device)
-    m = Mlp(*[t.data_ptr() for t in flat])
+    m = Mlp(*[t.data_ptr() for t in flat], DECODER_PRECISIONS[precision], 0)
     _check(library().stf_decoder_pack(ctypes.byref(m), ctypes.c_void_p(packed.data_ptr()), _stream_handle(stream)))
     return packed
 

@@ -14,11 +14,37 @@
 
 namespace stf {
 
-// Pack the decoder MLP for decode_latent: BF16 A operands in lane order with
-// the K permutation of dec_unit, b1 folded into layer 1 as K index 8, b2 and
-// b3 as FP32 accumulator start values. One workgroup.
+// Pack the decoder MLP for decode_latent. BF16: A operands in lane order
+// with the K permutation of dec_unit, b1 folded into layer 1 as K index 8,
+// b2 and b3 as FP32 accumulator start values. FP8: per-layer weight scale
+// s_l = max|W_l| / 448, A operands W_l / s_l as FP8 E4M3 in the same lane
+// order (8 one-byte K values per lane), every bias as b_l / s_l start
+// values. One workgroup of 256 threads.
 __global__ __launch_bounds__(256) void decoder_pack_kernel(stf_mlp m, uint8_t* out) {
-    u32x4* A = reinterpret_cast<u32x4*>(out);
+    __shared__ float red[3][256];
+    DecHeader* hd = reinterpret_cast<DecHeader*>(out);
+    const bool fp8 = m.precision == STF_DECODER_FP8;
+    float sc[3] = {1.0f, 1.0f, 1.0f};
+    if (fp8) {
+        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+        for (int i = threadIdx.x; i < 64 * 8; i += 256) a0 = fmaxf(a0, fabsf(m.w1[i]));
+        for (int i = threadIdx.x; i < 64 * 64; i += 256) a1 = fmaxf(a1, fabsf(m.w2[i]));
+        for (int i = threadIdx.x; i < 4 * 64; i += 256) a2 = fmaxf(a2, fabsf(m.w3[i]));
+        red[0][threadIdx.x] = a0;
+        red[1][threadIdx.x] = a1;
+        red[2][threadIdx.x] = a2;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w)
+                for (int l = 0; l < 3; ++l) red[l][threadIdx.x] = fmaxf(red[l][threadIdx.x], red[l][threadIdx.x + w]);
+            __syncthreads();
+        }
+        for (int l = 0; l < 3; ++l) sc[l] = red[l][0] > 0.0f ? red[l][0] / 448.0f : 1.0f;
+    }
+    if (threadIdx.x == 0) {
+        hd->precision = fp8 ? STF_DECODER_FP8 : STF_DECODER_BF16;
+        for (int l = 0; l < 3; ++l) hd->scale[l] = sc[l];
+    }
     for (int idx = threadIdx.x; idx < 14 * 64; idx += blockDim.x) {
         const int o = idx >> 6, lane = idx & 63, h = lane >> 5, row = lane & 31;
         float v[8];
@@ -27,28 +53,41 @@ __global__ __launch_bounds__(256) void decoder_pack_kernel(stf_mlp m, uint8_t* o
             const int k = 8 * h + t;
             if (o < 2) {                                      // layer 1, row tile o
                 const int u = 32 * o + row;
-                v[t] = h == 0 ? m.w1[u * 8 + t] : (t == 0 ? m.b1[u] : 0.0f);
+                v[t] = h == 0 ? m.w1[u * 8 + t] / sc[0] : ((t == 0 && !fp8) ? m.b1[u] : 0.0f);
             } else if (o < 10) {                              // layer 2, row tile, K step
                 const int mt = (o - 2) >> 2, st = (o - 2) & 3;
-                v[t] = m.w2[(32 * mt + row) * 64 + dec_unit(st, k)];
+                v[t] = m.w2[(32 * mt + row) * 64 + dec_unit(st, k)] / sc[1];
             } else {                                          // layer 3, K step (rows >= 4 are padding)
-                v[t] = row < 4 ? m.w3[row * 64 + dec_unit(o - 10, k)] : 0.0f;
+                v[t] = row < 4 ? m.w3[row * 64 + dec_unit(o - 10, k)] / sc[2] : 0.0f;
             }
         }
-        u32x4 q;
+        if (fp8) {
+            uint32_t w[2];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) q[i] = pack_bf16(v[2 * i], v[2 * i + 1]);
-        A[idx] = q;
+            for (int i = 0; i < 2; ++i) {
+                int x = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * i], v[4 * i + 1], 0, false);
+                x = __builtin_amdgcn_cvt_pk_fp8_f32(v[4 * i + 2], v[4 * i + 3], x, true);
+                w[i] = (uint32_t)x;
+            }
+            reinterpret_cast<uint2*>(out + kF8A1)[idx] = make_uint2(w[0], w[1]);
+        } else {
+            u32x4 q;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) q[i] = pack_bf16(v[2 * i], v[2 * i + 1]);
+            reinterpret_cast<u32x4*>(out + kDecA1)[idx] = q;
+        }
     }
-    float* C2 = reinterpret_cast<float*>(out + kDecC2);
+    float* C1 = reinterpret_cast<float*>(out + kF8C1);
+    float* C2 = reinterpret_cast<float*>(out + (fp8 ? kF8C2 : kDecC2));
+    float* C3 = reinterpret_cast<float*>(out + (fp8 ? kF8C3 : kDecC3));
     for (int idx = threadIdx.x; idx < 64; idx += blockDim.x) {
         const int mt = idx >> 5, h = (idx >> 4) & 1, j = idx & 15;
-        C2[idx] = m.b2[32 * mt + acc_row(j, h)];
+        if (fp8) C1[idx] = m.b1[32 * mt + acc_row(j, h)] / sc[0];
+        C2[idx] = m.b2[32 * mt + acc_row(j, h)] / sc[1];
     }
-    float* C3 = reinterpret_cast<float*>(out + kDecC3);
     for (int idx = threadIdx.x; idx < 32; idx += blockDim.x) {
         const int h = idx >> 4, j = idx & 15, r = acc_row(j, h);
-        C3[idx] = r < 4 ? m.b3[r] : 0.0f;
+        C3[idx] = r < 4 ? m.b3[r] / sc[2] : 0.0f;
     }
 }
 
@@ -315,6 +354,9 @@ int stf_decoder_pack(const stf_mlp* mlp, void* packed, void* hip_stream) {
         if ((reinterpret_cast<uintptr_t>(ws[i]) & 3) != 0) return fail(STF_EINVAL, "mlp array %d not 4-byte aligned", i);
     }
     if ((reinterpret_cast<uintptr_t>(packed) & 15) != 0) return fail(STF_EINVAL, "packed buffer not aligned to 16 bytes");
+    if (mlp->precision != STF_DECODER_BF16 && mlp->precision != STF_DECODER_FP8)
+        return fail(STF_EINVAL, "unknown decoder precision %d", mlp->precision);
+    if (mlp->reserved != 0) return fail(STF_EINVAL, "mlp reserved field must be 0");
     static_assert(stf::kDecBytes == STF_DECODER_BYTES, "packed decoder size");
     hipLaunchKernelGGL(stf::decoder_pack_kernel, dim3(1), dim3(256), 0, static_cast<hipStream_t>(hip_stream), *mlp,
                        static_cast<uint8_t*>(packed));

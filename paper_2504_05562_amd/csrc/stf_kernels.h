@@ -493,7 +493,7 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
     const uint32_t sx = pk.sx, sy = pk.sy;
     Texel<PL> T;
     if constexpr (LAT)
-        decode_latent_dedup(dec, latent_bf16(block_texel(pk.raw, sx, format_bytes(t.fmt)), t), sx, sy, mx, my,
+        decode_latent_dedup(dec, latent_operand(dec, block_texel(pk.raw, sx, format_bytes(t.fmt)), t), sx, sy, mx, my,
                             reinterpret_cast<uint8_t*>(lds), T.v);
     else
         T = decode<PL>(block_texel(pk.raw, sx, format_bytes(t.fmt)), t.fmt);
@@ -966,7 +966,7 @@ __device__ __forceinline__ void reference_slot(const Args& a, int slot, const Pi
             const uint32_t x = (uint32_t)(ctx.x.base + aa) & mx;
             Texel<PL> T;
             if constexpr (LAT)                       // every tap decodes (the full-filter cost)
-                decode_latent_dedup(dec, latent_bf16(block_texel(fetch_block(t, x, y, bpp), x, bpp), t), x, y, mx, my,
+                decode_latent_dedup(dec, latent_operand(dec, block_texel(fetch_block(t, x, y, bpp), x, bpp), t), x, y, mx, my,
                                     scratch, T.v);
             else
                 T = decode<PL>(block_texel(fetch_block(t, x, y, bpp), x, bpp), t.fmt);

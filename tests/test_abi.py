@@ -32,7 +32,7 @@ def test_texture_descriptor_layout():
     # stf_texture: pointer, 2 x int32, int64, 2 x int32, pointer, pointer
     assert ctypes.sizeof(stf.Texture) == 48
     assert stf.Texture.scale.offset == 32 and stf.Texture.decoder.offset == 40
-    assert ctypes.sizeof(stf.Mlp) == 48
+    assert ctypes.sizeof(stf.Mlp) == 56
     assert ctypes.sizeof(stf.Reuse) == 24 and stf.Reuse.flags.offset == 16
 
 
@@ -124,9 +124,13 @@ def test_latent_and_decoder_validation():
     ptrs = (ctypes.c_void_p * 1)(4096)
     assert lib.stf_backward(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(r), ptrs, ptrs, None) == -2
     # the packer validates its pointers before launching anything
-    m = stf.Mlp(4096, 4096, 4096, None, 4096, 4096)
+    m = stf.Mlp(4096, 4096, 4096, None, 4096, 4096, 0, 0)
     assert lib.stf_decoder_pack(ctypes.byref(m), ctypes.c_void_p(4096), None) == -1
-    m = stf.Mlp(4096, 4096, 4096, 4096, 4096, 4096)
+    m = stf.Mlp(4096, 4096, 4096, 4096, 4096, 4096, 2, 0)
+    assert lib.stf_decoder_pack(ctypes.byref(m), ctypes.c_void_p(4096), None) == -1
+    m = stf.Mlp(4096, 4096, 4096, 4096, 4096, 4096, 1, 5)
+    assert lib.stf_decoder_pack(ctypes.byref(m), ctypes.c_void_p(4096), None) == -1
+    m = stf.Mlp(4096, 4096, 4096, 4096, 4096, 4096, 0, 0)
     assert lib.stf_decoder_pack(ctypes.byref(m), ctypes.c_void_p(4104), None) == -1
     assert lib.stf_decoder_pack(None, ctypes.c_void_p(4096), None) == -1
 

@@ -202,3 +202,91 @@ def test_decoded_full_size_sampled():
         REL * np.maximum(np.abs(rv[ok]), support_max(decoded, uvs, o.BICUBIC)[:, 0])
     err = np.abs(got[py[ok], px[ok]].astype(np.float64) - rv[ok])
     assert np.all(err <= tol), f"worst {np.max(err / tol):.3g}x of the bound"
+
+
+# ----------------------------------------------------------------- FP8 decoder
+
+U_FP8 = 2.0 ** -4           # unit roundoff of FP8 E4M3 (4 significant bits)
+SUB_FP8 = 2.0 ** -10        # half the subnormal spacing of FP8 E4M3
+
+
+def bound_decode_fp8(x, layers, exact_inputs):
+    """Bound on |GPU FP8 decode - FP64 decode|: inputs and activations
+    rounded to FP8 E4M3 (relative 2^-4, absolute 2^-10 below the normal
+    range), weights stored as FP8 of W / s with s = max|W| / 448, FP32
+    accumulation."""
+    a = np.asarray(x, dtype=np.float64)
+    e = np.zeros_like(a) if exact_inputs else np.maximum(U_FP8 * np.abs(a), SUB_FP8)
+    for li, (wt, b) in enumerate(layers):
+        W = np.asarray(wt, dtype=np.float64)
+        bb = np.asarray(b, dtype=np.float64)
+        s = np.abs(W).max() / 448.0
+        dW = np.maximum(U_FP8 * np.abs(W), s * SUB_FP8)
+        z = a @ W.T + bb
+        aw = np.abs(W)
+        ez = e @ aw.T + (np.abs(a) + e) @ dW.T
+        ez = ez + gamma(W.shape[1] + 1) * ((np.abs(a) + e) @ (aw + dW).T + np.abs(bb)) + U_F32 * (np.abs(z) + ez)
+        if li < len(layers) - 1:
+            h = np.maximum(z, 0.0)
+            e = ez + np.maximum(U_FP8 * (h + ez), SUB_FP8)
+            a = h
+        else:
+            return ez
+
+
+@pytest.mark.parametrize("kind", ["fp8", "bf16"])
+@pytest.mark.parametrize("fp", [None, "quad2x2", "tile8x8"])
+def test_fp8_decoder_parity(kind, fp):
+    layers = w.decoder_weights(2)
+    stored, scale, x, _ = latent_case(kind, 3, 64)
+    decoded = o.mlp_decode(x, layers)
+    ebound = bound_decode_fp8(x, layers, exact_inputs=(kind == "fp8" and scale is None))
+    uv = w.small_screen(104, 56, 64, 4.0, offset_seed=6)
+    dec = stf.pack_decoder([(torch.from_numpy(np.ascontiguousarray(a)).cuda(),
+                             torch.from_numpy(np.ascontiguousarray(b)).cuda()) for a, b in layers], precision="fp8")
+    dt, duv = [device_latents(stored, kind)], torch.from_numpy(uv).cuda()
+    sc = [None if scale is None else list(scale)]
+    if fp is None:
+        outs, sel = stf.filter(dt, duv, "bicubic", 1, 0, sel=True, scales=sc, decoder=dec)
+        (rv, rs), = o.stf_filter([decoded], uv, o.BICUBIC, 1, 0)
+    else:
+        outs, sel = stf.filter_reuse(dt, duv, fp, "bicubic", 1, 0, sel=True, scales=sc, decoder=dec)
+        (rv, rs), = o.stf_filter_reuse([decoded], uv, o.BICUBIC, 1, 0, fp)
+    assert np.array_equal(host(sel)[0], image(rs, uv))
+    got = host(outs[0])
+    check(got, image(rv, uv), uv, o.BICUBIC, decoded, ebound, f"fp8 decoder {kind} {fp}")
+    # FP8 arithmetic is coarse but not vacuous: the typical error is a few
+    # percent of the output range
+    err = np.abs(got - image(rv, uv))
+    assert err.mean() < 0.05 * np.abs(decoded).max()
+
+
+def test_fp8_decoder_at_texel_centres_matches_a_simulated_fp8_decode():
+    # at texel centres one-tap STF returns the decode of the texel itself;
+    # compare with an FP64 simulation of the FP8 arithmetic (weights,
+    # latents and activations rounded to OCP E4M3 by torch's CPU cast)
+    layers = w.decoder_weights(5)
+    lat = w.latent_grid(9, 32).astype(np.float64)
+    codes = w.quantize(lat, "fp8")
+    c = ((np.arange(32) + 0.5) / 32).astype(np.float32)
+    uv = np.stack(np.broadcast_arrays(c[None, :], c[:, None]), -1).astype(np.float32)
+    dec = stf.pack_decoder([(torch.from_numpy(np.ascontiguousarray(a)).cuda(),
+                             torch.from_numpy(np.ascontiguousarray(b)).cuda()) for a, b in layers], precision="fp8")
+    got = host(stf.filter([device_latents(codes, "fp8")], torch.from_numpy(uv).cuda(), "bilinear", decoder=dec)[0])
+
+    def q8(v):
+        return torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).to(torch.float8_e4m3fn).to(
+            torch.float64).numpy()
+
+    a = o.fp8e4m3_value(codes)
+    for li, (wt, b) in enumerate(layers):
+        W = wt.astype(np.float64)
+        s = np.float32(np.abs(wt).max()) / np.float32(448.0)
+        Wq = q8(W / s)
+        z = s * (a @ Wq.T + b.astype(np.float64) / s)
+        a = q8(np.maximum(z, 0.0)) if li < 2 else z
+    # only the FP32 accumulation order and scale products differ, which can
+    # move an activation across an FP8 rounding boundary now and then: nearly
+    # every output agrees to 1e-3 of the range
+    err = np.abs(got - a)
+    assert np.mean(err <= 1e-3 * np.abs(a).max()) >= 0.99
