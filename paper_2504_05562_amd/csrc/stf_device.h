@@ -173,22 +173,11 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 
+// Half-precision value of the low 16 bits (exact in FP32). Written as a
+// conversion of a _Float16 so that fmaf(w, h2f(x), acc) compiles to one
+// v_fma_mix_f32 that reads the half operand directly.
 __device__ __forceinline__ float h2f(uint32_t bits16) {
-    return __half2float(__ushort_as_half((unsigned short)(bits16 & 0xFFFFu)));
-}
-
-// Exact-once-rounded (half(lo or hi 16 bits of x) - c) in one v_fma_mix_f32:
-// fma(half, 1.0, -c) with the half operand converted inside the ALU. The
-// compiler folds fma(x, 1, c) into an add before it can form the mix
-// instruction, so it is written out (ALU only, no memory operands).
-template <int HI>
-__device__ __forceinline__ float half_minus(uint32_t x, float neg_c) {
-    float d;
-    if constexpr (HI)
-        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(d) : "v"(x), "v"(neg_c));
-    else
-        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(d) : "v"(x), "v"(neg_c));
-    return d;
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(bits16 & 0xFFFFu));
 }
 
 // Texel payload kinds. F16x4 / F16x2 keep the raw half bits (exchanged and
@@ -197,27 +186,32 @@ __device__ __forceinline__ float half_minus(uint32_t x, float neg_c) {
 enum Payload { kF16x4 = 0, kF16x2 = 1, kF32x4 = 2, kF32x1 = 3, kLatent = 4 };
 
 template <int P> struct Texel;
+// C channels; W 32-bit words of payload (word(k) its bits).
 template <> struct Texel<kF16x4> {
-    static constexpr int C = 4;
+    static constexpr int C = 4, W = 2;
     uint2 raw;
     __device__ __forceinline__ float ch(int c) const {
         return h2f(c < 2 ? (raw.x >> (16 * c)) : (raw.y >> (16 * (c - 2))));
     }
+    __device__ __forceinline__ uint32_t word(int k) const { return k ? raw.y : raw.x; }
 };
 template <> struct Texel<kF16x2> {
-    static constexpr int C = 2;
+    static constexpr int C = 2, W = 1;
     uint32_t raw;
     __device__ __forceinline__ float ch(int c) const { return h2f(raw >> (16 * c)); }
+    __device__ __forceinline__ uint32_t word(int) const { return raw; }
 };
 template <> struct Texel<kF32x4> {
-    static constexpr int C = 4;
+    static constexpr int C = 4, W = 4;
     float v[4];
     __device__ __forceinline__ float ch(int c) const { return v[c]; }
+    __device__ __forceinline__ uint32_t word(int k) const { return __float_as_uint(v[k]); }
 };
 template <> struct Texel<kF32x1> {
-    static constexpr int C = 1;
+    static constexpr int C = 1, W = 1;
     float v[1];
     __device__ __forceinline__ float ch(int) const { return v[0]; }
+    __device__ __forceinline__ uint32_t word(int) const { return __float_as_uint(v[0]); }
 };
 
 __device__ __forceinline__ int format_bytes(int fmt) {

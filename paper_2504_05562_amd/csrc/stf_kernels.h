@@ -9,10 +9,12 @@
 //   3. draws two uniforms from the pcg4d hash and picks one texel per axis
 //      by exact integer CDF inversion (one-tap STF),
 //   4. fetches and decodes that single texel,
-//   5. (reuse) exchanges picks inside the tile and evaluates Eq. (14) in the
-//      difference form  out = T_c + sum_i w_i (T_i - T_c) / sum_i w_i,
-//      which equals Eq. (14) and keeps constant regions and the no-overlap
-//      fallback exact in FP32,
+//   5. (reuse) exchanges picks inside the tile and evaluates Eq. (14): the
+//      pair and record exchanges in the difference form
+//      out = T_c + sum_i w_i (T_i - T_c) / sum_i w_i (exact for constant
+//      regions and the no-overlap fallback in FP32), the whole-tile bins as
+//      sum_j f_c(j) N_j T_j / sum_j f_c(j) N_j (one FMA per channel and bin;
+//      a wave whose picks all hold the same texel returns it exactly),
 //   6. stores FP32 colours with non-temporal stores.
 // Exchange strategies:
 //   quad2x2  DPP quad_perm moves, no LDS;
@@ -39,20 +41,6 @@
 namespace stf {
 
 enum Mode { kModeStf = 0, kModeQuad = 1, kModeRecords = 2, kModeBins = 3 };
-
-// Whole-tile gather arithmetic: true accumulates w_j (T_j - T_c) (exact zero
-// for constant regions and the one-tap fallback in FP32); false accumulates
-// w_j T_j (one operation less per channel and bin; within a few ulp).
-#ifndef STF_EXACT_DIFF
-#define STF_EXACT_DIFF 1
-#endif
-constexpr bool kExactDiff = STF_EXACT_DIFF != 0;
-// 2D weights f_c = wx * wy from a per-pixel table (16 registers for the
-// B-spline) or formed per bin (one multiply more, fewer live registers).
-#ifndef STF_WEIGHT_TABLE
-#define STF_WEIGHT_TABLE 0
-#endif
-constexpr bool kWeightTable = STF_WEIGHT_TABLE != 0;
 
 // LDS per wavefront: bins (kBinRecords x 16 B records, or kBinRecords floats
 // of N plus kBinRecords x 16 B of decoded texels) followed by kBinRecords
@@ -196,8 +184,8 @@ struct Coverage {
 
 // One bin per texel of a kBinG x kBinG window: N = sum of 1/p over the picks
 // of that texel, plus the texel itself (raw half bits or decoded floats).
-// gather() adds one bin's term of  sum_j f_c(j) N_j (T_j - T_c)  (EXACT) or
-// of  sum_j f_c(j) N_j T_j , and f_c(j) N_j to B.
+// gather() adds one bin's term of  sum_j f_c(j) N_j T_j  to acc and
+// f_c(j) N_j to B (half channels enter the FMA unconverted: v_fma_mix_f32).
 template <int P> struct Bins;
 
 typedef unsigned int u3 __attribute__((ext_vector_type(3)));
@@ -217,22 +205,15 @@ template <> struct Bins<kF16x4> {             // record {raw.x, raw.y, N, pad}, 
         if (n == 0.0f) clear_one(l, rec);
         else l[rec * 4 + 2] = n;
     }
-    template <bool EXACT>
-    __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
+    __device__ static void gather(const float* l, int bin, float f, float& B, float* acc) {
         const u3 q = *reinterpret_cast<const u3*>(__builtin_assume_aligned(&l[bin * 4], 16));   // 12 of 16 bytes
-        const float w = f * __uint_as_float(q.z);
-        B += w;
-        if constexpr (EXACT) {
-            acc[0] = fmaf(w, half_minus<0>(q.x, nTc[0]), acc[0]);
-            acc[1] = fmaf(w, half_minus<1>(q.x, nTc[1]), acc[1]);
-            acc[2] = fmaf(w, half_minus<0>(q.y, nTc[2]), acc[2]);
-            acc[3] = fmaf(w, half_minus<1>(q.y, nTc[3]), acc[3]);
-        } else {
-            acc[0] = fmaf(h2f(q.x), w, acc[0]);
-            acc[1] = fmaf(h2f(q.x >> 16), w, acc[1]);
-            acc[2] = fmaf(h2f(q.y), w, acc[2]);
-            acc[3] = fmaf(h2f(q.y >> 16), w, acc[3]);
-        }
+        const float n = __uint_as_float(q.z);
+        const float w = f * n;
+        B = fmaf(f, n, B);
+        acc[0] = fmaf(w, h2f(q.x), acc[0]);
+        acc[1] = fmaf(w, h2f(q.x >> 16), acc[1]);
+        acc[2] = fmaf(w, h2f(q.y), acc[2]);
+        acc[3] = fmaf(w, h2f(q.y >> 16), acc[3]);
     }
     // Eq. (3) term of the bin (zero texel when empty) and its coverage
     __device__ static void exact(const float* l, int bin, float f, float* ex, bool& cov) {
@@ -258,18 +239,13 @@ template <> struct Bins<kF16x2> {             // record {raw, N}
         if (n == 0.0f) clear_one(l, rec);
         else l[rec * 2 + 1] = n;
     }
-    template <bool EXACT>
-    __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
+    __device__ static void gather(const float* l, int bin, float f, float& B, float* acc) {
         const uint2 q = reinterpret_cast<const uint2*>(l)[bin];
-        const float w = f * __uint_as_float(q.y);
-        B += w;
-        if constexpr (EXACT) {
-            acc[0] = fmaf(w, half_minus<0>(q.x, nTc[0]), acc[0]);
-            acc[1] = fmaf(w, half_minus<1>(q.x, nTc[1]), acc[1]);
-        } else {
-            acc[0] = fmaf(h2f(q.x), w, acc[0]);
-            acc[1] = fmaf(h2f(q.x >> 16), w, acc[1]);
-        }
+        const float n = __uint_as_float(q.y);
+        const float w = f * n;
+        B = fmaf(f, n, B);
+        acc[0] = fmaf(w, h2f(q.x), acc[0]);
+        acc[1] = fmaf(w, h2f(q.x >> 16), acc[1]);
     }
     __device__ static void exact(const float* l, int bin, float f, float* ex, bool& cov) {
         const uint2 q = reinterpret_cast<const uint2*>(l)[bin];
@@ -290,12 +266,11 @@ template <> struct Bins<kF32x1> {             // record {T, N}
         if (n == 0.0f) clear_one(l, rec);
         else l[rec * 2 + 1] = n;
     }
-    template <bool EXACT>
-    __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
+    __device__ static void gather(const float* l, int bin, float f, float& B, float* acc) {
         const float2 q = reinterpret_cast<const float2*>(l)[bin];
         const float w = f * q.y;
-        B += w;
-        acc[0] = EXACT ? fmaf(w, q.x + nTc[0], acc[0]) : fmaf(q.x, w, acc[0]);
+        B = fmaf(f, q.y, B);
+        acc[0] = fmaf(w, q.x, acc[0]);
     }
     __device__ static void exact(const float* l, int bin, float f, float* ex, bool& cov) {
         const float2 q = reinterpret_cast<const float2*>(l)[bin];
@@ -320,14 +295,15 @@ template <> struct Bins<kF32x4> {             // float4 T[kBinRecords], then flo
         if (n == 0.0f) clear_one(l, rec);
         else l[4 * kBinRecords + rec] = n;
     }
-    template <bool EXACT>
-    __device__ static void gather(const float* l, int bin, float f, const float* nTc, float& B, float* acc) {
+    __device__ static void gather(const float* l, int bin, float f, float& B, float* acc) {
         const float4 q = reinterpret_cast<const float4*>(l)[bin];
-        const float w = f * l[4 * kBinRecords + bin];
-        B += w;
-        const float T[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = EXACT ? fmaf(w, T[c] + nTc[c], acc[c]) : fmaf(T[c], w, acc[c]);
+        const float n = l[4 * kBinRecords + bin];
+        const float w = f * n;
+        B = fmaf(f, n, B);
+        acc[0] = fmaf(w, q.x, acc[0]);
+        acc[1] = fmaf(w, q.y, acc[1]);
+        acc[2] = fmaf(w, q.z, acc[2]);
+        acc[3] = fmaf(w, q.w, acc[3]);
     }
     __device__ static void exact(const float* l, int bin, float f, float* ex, bool& cov) {
         const float4 q = reinterpret_cast<const float4*>(l)[bin];
@@ -382,27 +358,36 @@ __device__ __forceinline__ void for_box(const BinBox& b, int lane, F f) {
         }
 }
 
-// Exact sums of 1/p per bin. With e_max the largest biased exponent of the
-// wave's reciprocal PMFs, every r whose exponent is at least e_max - 33 is
-// the integer m * 2^(e - e_max + 33) times 2^(e_max - 183) (m = 24-bit
-// significand), and at most 64 of them stay below 2^63: the 64-bit integer
-// sums are exact and independent of the order of the atomic adds; each bin
-// is then converted to FP32 (within 2 ulp, deterministically). Waves whose
-// exponents span more than 33 fall back to FP32 atomics.
-__device__ __forceinline__ uint64_t fixed_of(float r, uint32_t e_max) {
+// Exact sums of 1/p per bin at a fixed scale. p <= 1, so every reciprocal PMF
+// r >= 1 is an integer multiple of 2^-23 (its last significand bit is worth
+// at least that); for r < 2^34 the integer r * 2^23 is below 2^57, and 64 of
+// them sum below 2^63: the 64-bit sums are exact and independent of the
+// order of the atomic adds, and no wave-wide scale is needed. Each bin is
+// converted to FP32 within 2 ulp, deterministically. A wave holding an r
+// outside [1, 2^34) (probability below 2^-34 per pick) takes FP32 atomics.
+__device__ __forceinline__ bool fixed_range(float r) {
+    return (__float_as_uint(r) >> 23) - 127u <= 33u;      // also false for r < 1
+}
+
+__device__ __forceinline__ uint64_t fixed_r(float r) {
     const uint32_t b = __float_as_uint(r);
-    const uint32_t m = (b & 0x7FFFFFu) | 0x800000u;
-    return (uint64_t)m << ((b >> 23) - e_max + 33u);
+    return (uint64_t)((b & 0x7FFFFFu) | 0x800000u) << ((b >> 23) - 127u);
 }
 
-__device__ __forceinline__ float float_of(uint64_t n, uint32_t e_max) {
+__device__ __forceinline__ float float_r(uint64_t n) {
+    return fmaf((float)(uint32_t)(n >> 32), 4294967296.0f, (float)(uint32_t)n) * 0x1p-23f;   // within 2 ulp
+}
+
+// Signed sums with a wave-wide scale: with e_ref above the largest biased
+// exponent of the terms, v is stored as the integer v * 2^(183 - e_ref) in
+// two's complement (wrap-around addition is exact; 64 terms of at most 2^57
+// units fit). Magnitudes below 2^(e_ref - 183) truncate toward zero: the
+// absolute error per term is below 2^-57 of the largest term allowed.
+__device__ __forceinline__ float float_of(uint64_t n, uint32_t e_ref) {
     const float f = fmaf((float)(uint32_t)(n >> 32), 4294967296.0f, (float)(uint32_t)n);   // within 2 ulp
-    return ldexpf(f, (int)e_max - 183);
+    return ldexpf(f, (int)e_ref - 183);
 }
 
-// Signed values in the same fixed point (two's complement; wrap-around
-// addition is exact). Magnitudes below 2^(e_ref - 183) truncate toward zero:
-// the absolute error per term is below 2^-57 of the largest term allowed.
 __device__ __forceinline__ uint64_t signed_fixed_of(float v, uint32_t e_ref) {
     const uint32_t b = __float_as_uint(v);
     const uint32_t e = (b >> 23) & 0xFFu;
@@ -423,6 +408,7 @@ __device__ __forceinline__ float signed_float_of(uint64_t n, uint32_t e_ref) {
 template <int N>
 struct BinGeom {
     bool ok = false;         // every on-screen support fits the window
+    bool clean = false;      // the 64-bit sums of the box are zero (left so by the last finalize)
     uint32_t rx = 0, ry = 0; // this pixel's support start inside the window
     BinBox box;
     int tw = 0, th = 0;
@@ -437,6 +423,7 @@ __device__ __forceinline__ void update_geom(BinGeom<AxisCtx<FILT>::N>& g, const 
     g.ok = bin_window<N>(P, ctx.x.base, ctx.y.base, (uint32_t)tw - 1u, (uint32_t)th - 1u, tw, th, base_x, base_y,
                          g.rx, g.ry);
     if (g.ok) g.box = support_box<N>(P, g.rx, g.ry);
+    g.clean = false;
     g.tw = tw;
     g.th = th;
 }
@@ -475,6 +462,20 @@ __device__ __forceinline__ SlotPick pick_slot(const TexArg& t, const SelCtx<FILT
     return k;
 }
 
+// True when every on-screen lane holds the same texel payload (bit for bit).
+template <int PL>
+__device__ __forceinline__ bool wave_same_texel(const Texel<PL>& T, bool valid) {
+    const uint64_t on = __builtin_amdgcn_ballot_w64(valid);
+    const int first = on ? (int)__builtin_ctzll(on) : 0;
+    bool same = true;
+#pragma unroll
+    for (int k = 0; k < Texel<PL>::W; ++k) {
+        const uint32_t x = T.word(k);
+        same = same && x == (uint32_t)__builtin_amdgcn_readlane((int)x, first);
+    }
+    return __builtin_amdgcn_ballot_w64(valid && !same) == 0;
+}
+
 // Exchange and estimator for one texture slot of one pixel. LAT: the texture
 // holds latents; the picked texel is decoded by the MLP in `dec` (LDS) before
 // it is shared, so every pixel decodes exactly one texel.
@@ -482,7 +483,7 @@ __device__ __forceinline__ SlotPick pick_slot(const TexArg& t, const SelCtx<FILT
 // whenever the shared picks cover the pixel's support.
 template <int FILT, int MODE, int PL, bool LAT = false, bool EF = false>
 __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int slot, const Pixel& P,
-                                          const SelCtx<FILT>& ctx, const BinGeom<AxisCtx<FILT>::N>& geom,
+                                          const SelCtx<FILT>& ctx, BinGeom<AxisCtx<FILT>::N>& geom,
                                           const SlotPick& pk, float* lds, const uint8_t* dec = nullptr) {
     static_assert(!LAT || PL == kF32x4, "decoded latents are RGBA FP32");
     constexpr int N = SelCtx<FILT>::N;
@@ -542,53 +543,63 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
             if constexpr (MODE == kModeBins) {
                 use_bins = geom.ok;
                 if (use_bins) {
-                    const uint32_t rx = geom.rx, ry = geom.ry;
-                    const BinBox& box = geom.box;
-                    const int my_bin = (int)(ry + ky) * kBinStride + (int)(rx + kx);
-                    const uint32_t e = P.valid ? (__float_as_uint(r) >> 23) : 0u;
-                    const uint32_t e_max = wave_max(e);
-                    const bool fixed = __builtin_amdgcn_ballot_w64(P.valid && e + 33u < e_max) == 0;
-                    if (fixed) {
-                        uint64_t* acc64 = reinterpret_cast<uint64_t*>(lds + kAccFloatOffset);
-                        for_box(box, lane, [&](int rec) { acc64[rec] = 0ull; });
-                        wave_lds_sync();
-                        if (P.valid) {
-                            atomicAdd(reinterpret_cast<unsigned long long*>(&acc64[my_bin]),
-                                      (unsigned long long)fixed_of(r, e_max));
-                            Bins<PL>::put_texel(lds, my_bin, T);
+                    // every on-screen pick of the wave holds the same texel: Eq. (14) returns it
+                    const bool flat = wave_same_texel<PL>(T, P.valid);
+                    if (!flat || EF) {               // exact filtering still needs the coverage
+                        const uint32_t rx = geom.rx, ry = geom.ry;
+                        const BinBox& box = geom.box;
+                        const int my_bin = (int)(ry + ky) * kBinStride + (int)(rx + kx);
+                        const bool fixed = __builtin_amdgcn_ballot_w64(P.valid && !fixed_range(r)) == 0;
+                        if (fixed) {
+                            uint64_t* acc64 = reinterpret_cast<uint64_t*>(lds + kAccFloatOffset);
+                            if (!geom.clean) {
+                                for_box(box, lane, [&](int rec) { acc64[rec] = 0ull; });
+                                wave_lds_sync();
+                            }
+                            if (P.valid) {
+                                atomicAdd(reinterpret_cast<unsigned long long*>(&acc64[my_bin]),
+                                          (unsigned long long)fixed_r(r));
+                                Bins<PL>::put_texel(lds, my_bin, T);
+                            }
+                            wave_lds_sync();
+                            // N of every bin; the sums are left zero for the next texture of this size
+                            for_box(box, lane, [&](int rec) {
+                                const uint64_t n = acc64[rec];
+                                acc64[rec] = 0ull;
+                                Bins<PL>::finalize(lds, rec, float_r(n));
+                            });
+                            geom.clean = true;
+                        } else {
+                            for_box(box, lane, [&](int rec) { Bins<PL>::clear_one(lds, rec); });
+                            wave_lds_sync();
+                            if (P.valid) Bins<PL>::put(lds, my_bin, r, T);
                         }
                         wave_lds_sync();
-                        for_box(box, lane, [&](int rec) { Bins<PL>::finalize(lds, rec, float_of(acc64[rec], e_max)); });
-                    } else {
-                        for_box(box, lane, [&](int rec) { Bins<PL>::clear_one(lds, rec); });
-                        wave_lds_sync();
-                        if (P.valid) Bins<PL>::put(lds, my_bin, r, T);
-                    }
-                    wave_lds_sync();
-                    B = 0.0f;                        // the own pick is in the bins
-                    const int bin0 = (int)ry * kBinStride + (int)rx;
-                    float nTc[C];
+                        B = 0.0f;                    // the own pick is in the bins
+                        const int bin0 = (int)ry * kBinStride + (int)rx;
+                        bool all_in = true;
 #pragma unroll
-                    for (int c = 0; c < C; ++c) nTc[c] = -Tv[c];
-                    bool all_in = true;
+                        for (int b = 0; b < N; ++b) {
+                            const float wyb = ctx.y.w(b);
 #pragma unroll
-                    for (int b = 0; b < N; ++b) {
-                        const float wyb = ctx.y.w(b);
-#pragma unroll
-                        for (int aa = 0; aa < N; ++aa) {
-                            const float f = kWeightTable ? ctx.wxy[b * N + aa] : ctx.x.w(aa) * wyb;
-                            Bins<PL>::template gather<kExactDiff>(lds, bin0 + b * kBinStride + aa, f, nTc, B, acc);
-                            // same weights and order as the Eq. (3) kernel: bit-identical sums
-                            if constexpr (EF) Bins<PL>::exact(lds, bin0 + b * kBinStride + aa, f, cov.sum, all_in);
+                            for (int aa = 0; aa < N; ++aa) {
+                                const float f = ctx.x.w(aa) * wyb;
+                                Bins<PL>::gather(lds, bin0 + b * kBinStride + aa, f, B, acc);
+                                // same weights and order as the Eq. (3) kernel: bit-identical sums
+                                if constexpr (EF) Bins<PL>::exact(lds, bin0 + b * kBinStride + aa, f, cov.sum, all_in);
+                            }
                         }
+                        if constexpr (EF) covered = all_in;
+                        wave_lds_sync();             // reads done before the next slot reuses LDS
                     }
-                    if constexpr (EF) covered = all_in;
-                    if constexpr (!kExactDiff) {
-                        // sum_j w_j T_j  ->  sum_j w_j (T_j - T_c), the form the final step expects
+                    if (flat) {                      // out = T_c exactly
+                        B = 1.0f;
 #pragma unroll
-                        for (int c = 0; c < C; ++c) acc[c] = fmaf(-B, Tv[c], acc[c]);
+                        for (int c = 0; c < C; ++c) acc[c] = 0.0f;
+                    } else {                         // out = acc / B: no T_c term
+#pragma unroll
+                        for (int c = 0; c < C; ++c) Tv[c] = 0.0f;
                     }
-                    wave_lds_sync();                 // reads done before the next slot reuses LDS
                 }
             }
             if (!use_bins) {
@@ -685,10 +696,20 @@ __device__ __forceinline__ int payload_of(int fmt) {
     }
 }
 
+// Waves per SIMD the forward kernels are register-budgeted for. The
+// whole-tile kernel needs about 80 VGPRs (six waves per SIMD); one register
+// more would cost a wave, and a seventh wave (72 VGPRs) spills and runs
+// slower.
+#ifndef STF_BINS_WAVES
+#define STF_BINS_WAVES 6
+#endif
+template <int MODE, bool DEC, bool EF>
+constexpr int kForwardWaves = (MODE == kModeBins && !DEC && !EF) ? STF_BINS_WAVES : 1;
+
 // NT textures, unrolled: descriptors are loaded once, and every pick and
 // texel fetch is issued before the first exchange so their latencies overlap.
 template <int FILT, int MODE, int NT, bool DEC, bool EF>
-__global__ __launch_bounds__(kThreads) void forward_kernel(Args a) {
+__global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, DEC, EF>)) void forward_kernel(Args a) {
     // per-wave LDS: records or bins; with a decoder also the deduplicating decode's scratch
     constexpr bool kLds = MODE == kModeRecords || MODE == kModeBins || DEC;
     static_assert(kDedupBytes <= kLdsFloatsPerWave * 4, "decode scratch exceeds the wave's LDS");
@@ -1093,15 +1114,13 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                     for (int i = lane; i < kBins * (1 + C); i += 64) N64[i] = 0ull;
                     for (int i = lane; i < kBins; i += 64) Nb[i] = 0.0f;
                     const int my_bin = (int)(ry + ky) * kBinG + (int)(rx + kx);
-                    const uint32_t e = P.valid ? (__float_as_uint(r) >> 23) : 0u;
-                    const uint32_t e_max = wave_max(e);
-                    const bool fixed = __builtin_amdgcn_ballot_w64(P.valid && e + 33u < e_max) == 0;
+                    const bool fixed = __builtin_amdgcn_ballot_w64(P.valid && !fixed_range(r)) == 0;
                     wave_lds_sync();
                     if (fixed) {
                         if (P.valid) atomicAdd(reinterpret_cast<unsigned long long*>(&N64[my_bin]),
-                                               (unsigned long long)fixed_of(r, e_max));
+                                               (unsigned long long)fixed_r(r));
                         wave_lds_sync();
-                        for (int i = lane; i < kBins; i += 64) Nb[i] = float_of(N64[i], e_max);
+                        for (int i = lane; i < kBins; i += 64) Nb[i] = float_r(N64[i]);
                     } else {
                         if (P.valid) atomicAdd(&Nb[my_bin], r);
                     }
