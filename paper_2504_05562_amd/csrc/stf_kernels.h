@@ -649,18 +649,29 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
     }
 }
 
-__device__ __forceinline__ bool setup_pixel(const Args& a, Pixel& P) {
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    lane_pixel(lane, P.lx, P.ly);
+// This lane's pixel of screen tile (tx, ty); UV not loaded.
+__device__ __forceinline__ void place_pixel(const Args& a, int tx, int ty, Pixel& P) {
+    lane_pixel(lane_id(), P.lx, P.ly);
     P.q = P.ly * 8 + P.lx;
-    const int tx = blockIdx.x * kWavesPerGroup + wave;
-    if (tx * kTile >= a.sw) return false;                    // whole tile off screen
     P.px = tx * kTile + P.lx;
-    P.py = blockIdx.y * kTile + P.ly;
+    P.py = ty * kTile + P.ly;
     P.valid = (P.px < a.sw) && (P.py < a.sh);
-    const int cx = min(P.px, a.sw - 1), cy = min(P.py, a.sh - 1);
-    const v2f uv = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(a.uv) + ((int64_t)cy * a.sw + cx));
+}
+
+// UV of screen pixel (px, py), clamped to the screen (off-screen lanes of
+// edge tiles read their nearest on-screen pixel).
+__device__ __forceinline__ v2f load_uv(const Args& a, int px, int py) {
+    const int cx = min(px, a.sw - 1), cy = min(py, a.sh - 1);
+    return __builtin_nontemporal_load(reinterpret_cast<const v2f*>(a.uv) + ((int64_t)cy * a.sw + cx));
+}
+
+// Pixel and UV of this lane for one-tile-per-wave kernels; false when the
+// wave's whole tile is off screen.
+__device__ __forceinline__ bool setup_pixel(const Args& a, Pixel& P) {
+    const int tx = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
+    if (tx * kTile >= a.sw) return false;
+    place_pixel(a, tx, blockIdx.y, P);
+    const v2f uv = load_uv(a, P.px, P.py);
     P.u = uv.x;
     P.v = uv.y;
     return true;
@@ -696,32 +707,29 @@ __device__ __forceinline__ int payload_of(int fmt) {
     }
 }
 
-// Waves per SIMD the forward kernels are register-budgeted for. The
-// whole-tile kernel needs about 80 VGPRs (six waves per SIMD); one register
-// more would cost a wave, and a seventh wave (72 VGPRs) spills and runs
-// slower.
-#ifndef STF_BINS_WAVES
-#define STF_BINS_WAVES 6
-#endif
-template <int MODE, bool DEC, bool EF>
-constexpr int kForwardWaves = (MODE == kModeBins && !DEC && !EF) ? STF_BINS_WAVES : 1;
+// Waves per SIMD the forward kernels are register-budgeted for (VGPRs per
+// lane: 512 / waves, in steps of 8). The whole-tile kernel issues VALU most
+// of the time and hides its memory and LDS latency with occupancy: with up
+// to two textures it fits 72 VGPRs (seven waves; one texture fits 64, eight
+// waves), with more it keeps 80 (six waves) rather than spill.
+template <int MODE, int NT, bool DEC, bool EF>
+constexpr int kForwardWaves = (MODE == kModeBins && !DEC && !EF) ? (NT <= 2 ? 7 : 6) : 1;
 
-// NT textures, unrolled: descriptors are loaded once, and every pick and
-// texel fetch is issued before the first exchange so their latencies overlap.
+// Screen tile rows each forward wave filters one after the other (one tile
+// column): the next row's UV is loaded while the current row is filtered,
+// and a workgroup stages the decoder once for all its rows. Only the
+// decoder kernels take more than one row: in the others the extra live
+// registers cost more occupancy than the prefetch hides.
+template <bool DEC>
+constexpr int kForwardRows = DEC ? 2 : 1;
+
+// One screen tile, NT textures unrolled: descriptors are loaded once, and
+// every pick and texel fetch is issued before the first exchange so their
+// latencies overlap; then the UV of the wave's next tile (more = true) is
+// requested into uv_next.
 template <int FILT, int MODE, int NT, bool DEC, bool EF>
-__global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, DEC, EF>)) void forward_kernel(Args a) {
-    // per-wave LDS: records or bins; with a decoder also the deduplicating decode's scratch
-    constexpr bool kLds = MODE == kModeRecords || MODE == kModeBins || DEC;
-    static_assert(kDedupBytes <= kLdsFloatsPerWave * 4, "decode scratch exceeds the wave's LDS");
-    __shared__ __align__(16) float lds_all[kLds ? kWavesPerGroup * kLdsFloatsPerWave : 4];
-    __shared__ __align__(16) uint8_t dec[DEC ? kDecBytes : 16];
-    if constexpr (DEC) {                       // before any wave of the group can leave
-        stage_decoder(a.dec, dec);
-        __syncthreads();
-    }
-    Pixel P;
-    if (!setup_pixel(a, P)) return;
-    float* lds = lds_all + (kLds ? (threadIdx.x >> 6) * kLdsFloatsPerWave : 0);
+__device__ __forceinline__ void forward_tile(const Args& a, Pixel& P, float* lds, const uint8_t* dec, bool more,
+                                             v2f& uv_next) {
     TexArg t[NT];
 #pragma unroll
     for (int i = 0; i < NT; ++i) t[i] = a.tex[i];
@@ -742,6 +750,7 @@ __global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, DEC, EF>)) void forw
             pk[i].raw = fetch_block(t[i], pk[i].sx, pk[i].sy, format_bytes(t[i].fmt));
         }
     }
+    if (more) uv_next = load_uv(a, P.px, P.py + kTile);
     BinGeom<AxisCtx<FILT>::N> geom;
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
@@ -755,6 +764,45 @@ __global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, DEC, EF>)) void forw
             if constexpr (DEC) slot_pass<FILT, MODE, kF32x4, true, EF>(a, t[i], i, P, ctx, geom, pk[i], lds, dec);
             break;
         default: slot_pass<FILT, MODE, kF32x4, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
+        }
+    }
+}
+
+// Workgroup (x, y) filters tile columns 4x .. 4x+3 (one per wave) over tile
+// rows kForwardRows<DEC> * y onward.
+template <int FILT, int MODE, int NT, bool DEC, bool EF>
+__global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, NT, DEC, EF>)) void forward_kernel(Args a) {
+    // per-wave LDS: records or bins; with a decoder also the deduplicating decode's scratch
+    constexpr bool kLds = MODE == kModeRecords || MODE == kModeBins || DEC;
+    static_assert(kDedupBytes <= kLdsFloatsPerWave * 4, "decode scratch exceeds the wave's LDS");
+    __shared__ __align__(16) float lds_all[kLds ? kWavesPerGroup * kLdsFloatsPerWave : 4];
+    __shared__ __align__(16) uint8_t dec[DEC ? kDecBytes : 16];
+    if constexpr (DEC) {                       // before any wave of the group can leave
+        stage_decoder(a.dec, dec);
+        __syncthreads();
+    }
+    constexpr int kRows = kForwardRows<DEC>;
+    const int tx = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
+    if (tx * kTile >= a.sw) return;            // whole tile column off screen
+    float* lds = lds_all + (kLds ? (threadIdx.x >> 6) * kLdsFloatsPerWave : 0);
+    const int ty0 = blockIdx.y * kRows;
+    Pixel P;
+    place_pixel(a, tx, ty0, P);
+    v2f uv = load_uv(a, P.px, P.py);
+    if constexpr (kRows == 1) {
+        P.u = uv.x;
+        P.v = uv.y;
+        forward_tile<FILT, MODE, NT, DEC, EF>(a, P, lds, DEC ? dec : nullptr, false, uv);
+    } else {
+#pragma unroll 1
+        for (int k = 0; k < kRows; ++k) {
+            const int ty = ty0 + k;
+            if (ty * kTile >= a.sh) break;     // wave-uniform
+            if (k > 0) place_pixel(a, tx, ty, P);
+            P.u = uv.x;
+            P.v = uv.y;
+            const bool more = k + 1 < kRows && (ty + 1) * kTile < a.sh;
+            forward_tile<FILT, MODE, NT, DEC, EF>(a, P, lds, DEC ? dec : nullptr, more, uv);
         }
     }
 }
@@ -1235,9 +1283,17 @@ inline dim3 grid_of(const Args& a) {
                 (unsigned)((a.sh + kTile - 1) / kTile));
 }
 
+// Forward kernels: kForwardRows<DEC> tile rows per workgroup.
+template <bool DEC>
+inline dim3 grid_forward(const Args& a) {
+    const int rows = (a.sh + kTile - 1) / kTile;
+    return dim3((unsigned)((a.sw + kTile * kWavesPerGroup - 1) / (kTile * kWavesPerGroup)),
+                (unsigned)((rows + kForwardRows<DEC> - 1) / kForwardRows<DEC>));
+}
+
 template <int FILT, int MODE, bool DEC, bool EF>
 void launch_nt(const Args& a, hipStream_t s) {
-    const dim3 g = grid_of(a), b(kThreads);
+    const dim3 g = grid_forward<DEC>(a), b(kThreads);
     switch (a.ntex) {
     case 1: hipLaunchKernelGGL((forward_kernel<FILT, MODE, 1, DEC, EF>), g, b, 0, s, a); break;
     case 2: hipLaunchKernelGGL((forward_kernel<FILT, MODE, 2, DEC, EF>), g, b, 0, s, a); break;
