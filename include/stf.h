@@ -123,13 +123,21 @@ typedef struct stf_screen {
  * correlated. */
 #define STF_SHARE_SELECTION 1
 
+/* Testing aid for the whole-tile (STF_FP_TILE8X8) forward and adjoint
+ * kernels: the per-texel sums of reciprocal PMFs use FP32 LDS atomics, the
+ * path those kernels otherwise take only for a wave that holds a pick of
+ * probability below 2^-34 (exact 64-bit integer sums cover all others).
+ * Results stay within FP32 rounding of the default path but may depend on
+ * the order of the atomic adds. */
+#define STF_FLOAT_BIN_SUMS 2
+
 typedef struct stf_params {
     int32_t filter;         /* stf_filter_kind */
     int32_t address;        /* stf_address */
     uint32_t seed;          /* random stream: pcg4d(px, py, frame, seed + (k>>1)*0x9E3779B9), k the slot
                                (or with STF_SHARE_SELECTION the first slot of the same size) */
     uint32_t frame;
-    int32_t flags;          /* 0 or STF_SHARE_SELECTION */
+    int32_t flags;          /* 0, STF_SHARE_SELECTION | STF_FLOAT_BIN_SUMS */
     int32_t reserved;       /* must be 0 */
 } stf_params;
 

@@ -80,6 +80,7 @@ class Params(ctypes.Structure):
 
 
 SHARE_SELECTION = 1
+FLOAT_BIN_SUMS = 2
 
 
 class Reuse(ctypes.Structure):
@@ -249,10 +250,10 @@ def _screen(uv):
     return Screen(uv.data_ptr(), int(uv.shape[1]), int(uv.shape[0]))
 
 
-def _params(filter, seed, frame, share_selection=False):
+def _params(filter, seed, frame, share_selection=False, float_bin_sums=False):
     f = FILTERS[filter] if isinstance(filter, str) else int(filter)
     return Params(f, 0, int(seed) & 0xFFFFFFFF, int(frame) & 0xFFFFFFFF,
-                  SHARE_SELECTION if share_selection else 0, 0)
+                  (SHARE_SELECTION if share_selection else 0) | (FLOAT_BIN_SUMS if float_bin_sums else 0), 0)
 
 
 def _outputs(uv, chans, out=None):
@@ -294,16 +295,17 @@ def filter(textures, uv, filter="bicubic", seed=0, frame=0, sel=False, out=None,
 
 def filter_reuse(textures, uv, footprint="tile8x8", filter="bicubic", seed=0, frame=0, lut=None,
                  sel=False, out=None, stream=None, scales=None, decoder=None, exact_filtering=False,
-                 estimator="wis", clamp=False, share_selection=False):
+                 estimator="wis", clamp=False, share_selection=False, float_bin_sums=False):
     """STF with sample reuse (stf_filter_reuse). `lut` is a uint8 GPU tensor
     [64, K] of tile pixel ids for footprint='lut'; exact_filtering selects
     STF_REUSE_EXACT_FILTERING; estimator ('wis' = Eq. (14), 'is', 'mis',
-    'pmis', 'regression') and clamp select the comparison estimators."""
+    'pmis', 'regression') and clamp select the comparison estimators;
+    float_bin_sums sets STF_FLOAT_BIN_SUMS (a testing aid)."""
     import torch
     lib = library()
     descs, chans, _keep = _texture_descs(textures, scales=scales, decoder=decoder)
     scr = _screen(uv)
-    prm = _params(filter, seed, frame, share_selection)
+    prm = _params(filter, seed, frame, share_selection, float_bin_sums)
     r = _reuse(footprint, lut, exact_filtering, estimator, clamp)
     out, ptrs = _outputs(uv, chans, out)
     s = torch.empty((len(textures),) + tuple(uv.shape[:2]) + (2,), dtype=torch.int32, device=uv.device) if sel else None
@@ -325,14 +327,14 @@ def filter_reference(textures, uv, filter="bicubic", out=None, stream=None, scal
 
 
 def backward(textures, uv, grads, footprint="tile8x8", filter="bicubic", seed=0, frame=0, lut=None,
-             dtex=None, stream=None, scales=None, share_selection=False):
+             dtex=None, stream=None, scales=None, share_selection=False, float_bin_sums=False):
     """Adjoint of filter_reuse (stf_backward): accumulates dL/dT into `dtex`
     (float32 [H_t, W_t, C] per texture; zero-initialised if not given)."""
     import torch
     lib = library()
     descs, chans, _keep = _texture_descs(textures, scales=scales)
     scr = _screen(uv)
-    prm = _params(filter, seed, frame, share_selection)
+    prm = _params(filter, seed, frame, share_selection, float_bin_sums)
     r = _reuse(footprint, lut)
     if dtex is None:
         dtex = [torch.zeros((int(t.shape[0]), int(t.shape[1]), c), dtype=torch.float32, device=uv.device)

@@ -217,7 +217,9 @@ int prepare(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const s
     a.sh = scr->height;
     a.seed = p->seed;
     a.frame = p->frame;
-    if ((p->flags & ~STF_SHARE_SELECTION) != 0) return fail(STF_EINVAL, "unknown params flags 0x%x", p->flags);
+    if ((p->flags & ~(STF_SHARE_SELECTION | STF_FLOAT_BIN_SUMS)) != 0)
+        return fail(STF_EINVAL, "unknown params flags 0x%x", p->flags);
+    a.flags = (p->flags & STF_FLOAT_BIN_SUMS) ? stf::kFlagFloatBinSums : 0;
     if (p->reserved != 0) return fail(STF_EINVAL, "params reserved field must be 0");
     for (int i = 0; i < ntex; ++i) {
         a.leader[i] = i;
@@ -278,7 +280,7 @@ int forward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const s
         a.footprint = r->footprint;
         a.lut = r->lut;
         a.lut_k = r->lut_k;
-        a.flags = r->flags;
+        a.flags |= r->flags;
         switch (r->footprint) {
         case STF_FP_SELF: mode = stf::kModeStf; break;
         case STF_FP_QUAD2X2: mode = stf::kModeQuad; break;

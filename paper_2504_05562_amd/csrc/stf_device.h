@@ -35,6 +35,9 @@ struct TexArg {
     float scale[8];
 };
 
+// Args::flags: the stf_reuse flags plus kernel-internal bits.
+constexpr int32_t kFlagFloatBinSums = 1 << 8;   // STF_FLOAT_BIN_SUMS: FP32 atomics for the whole-tile sums
+
 struct Args {
     TexArg tex[STF_MAX_TEXTURES];
     float* out[STF_MAX_TEXTURES];

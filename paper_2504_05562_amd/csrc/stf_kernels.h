@@ -1,7 +1,8 @@
 // Kernels of the STF library (device code and forward launches), shared by
 // the translation units of libstf.so.
 //
-// One wavefront processes one 8x8 screen tile; a 256-thread workgroup holds
+// One wavefront processes one 8x8 screen tile at a time (the decoder
+// kernels two tile rows, one after the other); a 256-thread workgroup holds
 // four tiles side by side (32x8 pixels), so every UV row segment a group
 // reads is 256 contiguous bytes. Per pixel and texture slot a kernel:
 //   1. loads UV once (shared by all slots),
@@ -21,7 +22,7 @@
 //   tile8x8  texel bins in LDS: every lane adds its 1/p to the bin of its
 //            texel (N_j = sum over picks of texel j of 1/p_i), then each
 //            pixel visits only the N x N bins of its own support:
-//            sum_i w_i (T_i - T_c) = sum_j f_c(j) N_j (T_j - T_c);
+//            sum_i w_i T_i = sum_j f_c(j) N_j T_j;
 //   others   per-lane records in LDS read through the footprint member
 //            table (windows computed, or the caller's LUT).
 #pragma once
@@ -549,7 +550,8 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
                         const uint32_t rx = geom.rx, ry = geom.ry;
                         const BinBox& box = geom.box;
                         const int my_bin = (int)(ry + ky) * kBinStride + (int)(rx + kx);
-                        const bool fixed = __builtin_amdgcn_ballot_w64(P.valid && !fixed_range(r)) == 0;
+                        const bool fixed = !(a.flags & kFlagFloatBinSums) &&
+                                           __builtin_amdgcn_ballot_w64(P.valid && !fixed_range(r)) == 0;
                         if (fixed) {
                             uint64_t* acc64 = reinterpret_cast<uint64_t*>(lds + kAccFloatOffset);
                             if (!geom.clean) {
@@ -1162,7 +1164,8 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                     for (int i = lane; i < kBins * (1 + C); i += 64) N64[i] = 0ull;
                     for (int i = lane; i < kBins; i += 64) Nb[i] = 0.0f;
                     const int my_bin = (int)(ry + ky) * kBinG + (int)(rx + kx);
-                    const bool fixed = __builtin_amdgcn_ballot_w64(P.valid && !fixed_range(r)) == 0;
+                    const bool fixed = !(a.flags & kFlagFloatBinSums) &&
+                                       __builtin_amdgcn_ballot_w64(P.valid && !fixed_range(r)) == 0;
                     wave_lds_sync();
                     if (fixed) {
                         if (P.valid) atomicAdd(reinterpret_cast<unsigned long long*>(&N64[my_bin]),

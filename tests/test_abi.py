@@ -18,6 +18,11 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(stf_[a-z_]+)\s*\(", text)))
 
 
+def _define(name):
+    text = open(os.path.join(ROOT, "include", "stf.h")).read()
+    return int(re.search(r"#define\s+" + name + r"\s+(\d+)", text).group(1))
+
+
 def test_library_exports_every_declared_symbol():
     lib = stf.library()
     names = declared_functions()
@@ -155,7 +160,8 @@ def test_footprint_generator_validation():
 def test_params_layout_and_flags():
     assert ctypes.sizeof(stf.Params) == 24
     tex, scr, prm = _good()
-    prm.flags = 2
+    prm.flags = 4                       # neither STF_SHARE_SELECTION nor STF_FLOAT_BIN_SUMS
     assert _call_filter(tex, 1, ctypes.byref(scr), ctypes.byref(prm)) == -1
+    assert (stf.SHARE_SELECTION, stf.FLOAT_BIN_SUMS) == (_define("STF_SHARE_SELECTION"), _define("STF_FLOAT_BIN_SUMS"))
     prm.flags, prm.reserved = 1, 3
     assert _call_filter(tex, 1, ctypes.byref(scr), ctypes.byref(prm)) == -1

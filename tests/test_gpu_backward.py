@@ -18,14 +18,17 @@ def dev(a):
 
 
 @pytest.mark.parametrize("filt", ["bilinear", "bicubic"])
-@pytest.mark.parametrize("fp", ["self", "quad2x2", "square3x3", "tile8x8"])
-def test_backward_matches_oracle_adjoint(filt, fp):
+@pytest.mark.parametrize("fp,float_sums", [("self", False), ("quad2x2", False), ("square3x3", False),
+                                           ("tile8x8", False), ("tile8x8", True)])
+def test_backward_matches_oracle_adjoint(filt, fp, float_sums):
+    """float_sums: STF_FLOAT_BIN_SUMS, the FP32-atomic path of the whole-tile
+    sums of 1/p (otherwise taken only for picks of probability < 2^-34)."""
     rng = np.random.default_rng(3)
     tex = rng.random((32, 32, 4)).astype(np.float32)
     uv = w.small_screen(61, 45, 32, 2.5, offset_seed=7)
     H, W = uv.shape[:2]
     g = rng.standard_normal((H, W, 4)).astype(np.float32)
-    got = stf.backward([dev(tex)], dev(uv), [dev(g)], fp, filt, 4, 2)[0].cpu().numpy()
+    got = stf.backward([dev(tex)], dev(uv), [dev(g)], fp, filt, 4, 2, float_bin_sums=float_sums)[0].cpu().numpy()
     tiles = o.all_tiles(W, H)
     px = tiles[:, 0:1] * 8 + (np.arange(64) % 8)[None]
     py = tiles[:, 1:2] * 8 + (np.arange(64) // 8)[None]

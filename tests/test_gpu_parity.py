@@ -188,6 +188,49 @@ def test_constant_texture_exact_on_gpu():
         assert np.all(out == np.float32(0.375)), fp
 
 
+@pytest.mark.parametrize("filt", ["bilinear", "bicubic"])
+def test_float_bin_sums_path(filt):
+    """STF_FLOAT_BIN_SUMS: the whole-tile kernel's FP32-atomic sums of 1/p
+    (the path a wave takes only when it holds a pick of probability below
+    2^-34) on two textures of a ragged screen: selection bit-exact, colours
+    to the oracle's tolerance, and within that of the exact integer sums."""
+    texs = [w.tile_texture_rgba8(3, 64), w.small_texture(5)[:64, :64].copy()]
+    uv = w.small_screen(61, 37, 64, 3.3, offset_seed=4)
+    ftag = FILTERS[filt]
+    dt, duv = [dev(t) for t in texs], dev(uv)
+    outs, sel = stf.filter_reuse(dt, duv, "tile8x8", filt, 7, 3, sel=True, float_bin_sums=True)
+    exact = stf.filter_reuse(dt, duv, "tile8x8", filt, 7, 3)
+    ref = o.stf_filter_reuse(texs, uv, ftag, 7, 3, "tile8x8")
+    sel = host(sel)
+    for slot, (tex, (rv, rs)) in enumerate(zip(texs, ref)):
+        assert np.array_equal(sel[slot], oracle_image(rs, uv)), f"slot {slot}: selection differs"
+        scale = support_scale(tex, uv, ftag)
+        assert_close(host(outs[slot]), oracle_image(rv, uv), scale, f"slot {slot} float sums")
+        assert_close(host(outs[slot]), host(exact[slot]).astype(np.float64), scale, f"slot {slot} vs integer sums")
+
+
+def test_flat_waves_exact_and_mixed_waves_close():
+    """RGBA16F 64^2 whose columns < 32 hold one constant texel value and the
+    rest seeded noise, 128x64 screen at 2x, whole-tile reuse: every tile
+    whose 64 supports lie in the constant columns returns that value bit for
+    bit (the wave shares one texel), the image matches the oracle."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    tex = rng.random((64, 64, 4)).astype(np.float16)
+    tex[:, :32] = np.float16(0.3)
+    uv = w.small_screen(128, 64, 64, 2.0, offset_seed=3)
+    outs, _ = run_case([tex], uv, "bicubic", "tile8x8", seed=5)
+    out = host(outs[0])
+    i0x, _ = o.split_coord(o.texel_float_coord(uv[..., 0], 64))
+    cols = (i0x[..., None] - 1 + np.arange(4)) % 64              # bicubic support columns
+    inside = np.all(cols < 32, axis=-1).reshape(8, 8, 16, 8)      # [tile row, y, tile col, x]
+    flat_tiles = inside.all(axis=(1, 3))
+    assert flat_tiles.any() and not flat_tiles.all()
+    want = np.float32(np.float16(0.3))
+    blocks = out.reshape(8, 8, 16, 8, 4)
+    for ty, tx in zip(*np.nonzero(flat_tiles)):
+        assert np.all(blocks[ty, :, tx] == want), (ty, tx)
+
+
 def test_self_and_disjoint_equal_stf_bit_exact():
     tex = w.tile_texture_rgba8(2, 256)
     uv_far = w.small_screen(64, 64, 256, 1 / 8)        # supports never overlap
