@@ -326,18 +326,6 @@ __device__ __forceinline__ void store_out(float* out, int64_t pix, const float* 
 
 // ---------------------------------------------------------------- DPP
 
-// Maximum of v over the 64 lanes of the wavefront (DPP within rows of 16
-// lanes, then the four row results).
-__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
-    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
-    const uint32_t a = max((uint32_t)__builtin_amdgcn_readlane((int)v, 0), (uint32_t)__builtin_amdgcn_readlane((int)v, 16));
-    const uint32_t b = max((uint32_t)__builtin_amdgcn_readlane((int)v, 32), (uint32_t)__builtin_amdgcn_readlane((int)v, 48));
-    return max(a, b);
-}
-
 // Bitwise OR of v over the 64 lanes of the wavefront (DPP within rows of
 // 16 lanes, then the four row results).
 __device__ __forceinline__ uint32_t wave_or(uint32_t v) {

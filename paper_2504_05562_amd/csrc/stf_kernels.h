@@ -48,10 +48,12 @@ enum Mode { kModeStf = 0, kModeQuad = 1, kModeRecords = 2, kModeBins = 3 };
 // 64-bit fixed-point accumulators, or records (64 x {s, r} + 64 x 16 B).
 constexpr int kAccFloatOffset = kBinRecords * 5;
 constexpr int kLdsFloatsPerWave = kAccFloatOffset + kBinRecords * 2;
-// backward bins: Nb float [kBins], then (8-byte aligned) u64 [kBins] + u64 [kBins][4]
+// backward bins: Nb float [kBins], then (8-byte aligned) u64 [kBins], then
+// (16-byte aligned) one 16-float record per tile pixel for the matrix cores
 constexpr int kBwdN64Offset = (kBins + 1) & ~1;
-constexpr int kBwdLdsFloatsPerWave = kBwdN64Offset + kBins * (1 + 4) * 2;
-static_assert(kBwdLdsFloatsPerWave >= kLdsFloatsPerWave / 2, "backward LDS layout");
+constexpr int kBwdRecOffset = (kBwdN64Offset + kBins * 2 + 3) & ~3;
+constexpr int kBwdLdsFloatsPerWave = kBwdRecOffset + 64 * 16;
+static_assert(kBwdRecOffset % 4 == 0 && kLdsFloatsPerWave % 4 == 0, "16-byte aligned LDS records");
 
 struct Pixel {
     int px, py;          // screen pixel
@@ -377,31 +379,6 @@ __device__ __forceinline__ uint64_t fixed_r(float r) {
 
 __device__ __forceinline__ float float_r(uint64_t n) {
     return fmaf((float)(uint32_t)(n >> 32), 4294967296.0f, (float)(uint32_t)n) * 0x1p-23f;   // within 2 ulp
-}
-
-// Signed sums with a wave-wide scale: with e_ref above the largest biased
-// exponent of the terms, v is stored as the integer v * 2^(183 - e_ref) in
-// two's complement (wrap-around addition is exact; 64 terms of at most 2^57
-// units fit). Magnitudes below 2^(e_ref - 183) truncate toward zero: the
-// absolute error per term is below 2^-57 of the largest term allowed.
-__device__ __forceinline__ float float_of(uint64_t n, uint32_t e_ref) {
-    const float f = fmaf((float)(uint32_t)(n >> 32), 4294967296.0f, (float)(uint32_t)n);   // within 2 ulp
-    return ldexpf(f, (int)e_ref - 183);
-}
-
-__device__ __forceinline__ uint64_t signed_fixed_of(float v, uint32_t e_ref) {
-    const uint32_t b = __float_as_uint(v);
-    const uint32_t e = (b >> 23) & 0xFFu;
-    const uint64_t m = (uint64_t)((b & 0x7FFFFFu) | (e != 0u ? 0x800000u : 0u));
-    const int sh = (int)e - (int)e_ref + 33;
-    const uint64_t a = sh >= 0 ? (m << (sh > 39 ? 39 : sh)) : (sh > -25 ? (m >> -sh) : 0ull);
-    return (b >> 31) ? (0ull - a) : a;
-}
-
-__device__ __forceinline__ float signed_float_of(uint64_t n, uint32_t e_ref) {
-    const bool neg = (int64_t)n < 0;
-    const float f = float_of(neg ? 0ull - n : n, e_ref);
-    return neg ? -f : f;
 }
 
 // Bin window and support box of the wave for one texture size (shared by
@@ -1155,13 +1132,10 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                 use_bins = bin_window<N>(P, ctx.x.base, ctx.y.base, mx, my, t.w, t.h, base_x, base_y, rx, ry);
                 if (use_bins) {
                     // LDS: Nb float [kBins] (sum of 1/p per texel), N64 u64 [kBins]
-                    // (its fixed-point accumulator), Q64 i64 [kBins][C] (sum of
-                    // f_c(x) q_c in fixed point). Integer LDS atomics do not
-                    // serialise on shared addresses the way FP32 ones do.
+                    // (its exact integer accumulator, as in the forward pass)
                     float* Nb = lds;
                     uint64_t* N64 = reinterpret_cast<uint64_t*>(lds + kBwdN64Offset);
-                    uint64_t* Q64 = N64 + kBins;
-                    for (int i = lane; i < kBins * (1 + C); i += 64) N64[i] = 0ull;
+                    for (int i = lane; i < kBins; i += 64) N64[i] = 0ull;
                     for (int i = lane; i < kBins; i += 64) Nb[i] = 0.0f;
                     const int my_bin = (int)(ry + ky) * kBinG + (int)(rx + kx);
                     const bool fixed = !(a.flags & kFlagFloatBinSums) &&
@@ -1182,44 +1156,71 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                     for (int b = 0; b < N; ++b)
 #pragma unroll
                         for (int aa = 0; aa < N; ++aa) B += ctx.wxy[b * N + aa] * Nb[bin0 + b * kBinG + aa];
-                    // |f_c(x) q_c| <= |dL/dout_c| (B >= 1: the own pick contributes
-                    // f_c / p_c = 1), so the wave's largest gradient exponent fixes
-                    // the scale; 64 terms of at most 2^58 units fit in 64 bits
-                    float gmax = 0.0f;
+                    // Sum over the tile's pixels of f_c(x) q_c for every texel x of the
+                    // window (q_c = dL/dout_c / B_c): with f_c(x) = wy_c(row) wx_c(col)
+                    // it is the rank-64 product  Wy diag(q) Wx^T , run on the matrix
+                    // cores: window rows x window columns (12 x 12 in a 16 x 16 tile),
+                    // K = the 64 pixels, four per v_mfma_f32_16x16x4_f32 (A[i][k] and
+                    // B[k][j] of lane l: i = j = l % 16, k = l / 16). Each pixel first
+                    // publishes its support start, weights and q in LDS.
+                    float* rec = lds + kBwdRecOffset;               // [64][16]
+                    {
+                        const float inv = P.valid ? fast_rcp(B) : 0.0f;
+                        float rr[16];
+                        rr[0] = __uint_as_float(P.valid ? (rx | (ry << 8)) : 0xFFFFu);   // off-screen: no support
 #pragma unroll
-                    for (int c = 0; c < C; ++c) gmax = fmaxf(gmax, fabsf(g[c]));
-                    const uint32_t eq = wave_max(__float_as_uint(gmax) >> 23) + 1u;
-                    if (P.valid) {
-                        const float inv = fast_rcp(B);
-                        // lanes visit their support in rotated orders, so one atomic
-                        // instruction mostly hits N*N different bins even where every
-                        // pixel of the tile has the same support (high magnification)
-                        const int rot = lane % (N * N);
+                        for (int b = 0; b < N; ++b) rr[1 + b] = ctx.y.w(b);
 #pragma unroll
-                        for (int k = 0; k < N * N; ++k) {
-                            const int kk = (k + rot) % (N * N);
-                            const int aa = kk % N, b = kk / N;
-                            const int idx = bin0 + b * kBinG + aa;
-                            if (Nb[idx] != 0.0f) {
-                                const float f = ctx.x.wsel((uint32_t)aa) * ctx.y.wsel((uint32_t)b) * inv;
+                        for (int b = 0; b < N; ++b) rr[1 + N + b] = ctx.x.w(b);
 #pragma unroll
-                                for (int c = 0; c < C; ++c)
-                                    atomicAdd(reinterpret_cast<unsigned long long*>(&Q64[idx * C + c]),
-                                              (unsigned long long)signed_fixed_of(f * g[c], eq));
-                            }
-                        }
+                        for (int c = 0; c < C; ++c) rr[1 + 2 * N + c] = g[c] * inv;
+#pragma unroll
+                        for (int k = 1 + 2 * N + C; k < 16; ++k) rr[k] = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            reinterpret_cast<float4*>(rec)[P.q * 4 + k] =
+                                make_float4(rr[4 * k], rr[4 * k + 1], rr[4 * k + 2], rr[4 * k + 3]);
                     }
                     wave_lds_sync();
-                    // flush: lane handles bins lane, lane + 64, ...
-                    for (int idx = lane; idx < kBins; idx += 64) {
-                        const float nx = Nb[idx];
-                        if (nx != 0.0f) {
-                            const uint32_t tx = (uint32_t)(base_x + (idx % kBinG)) & mx;
-                            const uint32_t ty = (uint32_t)(base_y + (idx / kBinG)) & my;
-                            float q[C];
+                    const int ij = lane & 15, kp = lane >> 4;
+                    v4f acc[C];
 #pragma unroll
-                            for (int c = 0; c < C; ++c) q[c] = signed_float_of(Q64[idx * C + c], eq);
-                            atomic_texel<C>(grad, t.w, tx | (ty << 16), q, nx);
+                    for (int c = 0; c < C; ++c) acc[c] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+                    for (int m = 0; m < 16; ++m) {
+                        const float4* rp = reinterpret_cast<const float4*>(rec) + (4 * m + kp) * 4;
+                        float rr[16];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const float4 v = rp[k];
+                            rr[4 * k] = v.x; rr[4 * k + 1] = v.y; rr[4 * k + 2] = v.z; rr[4 * k + 3] = v.w;
+                        }
+                        const uint32_t st = __float_as_uint(rr[0]);
+                        const int dy = ij - (int)(st >> 8), dx = ij - (int)(st & 0xFFu);
+                        float wa = 0.0f, wb = 0.0f;
+#pragma unroll
+                        for (int b = 0; b < N; ++b) {
+                            wa = dy == b ? rr[1 + b] : wa;
+                            wb = dx == b ? rr[1 + N + b] : wb;
+                        }
+#pragma unroll
+                        for (int c = 0; c < C; ++c)
+                            acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, wb * rr[1 + 2 * N + c], acc[c], 0, 0, 0);
+                    }
+                    // flush: lane holds window rows 4 (l / 16) + v, column l % 16
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = 4 * kp + v;
+                        if (i < kBinG && ij < kBinG) {
+                            const float nx = Nb[i * kBinG + ij];
+                            if (nx != 0.0f) {
+                                const uint32_t tx = (uint32_t)(base_x + ij) & mx;
+                                const uint32_t ty = (uint32_t)(base_y + i) & my;
+                                float q[C];
+#pragma unroll
+                                for (int c = 0; c < C; ++c) q[c] = acc[c][v];
+                                atomic_texel<C>(grad, t.w, tx | (ty << 16), q, nx);
+                            }
                         }
                     }
                     wave_lds_sync();
@@ -1259,8 +1260,9 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
     }
 }
 
+// The whole-tile adjoint is budgeted for four waves per SIMD (128 VGPRs).
 template <int FILT, int MODE>
-__global__ __launch_bounds__(kThreads) void backward_kernel(Args a) {
+__global__ __launch_bounds__(kThreads, (MODE == kModeBins ? 4 : 1)) void backward_kernel(Args a) {
     constexpr int kPerWave = kBwdLdsFloatsPerWave > kLdsFloatsPerWave ? kBwdLdsFloatsPerWave : kLdsFloatsPerWave;
     __shared__ __align__(16) float lds_all[kWavesPerGroup * kPerWave];
     Pixel P;
