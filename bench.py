@@ -127,21 +127,28 @@ def cpu_baseline(texs, uv, n_tiles=None, seed=0):
             "sample": f"{n_tiles} of the frame's 8x8 tiles ({px} px), both textures, {dt:.1f} s"}
 
 
-def launch_time(torch, fn, steps, warmup):
-    """Average device time per call of fn() (HIP events on the current
-    stream around `steps` calls, after `warmup` untimed calls)."""
+def launch_time(torch, fn, steps, warmup, batches=1):
+    """Device time per call of fn() (HIP events on the current stream around
+    `steps` calls, after `warmup` untimed calls). With batches > 1 the calls
+    are timed in that many equal batches and the median batch average is
+    returned, so that one stall of the machine does not set a secondary
+    figure (the headline timing uses one batch over its whole timed region)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(steps):
-        fn()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / 1e3 / steps
+    per = max(1, steps // batches)
+    avgs = []
+    for _ in range(batches):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(per):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        avgs.append(ev0.elapsed_time(ev1) / 1e3 / per)
+    return float(np.median(avgs))
 
 
 def psnr_rgb(torch, a, b, peak=1.0):
@@ -170,7 +177,7 @@ def precision_forms(torch, stf, w, uv, steps, warmup):
     for name, (t, scales) in forms.items():
         tex = [t.cuda()]
         dt = launch_time(torch, lambda: stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, out=[out],
-                                                        scales=scales), steps, warmup)
+                                                        scales=scales), steps, warmup, batches=5)
         o = stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, scales=scales)[0]
         r = stf.filter_reference(tex, uv, "bicubic", scales=scales)[0]
         res[name] = {"avg_launch_us": round(dt * 1e6, 2), "Mpixel_s": round(H * W / dt / 1e6, 1),
@@ -188,7 +195,7 @@ def backward_form(torch, stf, texs, uv, steps, warmup):
     g = [torch.randn((H, W, int(t.shape[2])), dtype=torch.float32, device=uv.device) for t in texs]
     dtex = [torch.zeros((int(t.shape[0]), int(t.shape[1]), int(t.shape[2])), dtype=torch.float32, device=uv.device)
             for t in texs]
-    dt = launch_time(torch, lambda: stf.backward(texs, uv, g, "tile8x8", "bicubic", 0, 0, dtex=dtex), steps, warmup)
+    dt = launch_time(torch, lambda: stf.backward(texs, uv, g, "tile8x8", "bicubic", 0, 0, dtex=dtex), steps, warmup, batches=5)
     return {"avg_launch_us": round(dt * 1e6, 2), "Mpixel_s": round(H * W / dt / 1e6, 1),
             "textures": "RGBA16F + RG16F 2048^2, FP32 gradients"}
 
@@ -199,7 +206,7 @@ def shared_selection_form(torch, stf, texs, uv, ref, steps, warmup):
     H, W = uv.shape[:2]
     outs = [torch.empty((H, W, int(t.shape[2])), dtype=torch.float32, device=uv.device) for t in texs]
     dt = launch_time(torch, lambda: stf.filter_reuse(texs, uv, "tile8x8", "bicubic", 0, 0, out=outs,
-                                                    share_selection=True), steps, warmup)
+                                                    share_selection=True), steps, warmup, batches=5)
     o = stf.filter_reuse(texs[:1], uv, "tile8x8", "bicubic", 0, 0, share_selection=True)[0]
     return {"avg_launch_us": round(dt * 1e6, 2), "Mpixel_s": round(H * W / dt / 1e6, 1),
             "psnr_albedo_db": round(psnr_rgb(torch, o, ref), 2)}
@@ -265,11 +272,11 @@ def latent_form(torch, stf, w, steps, warmup):
     scales = [list(sc)]
     out = torch.empty((H, W, 4), dtype=torch.float32, device=uv.device)
     t_r = launch_time(torch, lambda: stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, out=[out], scales=scales,
-                                                      decoder=dec), steps, warmup)
+                                                      decoder=dec), steps, warmup, batches=5)
     t_s = launch_time(torch, lambda: stf.filter(tex, uv, "bicubic", 0, 0, out=[out], scales=scales, decoder=dec),
-                      steps, warmup)
+                      steps, warmup, batches=5)
     t_f = launch_time(torch, lambda: stf.filter_reference(tex, uv, "bicubic", out=[out], scales=scales, decoder=dec),
-                      max(steps // 10, 5), 2)
+                      max(steps // 10, 5), 2, batches=5)
     ref = stf.filter_reference(tex, uv, "bicubic", scales=scales, decoder=dec)[0]
     o_r = stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, scales=scales, decoder=dec)[0]
     o_s = stf.filter(tex, uv, "bicubic", 0, 0, scales=scales, decoder=dec)[0]
@@ -281,9 +288,9 @@ def latent_form(torch, stf, w, steps, warmup):
                 "decode_tflops": round(px * decodes * DECODE_FLOPS_PER_TEXEL / t / 1e12, 1)}
 
     t_r8 = launch_time(torch, lambda: stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, out=[out], scales=scales,
-                                                       decoder=dec8), steps, warmup)
+                                                       decoder=dec8), steps, warmup, batches=5)
     t_s8 = launch_time(torch, lambda: stf.filter(tex, uv, "bicubic", 0, 0, out=[out], scales=scales, decoder=dec8),
-                       steps, warmup)
+                       steps, warmup, batches=5)
     o_r8 = stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, scales=scales, decoder=dec8)[0]
     fp8 = {"reuse_tile8x8": row(t_r8, 1), "stf_1sample": row(t_s8, 1),
            "psnr_reuse_db": round(psnr_rgb(torch, o_r8, ref, peak), 2),
