@@ -690,9 +690,10 @@ __device__ __forceinline__ int payload_of(int fmt) {
 // lane: 512 / waves, in steps of 8). The whole-tile kernel issues VALU most
 // of the time and hides its memory and LDS latency with occupancy: with up
 // to two textures it fits 72 VGPRs (seven waves; one texture fits 64, eight
-// waves), with more it keeps 80 (six waves) rather than spill.
+// waves), with more it keeps 80 (six waves) rather than spill; with the
+// latent decoder and one texture it keeps 128 (four waves).
 template <int MODE, int NT, bool DEC, bool EF>
-constexpr int kForwardWaves = (MODE == kModeBins && !DEC && !EF) ? (NT <= 2 ? 7 : 6) : 1;
+constexpr int kForwardWaves = (MODE == kModeBins && !EF) ? (DEC ? (NT == 1 ? 4 : 1) : NT <= 2 ? 7 : 6) : 1;
 
 // Screen tile rows each forward wave filters one after the other (one tile
 // column): the next row's UV is loaded while the current row is filtered,
