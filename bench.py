@@ -17,6 +17,7 @@ precisions, the backward pass, and latent textures decoded by the MLP.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -139,6 +140,7 @@ def launch_time(torch, fn, steps, warmup, batches=1):
     stream = torch.cuda.current_stream()
     per = max(1, steps // batches)
     avgs = []
+    gc.disable()
     for _ in range(batches):
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
@@ -148,6 +150,7 @@ def launch_time(torch, fn, steps, warmup, batches=1):
         ev1.record(stream)
         torch.cuda.synchronize()
         avgs.append(ev0.elapsed_time(ev1) / 1e3 / per)
+    gc.enable()
     return float(np.median(avgs))
 
 
@@ -392,6 +395,7 @@ def main():
         stream = torch.cuda.current_stream()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
+        gc.disable()                       # no collector pause while the launches are queued
         t0 = time.perf_counter()
         ev0.record(stream)
         for i in range(args.steps):
@@ -399,6 +403,7 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        gc.enable()
         return wall, ev0.elapsed_time(ev1) / 1e3
 
     wall_r, gpu_r = timed("reuse")
