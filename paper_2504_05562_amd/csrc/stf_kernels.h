@@ -497,7 +497,8 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
         return;
     } else {
         // 1/p of the own pick; off-screen pixels share a pick of weight zero
-        const float r = P.valid ? fast_rcp(ctx.x.wsel(kx) * ctx.y.wsel(ky)) : 0.0f;
+        const float pc = ctx.x.wsel(kx) * ctx.y.wsel(ky);
+        const float r = P.valid ? fast_rcp(pc) : 0.0f;
         if (!P.valid) {
 #pragma unroll
             for (int c = 0; c < C; ++c) Tv[c] = 0.0f;
@@ -509,6 +510,7 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
         for (int c = 0; c < C; ++c) acc[c] = 0.0f;
         Coverage<FILT, EF ? C : 1> cov;            // used only with EF
         bool covered = false;
+        bool lone = false;                         // whole tile: no other pick in the support
 
         if constexpr (MODE == kModeQuad) {
             if constexpr (EF) cov.add(ctx, (uint32_t)kx, (uint32_t)ky, Tv);
@@ -575,9 +577,14 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
                         B = 1.0f;
 #pragma unroll
                         for (int c = 0; c < C; ++c) acc[c] = 0.0f;
-                    } else {                         // out = acc / B: no T_c term
+                    } else {
+                        // No other pick of positive weight in the support: B is then exactly
+                        // the own bin's term p_c r_c (the other bins add exact zeros), and
+                        // Eq. (14) is the own texel, returned as one-tap STF returns it.
+                        // Otherwise out = acc / B, with no T_c term.
+                        lone = B == pc * r;
 #pragma unroll
-                        for (int c = 0; c < C; ++c) Tv[c] = 0.0f;
+                        for (int c = 0; c < C; ++c) Tv[c] = lone ? Tv[c] : 0.0f;
                     }
                 }
             }
@@ -610,7 +617,7 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
         }
         if (P.valid) {
             float o[C];
-            const float inv = fast_rcp(B);
+            const float inv = lone ? 0.0f : fast_rcp(B);
 #pragma unroll
             for (int c = 0; c < C; ++c) o[c] = fmaf(acc[c], inv, Tv[c]);
             if constexpr (EF) {

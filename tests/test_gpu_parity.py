@@ -231,6 +231,40 @@ def test_flat_waves_exact_and_mixed_waves_close():
         assert np.all(blocks[ty, :, tx] == want), (ty, tx)
 
 
+def lone_pixels(sel, uv, tex_size):
+    """Pixels of full 8x8 tiles whose bilinear support (its texels of positive
+    weight) holds no pick of another pixel of the same tile."""
+    H, W = uv.shape[:2]
+    i0x, Fx = o.split_coord(o.texel_float_coord(uv[..., 0], tex_size))
+    i0y, Fy = o.split_coord(o.texel_float_coord(uv[..., 1], tex_size))
+    tiles = lambda a: a.reshape(H // 8, 8, W // 8, 8, *a.shape[2:]).swapaxes(1, 2).reshape(H // 8, W // 8, 64, *a.shape[2:])
+    sx, sy = tiles(sel[..., 0]), tiles(sel[..., 1])
+    bx, by, fx, fy = tiles(i0x), tiles(i0y), tiles(Fx), tiles(Fy)
+    dx = (sx[..., None, :] - bx[..., :, None]) % tex_size          # [ty, tx, c, i]
+    dy = (sy[..., None, :] - by[..., :, None]) % tex_size
+    inside = ((dx == 0) | ((dx == 1) & (fx[..., :, None] > 0))) & ((dy == 0) | ((dy == 1) & (fy[..., :, None] > 0)))
+    inside &= ~np.eye(64, dtype=bool)
+    lone = ~inside.any(-1)                                           # [ty, tx, c]
+    return lone.reshape(H // 8, W // 8, 8, 8).swapaxes(1, 2).reshape(H, W)
+
+
+def test_whole_tile_lone_picks_equal_stf_bit_exact():
+    """Whole-tile bins at 1.6x, bilinear (low enough for lone picks, high
+    enough that every tile's supports fit the 12x12 bin window): a pixel
+    whose support holds no other pick of its tile returns its one-tap value
+    bit for bit, the exact fallback of Eq. (14)."""
+    tex = w.tile_texture_rgba8(7, 256)
+    uv = w.small_screen(1024, 512, 256, 1.6, offset_seed=9)
+    i0x, _ = o.split_coord(o.texel_float_coord(uv[..., 0], 256))
+    starts = i0x.reshape(64, 8, 128, 8).swapaxes(1, 2).reshape(64, 128, 64)
+    assert np.all(starts.max(-1) - starts.min(-1) <= 5)               # the window fits every tile
+    reuse, sel = stf.filter_reuse([dev(tex)], dev(uv), "tile8x8", "bilinear", 2, 0, sel=True)
+    one = stf.filter([dev(tex)], dev(uv), "bilinear", 2, 0)
+    lone = lone_pixels(host(sel)[0], uv, 256)
+    assert lone.sum() > 100
+    assert np.array_equal(host(reuse[0])[lone], host(one[0])[lone])
+
+
 def test_self_and_disjoint_equal_stf_bit_exact():
     tex = w.tile_texture_rgba8(2, 256)
     uv_far = w.small_screen(64, 64, 256, 1 / 8)        # supports never overlap
