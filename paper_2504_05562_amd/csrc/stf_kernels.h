@@ -318,19 +318,44 @@ template <> struct Bins<kF32x4> {             // float4 T[kBinRecords], then flo
     }
 };
 
-// Bin window of the wave: kBinG x kBinG texels whose corner sits `margin`
-// texels before lane 0's support. Returns false (wave-uniformly) when some
-// on-screen pixel's support leaves the window.
+// Offset of support start b from lane 0's b0 modulo the texture size m + 1,
+// taken in [-(m + 1) / 2, (m + 1) / 2).
+__device__ __forceinline__ int wrapped_offset(int b, int b0, uint32_t m) {
+    const int d = (int)((uint32_t)(b - b0) & m);
+    return d > (int)(m >> 1) ? d - (int)m - 1 : d;
+}
+
+// Bin window of the wave: kBinG x kBinG texels, first with its corner
+// `margin` texels before lane 0's support (no reduction: the common case at
+// magnification); if some pixel's support leaves that, from the wave's
+// smallest support start (two wave reductions per axis), which holds every
+// tile whose support starts spread over at most kBinG - N texels per axis
+// (about 1x magnification for the B-spline, 0.8x for bilinear). Returns
+// false (wave-uniformly) when neither placement holds every support. Lanes
+// off the screen read the UV of their nearest on-screen pixel, so their
+// supports are among the on-screen ones.
 template <int N>
 __device__ __forceinline__ bool bin_window(const Pixel& P, int bx, int by, uint32_t mx, uint32_t my, int tw, int th,
                                            int& base_x, int& base_y, uint32_t& rx, uint32_t& ry) {
     constexpr int margin = (kBinG - N) / 2;
-    base_x = __builtin_amdgcn_readfirstlane(bx) - margin;
-    base_y = __builtin_amdgcn_readfirstlane(by) - margin;
+    constexpr int span = kBinG - N;
+    if (tw < kBinG || th < kBinG) return false;
+    const int x0 = __builtin_amdgcn_readfirstlane(bx), y0 = __builtin_amdgcn_readfirstlane(by);
+    base_x = x0 - margin;
+    base_y = y0 - margin;
     rx = (uint32_t)(bx - base_x) & mx;
     ry = (uint32_t)(by - base_y) & my;
-    const bool fits = !P.valid || (rx <= (uint32_t)(kBinG - N) && ry <= (uint32_t)(kBinG - N));
-    return (tw >= kBinG) && (th >= kBinG) && (__builtin_amdgcn_ballot_w64(!fits) == 0);
+    const bool fits = !P.valid || (rx <= (uint32_t)span && ry <= (uint32_t)span);
+    if (__builtin_amdgcn_ballot_w64(!fits) == 0) return true;
+    const int dx = wrapped_offset(bx, x0, mx), dy = wrapped_offset(by, y0, my);
+    const int lo_x = wave_min(dx), hi_x = -wave_min(-dx);
+    const int lo_y = wave_min(dy), hi_y = -wave_min(-dy);
+    if (hi_x - lo_x > span || hi_y - lo_y > span) return false;
+    base_x = x0 + lo_x;
+    base_y = y0 + lo_y;
+    rx = (uint32_t)(dx - lo_x);
+    ry = (uint32_t)(dy - lo_y);
+    return true;
 }
 
 // Bounding box, in window coordinates, of every on-screen pixel's support:

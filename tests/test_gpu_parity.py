@@ -121,6 +121,20 @@ def test_tile_bins_fallback_under_minification():
     run_case([w.small_texture(1)], uv, "bicubic", "tile8x8", seed=1)
 
 
+@pytest.mark.parametrize("filt,mag", [("bicubic", 1.05), ("bilinear", 0.85)])
+def test_tile_bins_window_from_wave_minimum(filt, mag):
+    """Near 1x the tile's support starts spread over more texels than the
+    window centred on lane 0 allows but at most 12 - N: the kernel places the
+    window at the wave's smallest start instead (61x45 screen: partial tiles)."""
+    uv = w.small_screen(61, 45, 256, mag, offset_seed=2)
+    n, margin = (4, 4) if filt == "bicubic" else (2, 5)
+    i0x, _ = o.split_coord(o.texel_float_coord(uv[:40, :56, 0], 256))
+    spread = i0x.reshape(5, 8, 7, 8).swapaxes(1, 2).reshape(5, 7, 64)
+    spread = spread.max(-1) - spread.min(-1)
+    assert np.all(spread > margin) and np.all(spread <= 12 - n)      # full tiles: second placement
+    run_case([w.small_texture(1)], uv, filt, "tile8x8", seed=6, frame=1)
+
+
 def test_tiny_inputs():
     run_case([w.tile_texture_rgba8(1, 4)], w.small_screen(1, 1, 4, 2.0), "bicubic", "tile8x8")
     run_case([w.tile_texture_rgba8(1, 4)], w.small_screen(3, 9, 4, 2.0), "bilinear", "quad2x2")
