@@ -12,6 +12,11 @@
 #include "stf_kernels.h"
 #include "stf_status.h"
 
+// The whole-tile kernels keep their 64-bit sums zero between textures of one
+// size (the finalisation clears them); the latent decode's LDS scratch, used
+// in between, must stay below them.
+static_assert(stf::kDedupBytes <= stf::kAccFloatOffset * 4, "decode scratch overlaps the whole-tile sums");
+
 namespace stf {
 
 // Pack the decoder MLP for decode_latent. BF16: A operands in lane order
