@@ -54,7 +54,7 @@ extern "C" {
 typedef enum stf_status {
     STF_OK = 0,
     STF_EINVAL = -1,        /* bad pointer, size, enum value or layout */
-    STF_EUNSUPPORTED = -2,  /* valid request this build does not implement */
+    STF_EUNSUPPORTED = -2,  /* valid request the library does not implement */
     STF_EHIP = -3           /* the HIP runtime reported an error at launch */
 } stf_status;
 
