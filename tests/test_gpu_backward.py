@@ -75,5 +75,5 @@ def test_autograd_function_and_fitting():
             loss = loss + ((out - ref) ** 2).mean()
         loss.backward()
         opt.step()
-        losses.append(float(loss))
+        losses.append(float(loss.detach()))
     assert losses[-1] < 0.1 * losses[0], (losses[0], losses[-1])
