@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpixel/s filtered (reuse vs 1-sample STF) @1080p bicubic, %HBM peak, PSNR dB"
 HBM_PEAK_GBS = 8000.0
+SIMDS = 256 * 4                  # 256 compute units x 4 SIMDs
+CLOCK_HZ = 2.4e9
 KERNEL_SOURCES = ["paper_2504_05562_amd/csrc/stf_kernels.h", "paper_2504_05562_amd/csrc/stf_device.h",
                   "paper_2504_05562_amd/csrc/stf_decoder.h"]
 BENCH_KERNEL = "forward_kernel<1, 3, 2, false, false>"     # bicubic, whole-tile bins, 2 textures
@@ -45,25 +47,44 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
+def counter_summary():
+    """The committed rocprofv3 counter summary of the benchmark kernel, if it
+    was taken on the current kernel source; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("source_hash") != source_hash():
+    return d if d.get("source_hash") == source_hash() else None
+
+
+def measured_traffic():
+    """HBM bytes per launch from the counter summary, or None."""
+    d = counter_summary()
+    return None if d is None else d.get("bytes_per_launch")
+
+
+def valu_issue(launch_s):
+    """VALU issue of the benchmark kernel: SQ_INSTS_VALU per wave from the
+    counter summary times the waves, 4 clocks each (a wave64 instruction on a
+    16-lane SIMD), over what 1024 SIMDs at 2.4 GHz issue in one launch time.
+    None without a current summary."""
+    d = counter_summary()
+    if d is None or "valu_per_wave" not in d:
         return None
-    return d.get("bytes_per_launch")
+    clocks = d["valu_per_wave"] * d["waves"] * 4.0
+    return {"valu_per_wave": d["valu_per_wave"], "waves": d["waves"],
+            "frac_of_simd_clocks": round(clocks / (SIMDS * CLOCK_HZ * launch_s), 4)}
 
 
-def summarize_pmc(fetch_csv: str, write_csv: str, out_path: str = TRAFFIC_FILE) -> dict:
+def summarize_pmc(fetch_csv: str, write_csv: str, sq_csv: str | None = None, out_path: str = TRAFFIC_FILE) -> dict:
     """Per-launch HBM traffic of the benchmarked reuse kernel from two
     rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
     dispatch). Each counter is scaled by what it reads for the 512 MB copy of
     the copy probe (whose true bytes are known), so the result is in bytes.
-    Only the two-texture dispatches (the timed launches) are averaged."""
+    Only the two-texture dispatches (the timed launches) are averaged. With a
+    third run's CSV holding SQ_INSTS_VALU, also the VALU instructions per
+    wave (waves = grid threads / 64)."""
     import csv
 
     def per_kernel(path, counter):
@@ -88,6 +109,13 @@ def summarize_pmc(fetch_csv: str, write_csv: str, out_path: str = TRAFFIC_FILE) 
          "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
          "fetch_bytes_per_launch": int(fetch), "write_bytes_per_launch": int(write),
          "bytes_per_launch": int(fetch + write), "launches_averaged": [len(f_k), len(w_sorted)]}
+    if sq_csv is not None:
+        rows = [r for r in csv.DictReader(open(sq_csv))
+                if BENCH_KERNEL in r["Kernel_Name"] and r["Counter_Name"] == "SQ_INSTS_VALU"]
+        if rows:
+            waves = [int(r["Grid_Size"]) // 64 for r in rows]
+            d["valu_per_wave"] = round(sum(float(r["Counter_Value"]) for r in rows) / sum(waves), 1)
+            d["waves"] = max(waves)
     with open(out_path, "w") as f:
         json.dump(d, f, indent=1)
     return d
@@ -396,7 +424,7 @@ def main():
                     help="skip the precision, backward and latent-decoder comparisons")
     ap.add_argument("--profile", choices=["latent", "backward"],
                     help="only run 5 launches of the latent-decoder or backward workload (for rocprofv3) and exit")
-    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="CSV",
                     help="write the per-launch traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
     if args.summarize_pmc:
@@ -512,6 +540,7 @@ def main():
             "kernel": "forward_kernel<bicubic, bins>", "algorithmic_bytes_per_launch": alg_bytes,
             "avg_launch_us": round(launch_s * 1e6, 3),
             "frac_of_copy_probe": round(achieved / probe["gbs"], 4), "copy_probe_gbs": probe["gbs"],
+            "valu_issue": valu_issue(launch_s),
         },
         "stf_1sample": {
             "value": round(px * args.steps / wall_s / 1e6, 1), "unit": "Mpixel/s",
