@@ -379,6 +379,11 @@ __device__ __forceinline__ BinBox support_box(const Pixel& P, uint32_t rx, uint3
 // (lane -> (lane & 7, lane >> 3)); wave-uniform trip counts.
 template <typename F>
 __device__ __forceinline__ void for_box(const BinBox& b, int lane, F f) {
+    const int x = b.x0 + (lane & 7), y = b.y0 + (lane >> 3);
+    if (b.x1 - b.x0 < 8 && b.y1 - b.y0 < 8) {          // one block (magnification >= ~1.6x)
+        if (x <= b.x1 && y <= b.y1) f(y * kBinStride + x);
+        return;
+    }
     for (int by = b.y0; by <= b.y1; by += 8)
         for (int bx = b.x0; bx <= b.x1; bx += 8) {
             const int x = bx + (lane & 7), y = by + (lane >> 3);
@@ -403,7 +408,8 @@ __device__ __forceinline__ uint64_t fixed_r(float r) {
 }
 
 __device__ __forceinline__ float float_r(uint64_t n) {
-    return fmaf((float)(uint32_t)(n >> 32), 4294967296.0f, (float)(uint32_t)n) * 0x1p-23f;   // within 2 ulp
+    // n < 2^63, so its high word is below 2^31 and converts as a signed int
+    return fmaf((float)(int32_t)(n >> 32), 4294967296.0f, (float)(uint32_t)n) * 0x1p-23f;   // within 2 ulp
 }
 
 // Bin window and support box of the wave for one texture size (shared by
