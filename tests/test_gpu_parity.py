@@ -121,16 +121,22 @@ def test_tile_bins_fallback_under_minification():
     run_case([w.small_texture(1)], uv, "bicubic", "tile8x8", seed=1)
 
 
-@pytest.mark.parametrize("filt,mag", [("bicubic", 1.05), ("bilinear", 0.85)])
-def test_tile_bins_window_from_wave_minimum(filt, mag):
+@pytest.mark.parametrize("filt,mag,seam", [("bicubic", 1.05, False), ("bilinear", 0.85, False),
+                                           ("bicubic", 1.05, True)])
+def test_tile_bins_window_from_wave_minimum(filt, mag, seam):
     """Near 1x the tile's support starts spread over more texels than the
     window centred on lane 0 allows but at most 12 - N: the kernel places the
-    window at the wave's smallest start instead (61x45 screen: partial tiles)."""
+    window at the wave's smallest start instead (61x45 screen: partial tiles;
+    seam: the screen starts 20 texels before the wrap-around in u and v, so
+    windows straddle it)."""
     uv = w.small_screen(61, 45, 256, mag, offset_seed=2)
+    if seam:
+        uv = ((uv + np.float32(236.0 / 256.0)) % np.float32(1.0)).astype(np.float32)
     n, margin = (4, 4) if filt == "bicubic" else (2, 5)
     i0x, _ = o.split_coord(o.texel_float_coord(uv[:40, :56, 0], 256))
-    spread = i0x.reshape(5, 8, 7, 8).swapaxes(1, 2).reshape(5, 7, 64)
-    spread = spread.max(-1) - spread.min(-1)
+    starts = i0x.reshape(5, 8, 7, 8).swapaxes(1, 2).reshape(5, 7, 64)
+    d = (starts - starts[..., :1] + 128) % 256 - 128                  # offsets across the wrap
+    spread = d.max(-1) - d.min(-1)
     assert np.all(spread > margin) and np.all(spread <= 12 - n)      # full tiles: second placement
     run_case([w.small_texture(1)], uv, filt, "tile8x8", seed=6, frame=1)
 
