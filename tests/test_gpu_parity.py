@@ -312,6 +312,30 @@ def test_convex_hull_on_gpu():
         assert np.all(out >= lo - slack) and np.all(out <= hi + slack), fp
 
 
+def test_side_stream_launches_match_current_stream():
+    """The entry points enqueue on the stream they are given (the current
+    torch stream by default): results computed on a side stream of default
+    priority equal those of the current stream, bit for bit."""
+    tex = dev(w.tile_texture_rgba8(2, 64))
+    uv = dev(w.small_screen(64, 48, 64, 3.0, offset_seed=1))
+    calls = {
+        "reuse": lambda **k: stf.filter_reuse([tex], uv, "tile8x8", "bicubic", 3, **k)[0],
+        "quad": lambda **k: stf.filter_reuse([tex], uv, "quad2x2", "bilinear", 3, **k)[0],
+        "stf": lambda **k: stf.filter([tex], uv, "bicubic", 3, **k)[0],
+        "reference": lambda **k: stf.filter_reference([tex], uv, "bicubic", **k)[0],
+    }
+    want = {name: host(fn()) for name, fn in calls.items()}
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):                   # current stream = side
+        got = {name: fn() for name, fn in calls.items()}
+    side.synchronize()
+    explicit = {name: fn(stream=side) for name, fn in calls.items()}
+    side.synchronize()
+    for name in calls:
+        assert np.array_equal(host(got[name]), want[name]), name
+        assert np.array_equal(host(explicit[name]), want[name]), name
+
+
 def test_deterministic_bits(plane):
     texs, uv = plane
     dt = [dev(t) for t in texs]
