@@ -271,6 +271,60 @@ def estimator_sweep(torch, stf, w, frames=4):
     return {"psnr_db_by_magnification": rows, "footprint": "square3x3", "filter": "bilinear", "frames": frames}
 
 
+def material_form(torch, stf, w, steps, warmup):
+    """Four textures sharing one UV set (albedo RGBA8 2048^2, normal RG16F
+    2048^2, roughness R8 1024^2, mask R8 512^2), bicubic, perspective plane
+    at 2x-32x. Launch times at 3840x2160 of one-tap STF, whole-tile reuse
+    (independent and shared selection) and the deterministic filter (the
+    full-filter cost); then 16 frames at 1920x1080 with Halton sub-pixel
+    jitter and frame-indexed seeds: PSNR of one-tap STF and of reuse against
+    the deterministic filter, per frame (mean squared error over the frames)
+    and for the 16-frame average against the average of the references."""
+    texs = [torch.from_numpy(np.ascontiguousarray(t)).cuda() for t in w.material_set(0)]
+    chans = [4, 2, 1, 1]
+    uv = torch.from_numpy(w.perspective_plane(3840, 2160, 2048, 2.0, 32.0)[0]).cuda()
+    outs = [torch.empty((2160, 3840, c), dtype=torch.float32, device=uv.device) for c in chans]
+    px = 3840 * 2160
+
+    def row(fn, n, wu):
+        t = launch_time(torch, fn, n, wu, batches=5)
+        return {"avg_launch_us": round(t * 1e6, 2), "Mpixel_s": round(px / t / 1e6, 1)}
+
+    res = {"screen": [3840, 2160], "textures": ["RGBA8 2048^2", "RG16F 2048^2", "R8 1024^2", "R8 512^2"],
+           "stf_1sample": row(lambda: stf.filter(texs, uv, "bicubic", 0, 0, out=outs), steps, warmup),
+           "reuse_tile8x8": row(lambda: stf.filter_reuse(texs, uv, "tile8x8", "bicubic", 0, 0, out=outs), steps, warmup),
+           "reuse_shared_selection": row(lambda: stf.filter_reuse(texs, uv, "tile8x8", "bicubic", 0, 0, out=outs,
+                                                                  share_selection=True), steps, warmup),
+           "deterministic_filter": row(lambda: stf.filter_reference(texs, uv, "bicubic", out=outs),
+                                       max(steps // 4, 5), 2)}
+    res["full_filter_cost_vs_stf"] = round(res["deterministic_filter"]["avg_launch_us"]
+                                           / res["stf_1sample"]["avg_launch_us"], 2)
+    del outs, uv
+    mse = {"stf": np.zeros(4), "reuse": np.zeros(4)}
+    acc = {k: [None] * 4 for k in ("stf", "reuse", "ref")}
+    frames = 16
+    for f in range(frames):
+        uvf = torch.from_numpy(w.perspective_plane(1920, 1080, 2048, 2.0, 32.0, jitter=w.frame_jitter(f))[0]).cuda()
+        got = {"ref": stf.filter_reference(texs, uvf, "bicubic"),
+               "reuse": stf.filter_reuse(texs, uvf, "tile8x8", "bicubic", 1000 + f, f),
+               "stf": stf.filter(texs, uvf, "bicubic", 1000 + f, f)}
+        for t in range(4):
+            for k in ("stf", "reuse"):
+                mse[k][t] += float(((got[k][t].double() - got["ref"][t].double()) ** 2).mean()) / frames
+            for k in acc:
+                acc[k][t] = got[k][t].double() if acc[k][t] is None else acc[k][t] + got[k][t].double()
+
+    def psnr(m):
+        return [round(10.0 * float(np.log10(1.0 / v)), 2) for v in m]
+
+    avg = {k: psnr([float(((acc[k][t] - acc["ref"][t]) ** 2).mean()) / frames ** 2 for t in range(4)])
+           for k in ("stf", "reuse")}
+    res["frames_1080p"] = {"frames": frames, "psnr_per_frame_db": {"stf": psnr(mse["stf"]), "reuse": psnr(mse["reuse"])},
+                           "psnr_16_frame_average_db": avg, "peak": 1.0,
+                           "order": ["albedo", "normal", "roughness", "mask"]}
+    return res
+
+
 def fitting_form(torch, stf, w, steps=100):
     """Texture optimisation through the adjoint: a 1024^2 RGBA FP32 texture,
     initialised to 0.5, fitted with Adam (lr 0.05) to the deterministic
@@ -558,6 +612,7 @@ def main():
         res["estimators"] = estimator_sweep(torch, stf, w)
         res["footprint_generator"] = footprint_generator_form(torch, stf)
         res["texture_fitting"] = fitting_form(torch, stf, w)
+        res["materials_4k"] = material_form(torch, stf, w, args.steps // 4, args.warmup // 2)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(texs_np, uv_np)
     print(json.dumps(res), flush=True)
