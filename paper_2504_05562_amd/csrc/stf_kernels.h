@@ -728,7 +728,8 @@ __device__ __forceinline__ int payload_of(int fmt) {
 // lane: 512 / waves, in steps of 8). The whole-tile kernel issues VALU most
 // of the time and hides its memory and LDS latency with occupancy: with up
 // to two textures it fits 72 VGPRs (seven waves; one texture fits 64, eight
-// waves), with more it keeps 80 (six waves) rather than spill; with the
+// waves), with more it keeps 80 (six waves; four textures spill a few
+// registers, and 96 without spills, five waves, measured no faster); with the
 // latent decoder and one texture it keeps 128 (four waves).
 template <int MODE, int NT, bool DEC, bool EF>
 constexpr int kForwardWaves = (MODE == kModeBins && !EF) ? (DEC ? (NT == 1 ? 4 : 1) : NT <= 2 ? 7 : 6) : 1;
@@ -759,14 +760,12 @@ __device__ __forceinline__ void forward_tile(const Args& a, Pixel& P, float* lds
         uint32_t hx, hy;
         slot_uniforms(a, P, i, hq, hx, hy);
         ctx.update(P, t[i].w, t[i].h);
-        if (a.leader[i] == i) {
-            pk[i] = pick_slot<FILT>(t[i], ctx, hx, hy);
-        } else {                               // shared selection: the leader's texel of this texture
-#pragma unroll
-            for (int j = 0; j < i; ++j)
-                if (a.leader[i] == j) pk[i] = pk[j];
-            pk[i].raw = fetch_block(t[i], pk[i].sx, pk[i].sy, format_bytes(t[i].fmt));
-        }
+        // shared selection: the leader has this texture's size, so its random
+        // numbers pick the same texel here (recomputed rather than copied from
+        // the leader's pick: a copy under a runtime slot index makes the
+        // compiler keep every pick in scratch memory)
+        if (a.leader[i] != i) keyed_uniforms(a, P, i, hx, hy);
+        pk[i] = pick_slot<FILT>(t[i], ctx, hx, hy);
     }
     if (more) uv_next = load_uv(a, P.px, P.py + kTile);
     BinGeom<AxisCtx<FILT>::N> geom;
