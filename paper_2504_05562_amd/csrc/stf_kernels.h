@@ -763,8 +763,8 @@ __device__ __forceinline__ void forward_tile(const Args& a, Pixel& P, float* lds
         // shared selection: the leader has this texture's size, so its random
         // numbers pick the same texel here (recomputed rather than copied from
         // the leader's pick: a copy under a runtime slot index makes the
-        // compiler keep every pick in scratch memory)
-        if (a.leader[i] != i) keyed_uniforms(a, P, i, hx, hy);
+        // compiler keep every pick in scratch memory); slot 0 leads always
+        if (i > 0 && a.leader[i] != i) keyed_uniforms(a, P, i, hx, hy);
         pk[i] = pick_slot<FILT>(t[i], ctx, hx, hy);
     }
     if (more) uv_next = load_uv(a, P.px, P.py + kTile);
