@@ -755,16 +755,25 @@ __device__ __forceinline__ void forward_tile(const Args& a, Pixel& P, float* lds
     SelCtx<FILT> ctx;
     SlotPick pk[NT];
     uint4 hq;
+    uint32_t hxs[NT], hys[NT];
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
         uint32_t hx, hy;
         slot_uniforms(a, P, i, hq, hx, hy);
         ctx.update(P, t[i].w, t[i].h);
-        // shared selection: the leader has this texture's size, so its random
-        // numbers pick the same texel here (recomputed rather than copied from
-        // the leader's pick: a copy under a runtime slot index makes the
-        // compiler keep every pick in scratch memory); slot 0 leads always
-        if (i > 0 && a.leader[i] != i) keyed_uniforms(a, P, i, hx, hy);
+        // shared selection: the leader, an earlier slot of this texture's
+        // size, picks the same texel here with its own random numbers. They
+        // are selected value by value (copying the leader's whole pick under
+        // a runtime slot index made the compiler keep every pick in scratch
+        // memory).
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+            const bool lead = a.leader[i] == j;
+            hx = lead ? hxs[j] : hx;
+            hy = lead ? hys[j] : hy;
+        }
+        hxs[i] = hx;
+        hys[i] = hy;
         pk[i] = pick_slot<FILT>(t[i], ctx, hx, hy);
     }
     if (more) uv_next = load_uv(a, P.px, P.py + kTile);
