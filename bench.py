@@ -451,6 +451,15 @@ def profile_launches(torch, stf, w, which, n=5):
         dtex = [torch.zeros((2048, 2048, int(t.shape[2])), device=dev) for t in texs]
         for _ in range(n):
             stf.backward(texs, uv, g, "tile8x8", "bicubic", 0, 0, dtex=dtex)
+    elif which == "materials":
+        texs = [torch.from_numpy(np.ascontiguousarray(t)).to(dev) for t in w.material_set(0)]
+        uv = torch.from_numpy(w.perspective_plane(3840, 2160, 2048, 2.0, 32.0)[0]).to(dev)
+        outs = [torch.empty((2160, 3840, c), device=dev) for c in (4, 2, 1, 1)]
+        for _ in range(n):
+            stf.filter(texs, uv, "bicubic", 0, 0, out=outs)
+            stf.filter_reuse(texs, uv, "tile8x8", "bicubic", 0, 0, out=outs)
+            stf.filter_reuse(texs, uv, "tile8x8", "bicubic", 0, 0, out=outs, share_selection=True)
+        stf.filter_reference(texs, uv, "bicubic", out=outs)
     else:
         uv = torch.from_numpy(w.perspective_plane(1920, 1080, 1024, 4.0, 16.0)[0]).to(dev)
         lat = w.latent_grid(0, 1024).astype(np.float64)
@@ -476,8 +485,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision, backward and latent-decoder comparisons")
-    ap.add_argument("--profile", choices=["latent", "backward"],
-                    help="only run 5 launches of the latent-decoder or backward workload (for rocprofv3) and exit")
+    ap.add_argument("--profile", choices=["latent", "backward", "materials"],
+                    help="only run 5 launches of the latent-decoder, backward or 4K four-texture workload "
+                         "(for rocprofv3) and exit")
     ap.add_argument("--summarize-pmc", nargs="+", metavar="CSV",
                     help="write the per-launch traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
