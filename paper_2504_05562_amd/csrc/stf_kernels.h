@@ -500,7 +500,10 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
     const int lane = lane_id();
     const int kx = pk.kx, ky = pk.ky;
     const uint32_t mx = (uint32_t)t.w - 1u, my = (uint32_t)t.h - 1u;
-    const uint32_t sx = pk.sx, sy = pk.sy;
+    // reuse modes recompute the picked texel from the offsets, so that the
+    // pick's copies are not kept live across the other slots' passes
+    const uint32_t sx = MODE == kModeStf ? pk.sx : (uint32_t)(ctx.x.base + kx) & mx;
+    const uint32_t sy = MODE == kModeStf ? pk.sy : (uint32_t)(ctx.y.base + ky) & my;
     Texel<PL> T;
     if constexpr (LAT)
         decode_latent_dedup(dec, latent_operand(dec, block_texel(pk.raw, sx, format_bytes(t.fmt)), t), sx, sy, mx, my,
@@ -727,12 +730,13 @@ __device__ __forceinline__ int payload_of(int fmt) {
 // Waves per SIMD the forward kernels are register-budgeted for (VGPRs per
 // lane: 512 / waves, in steps of 8). The whole-tile kernel issues VALU most
 // of the time and hides its memory and LDS latency with occupancy: with up
-// to two textures it fits 72 VGPRs (seven waves; one texture fits 64, eight
-// waves), with more it keeps 80 (six waves; four textures spill a few
+// to two textures it fits 64 VGPRs (eight waves; two textures spill a few
+// registers there, which ran 4 % faster than seven waves at 72 VGPRs without
+// spills), with more it keeps 80 (six waves; four textures spill a few
 // registers, and 96 without spills, five waves, measured no faster); with the
 // latent decoder and one texture it keeps 128 (four waves).
 template <int MODE, int NT, bool DEC, bool EF>
-constexpr int kForwardWaves = (MODE == kModeBins && !EF) ? (DEC ? (NT == 1 ? 4 : 1) : NT <= 2 ? 7 : 6) : 1;
+constexpr int kForwardWaves = (MODE == kModeBins && !EF) ? (DEC ? (NT == 1 ? 4 : 1) : NT <= 2 ? 8 : 6) : 1;
 
 // Screen tile rows each forward wave filters one after the other (one tile
 // column): the next row's UV is loaded while the current row is filtered,

@@ -107,7 +107,7 @@ def test_every_forward_instantiation_is_present(kernels):
 @pytest.mark.parametrize("filt", [0, 1], ids=["bilinear", "bicubic"])
 def test_whole_tile_kernels_keep_their_register_budget(kernels, filt):
     fwd = _forward(kernels)
-    for nt, budget in ((1, 72), (2, 72), (3, 80), (4, 80)):
+    for nt, budget in ((1, 64), (2, 64), (3, 80), (4, 80)):
         k = fwd[(filt, "bins", nt, False, False)]
         assert k[".vgpr_count"] + k[".agpr_count"] <= budget, (nt, k[".vgpr_count"])
     k = fwd[(filt, "bins", 1, True, False)]             # latent decoder, one texture: four waves
@@ -120,8 +120,9 @@ def test_forward_kernels_keep_per_lane_data_in_registers(kernels, filt):
     for mode in MODES.values():
         for nt in (1, 2, 3, 4):
             k = fwd[(filt, mode, nt, False, False)]
-            # four textures in the whole-tile kernel spill a few registers at 80 VGPRs
-            limit = 64 if (mode == "bins" and nt == 4) else 0
+            # the whole-tile kernel spills a few registers with two textures at
+            # 64 VGPRs and with four at 80
+            limit = {2: 32, 4: 64}.get(nt, 0) if mode == "bins" else 0
             assert k[".private_segment_fixed_size"] <= limit, (mode, nt, k[".private_segment_fixed_size"])
             assert not k[".uses_dynamic_stack"], (mode, nt)
     # the one-texture latent whole-tile kernel spills a few registers at its 128-VGPR budget
