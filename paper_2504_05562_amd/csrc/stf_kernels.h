@@ -732,11 +732,12 @@ __device__ __forceinline__ int payload_of(int fmt) {
 // of the time and hides its memory and LDS latency with occupancy: with up
 // to two textures it fits 64 VGPRs (eight waves; two textures spill a few
 // registers there, which ran 4 % faster than seven waves at 72 VGPRs without
-// spills), with more it keeps 80 (six waves; four textures spill a few
-// registers, and 96 without spills, five waves, measured no faster); with the
-// latent decoder and one texture it keeps 128 (four waves).
+// spills), three textures fit 72 (seven waves), four keep 80 (six waves;
+// they spill a few registers, and at 72 more of them, which ran 15 % slower;
+// 96 without spills, five waves, measured no faster); with the latent
+// decoder and one texture it keeps 128 (four waves).
 template <int MODE, int NT, bool DEC, bool EF>
-constexpr int kForwardWaves = (MODE == kModeBins && !EF) ? (DEC ? (NT == 1 ? 4 : 1) : NT <= 2 ? 8 : 6) : 1;
+constexpr int kForwardWaves = (MODE == kModeBins && !EF) ? (DEC ? (NT == 1 ? 4 : 1) : NT <= 2 ? 8 : NT == 3 ? 7 : 6) : 1;
 
 // Screen tile rows each forward wave filters one after the other (one tile
 // column): the next row's UV is loaded while the current row is filtered,

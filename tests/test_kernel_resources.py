@@ -107,7 +107,7 @@ def test_every_forward_instantiation_is_present(kernels):
 @pytest.mark.parametrize("filt", [0, 1], ids=["bilinear", "bicubic"])
 def test_whole_tile_kernels_keep_their_register_budget(kernels, filt):
     fwd = _forward(kernels)
-    for nt, budget in ((1, 64), (2, 64), (3, 80), (4, 80)):
+    for nt, budget in ((1, 64), (2, 64), (3, 72), (4, 80)):
         k = fwd[(filt, "bins", nt, False, False)]
         assert k[".vgpr_count"] + k[".agpr_count"] <= budget, (nt, k[".vgpr_count"])
     k = fwd[(filt, "bins", 1, True, False)]             # latent decoder, one texture: four waves
