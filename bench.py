@@ -153,7 +153,11 @@ def cpu_baseline(texs, uv, n_tiles=None, seed=0):
     dt = time.perf_counter() - t0
     px = n_tiles * 64
     return {"value": px / dt / 1e6, "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+            "host_cores_available": len(os.sched_getaffinity(0)),
             "sample": f"{n_tiles} of the frame's 8x8 tiles ({px} px), both textures, {dt:.1f} s"}
+
+
+MIN_LAUNCHES_PER_BATCH = 20
 
 
 def launch_time(torch, fn, steps, warmup, batches=1):
@@ -161,12 +165,14 @@ def launch_time(torch, fn, steps, warmup, batches=1):
     `steps` calls, after `warmup` untimed calls). With batches > 1 the calls
     are timed in that many equal batches and the median batch average is
     returned, so that one stall of the machine does not set a secondary
-    figure (the headline timing uses one batch over its whole timed region)."""
+    figure (the headline timing uses one batch over its whole timed region).
+    Every batch holds at least MIN_LAUNCHES_PER_BATCH calls whatever `steps`
+    is, so the secondary figures do not depend on the driver's step count."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    per = max(1, steps // batches)
+    per = max(MIN_LAUNCHES_PER_BATCH, steps // batches)
     avgs = []
     gc.disable()
     for _ in range(batches):

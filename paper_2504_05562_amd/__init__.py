@@ -236,6 +236,10 @@ def _texture_descs(textures: Sequence, need_data: bool = True, scales=None, deco
         if fmt in LATENT_FORMATS:
             if decoder is None:
                 raise ValueError(f"texture {i} holds latents: pass decoder= (from pack_decoder)")
+            if (decoder.dtype != __import__("torch").uint8 or decoder.numel() != DECODER_BYTES
+                    or not decoder.is_cuda or not decoder.is_contiguous()):
+                raise ValueError(f"decoder must be the contiguous uint8 GPU tensor of {DECODER_BYTES} bytes "
+                                 "from pack_decoder")
             arr[i].decoder = decoder.data_ptr()
         else:
             arr[i].decoder = None
@@ -256,11 +260,30 @@ def _params(filter, seed, frame, share_selection=False, float_bin_sums=False):
                   (SHARE_SELECTION if share_selection else 0) | (FLOAT_BIN_SUMS if float_bin_sums else 0), 0)
 
 
+def _check_buffers(name, bufs, shapes, device):
+    """The kernels write (or atomically add) whole [rows, cols, C] FP32 arrays
+    through these pointers: one contiguous float32 tensor of exactly that
+    shape per texture, on the launch device, or the call is refused here."""
+    import torch
+    if len(bufs) != len(shapes):
+        raise ValueError(f"{name}: {len(shapes)} tensors expected, got {len(bufs)}")
+    for i, (b, sh) in enumerate(zip(bufs, shapes)):
+        if not isinstance(b, torch.Tensor) or b.dtype != torch.float32 or not b.is_cuda or not b.is_contiguous():
+            raise ValueError(f"{name}[{i}] must be a contiguous float32 GPU tensor")
+        if tuple(b.shape) != tuple(sh):
+            raise ValueError(f"{name}[{i}] has shape {tuple(b.shape)}, {tuple(sh)} expected")
+        if b.device != device:
+            raise ValueError(f"{name}[{i}] is on {b.device}, the screen on {device}")
+
+
 def _outputs(uv, chans, out=None):
     import torch
     H, W = int(uv.shape[0]), int(uv.shape[1])
     if out is None:
         out = [torch.empty((H, W, c), dtype=torch.float32, device=uv.device) for c in chans]
+    else:
+        out = list(out)
+        _check_buffers("out", out, [(H, W, c) for c in chans], uv.device)
     ptrs = (ctypes.c_void_p * len(out))(*[o.data_ptr() for o in out])
     return out, ptrs
 
@@ -271,7 +294,8 @@ def _reuse(footprint, lut, exact_filtering=False, estimator="wis", clamp=False):
     est = ESTIMATORS[estimator] if isinstance(estimator, str) else int(estimator)
     if lut is None:
         return Reuse(fp, 0, None, flags, est)
-    if lut.dtype != __import__("torch").uint8 or lut.dim() != 2 or lut.shape[0] != 64 or not lut.is_contiguous():
+    if (lut.dtype != __import__("torch").uint8 or lut.dim() != 2 or lut.shape[0] != 64 or not lut.is_contiguous()
+            or not lut.is_cuda):
         raise ValueError("lut must be a contiguous uint8 GPU tensor [64, K]")
     return Reuse(fp, int(lut.shape[1]), lut.data_ptr(), flags, est)
 
@@ -336,12 +360,15 @@ def backward(textures, uv, grads, footprint="tile8x8", filter="bicubic", seed=0,
     scr = _screen(uv)
     prm = _params(filter, seed, frame, share_selection, float_bin_sums)
     r = _reuse(footprint, lut)
+    tex_shapes = [(int(t.shape[0]), int(t.shape[1]), c) for t, c in zip(textures, chans)]
     if dtex is None:
-        dtex = [torch.zeros((int(t.shape[0]), int(t.shape[1]), c), dtype=torch.float32, device=uv.device)
-                for t, c in zip(textures, chans)]
-    for g in grads:
-        if g.dtype != torch.float32 or not g.is_contiguous():
-            raise ValueError("grads must be contiguous float32")
+        dtex = [torch.zeros(sh, dtype=torch.float32, device=uv.device) for sh in tex_shapes]
+    else:
+        dtex = list(dtex)
+        _check_buffers("dtex", dtex, tex_shapes, uv.device)
+    grads = list(grads)
+    H, W = int(uv.shape[0]), int(uv.shape[1])
+    _check_buffers("grads", grads, [(H, W, c) for c in chans], uv.device)
     gp = (ctypes.c_void_p * len(grads))(*[g.data_ptr() for g in grads])
     dp = (ctypes.c_void_p * len(dtex))(*[d.data_ptr() for d in dtex])
     _check(lib.stf_backward(descs, len(textures), ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(r), gp, dp,

@@ -118,7 +118,7 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
-void clear_error() { stf_host::clear_error(); }
+void clear_error() { g_last_error.clear(); }
 
 const char* last_error() { return g_last_error.c_str(); }
 

@@ -2,10 +2,19 @@
 pairwise MIS, regression; each also clamped) on the GPU against the FP64
 oracle, through the C ABI. Selection is bit-exact. These estimators are not
 convex combinations, so the FP32 tolerance is 1e-5 relative to the sum of
-the absolute terms each estimate adds up (the oracle's "magnitude"); the
-regression estimate is compared where its coefficient beta is well
-conditioned (sum (w - wbar)^2 >= 1e-3 sum w^2); below that the FP32
-difference w_i - wbar is dominated by rounding of w_i itself."""
+the absolute terms each estimate adds up (the oracle's "magnitude").
+
+Every pixel is compared, the regression estimate too, whose coefficient
+beta = sum d_i w_i T_i / D (d_i = w_i - wbar, D = sum d_i^2) amplifies
+rounding: each d_i carries an absolute error of a few units of rounding u
+times |w_i| + |wbar| (FP32 w_i and wbar), so by Cauchy-Schwarz the relative
+errors of D and of the numerator are at most c u sum (|w_i| + |wbar|) |d_i| / D
+<= 2 c u sqrt(sum w_i^2 / D) = 2 c u / sqrt(spread), spread = D / sum w_i^2.
+beta enters the estimate as beta cv / n, a term of the magnitude, so the
+tolerance of the regression estimate is the magnitude's divided by
+sqrt(spread) (1e-5 is far above 2 c u for the handful of roundings here);
+where spread is so small that this exceeds the magnitude itself, FP32 may
+legitimately find D = 0 and beta = 0, and the bound still covers it."""
 import numpy as np
 import pytest
 
@@ -59,14 +68,14 @@ def test_estimator_parity(est, clamp, filt, fp):
     got = out[0].cpu().numpy().astype(np.float64)
     want = image(rv, uv)
     mag = image(diag[0]["magnitude"], uv)
-    ok = np.ones(want.shape, bool)
+    cond = np.ones(want.shape)
     if est == "regression":
         spread = image(diag[0]["spread"][..., None], uv)
-        ok = np.broadcast_to(spread >= 1e-3, want.shape)
-        assert ok.mean() > 0.5
-    tol = REL * np.maximum(mag, np.abs(want)) + 1e-30
-    bad = ok & (np.abs(got - want) > tol)
-    assert not bad.any(), f"{bad.sum()} beyond tolerance, worst {np.max(np.abs(got - want)[ok] / tol[ok]):.3g}x"
+        cond = np.broadcast_to(1.0 / np.sqrt(np.clip(spread, 1e-300, 1.0)), want.shape)
+    tol = REL * np.maximum(mag, np.abs(want)) * cond + 1e-30
+    err = np.abs(got - want)
+    bad = err > tol
+    assert not bad.any(), f"{bad.sum()} beyond tolerance, worst {np.max(err / tol):.3g}x"
 
 
 def test_estimators_rank_like_the_paper_on_the_magnified_plane():
