@@ -17,7 +17,8 @@ Stochastic Texture Filtering Through Sample Reuse", 2025):
   * the multi-PDF weighted importance sampling estimator, Eq. (14)
     (Sec. 4.2; loop structure of Sec. 4.5),
   * the deterministic filtered value, Eq. (3),
-  * the adjoint of Eq. (14) with respect to the texels.
+  * the adjoint of Eq. (14) with respect to the texels, and through the
+    latent decoder MLP to the latents and the decoder's weights and biases.
 
 footprint_oracle holds the sparse sharing-footprint generator (Sec. 4.3,
 Sec. S5); its header lists the readings it takes.

@@ -32,7 +32,7 @@ __all__ = [
     "stf_filter", "stf_filter_reuse", "reference_filter", "stf_adjoint",
     "tiles_to_image", "all_tiles", "psnr",
     "fp8e4m3_value", "bf16_value", "dequantize", "mlp_decode", "decode_latent_texture",
-    "texture_values", "selection_slots",
+    "texture_values", "selection_slots", "mlp_backward", "stf_adjoint_decoder",
 ]
 
 BILINEAR = "bilinear"
@@ -579,6 +579,70 @@ def stf_adjoint(textures, uv, filt, seed, frame, footprint, grads, lut=None, til
                       contrib.reshape(-1, C))
         res.append(grad)
     return res
+
+
+# --------------------------------------------------------------------------
+# adjoint through the latent decoder (the neural-texture setting)
+# --------------------------------------------------------------------------
+
+def mlp_backward(latent: np.ndarray, layers, g: np.ndarray):
+    """Reverse-mode derivative of mlp_decode at n latents [n, in] for output
+    gradients g [n, out], in FP64. Returns dL/dlatent [n, in] and, per layer,
+    (dL/dW_l [out, in], dL/db_l [out]) summed over the n latents. The ReLU
+    passes the gradient where its input is > 0 and blocks it elsewhere."""
+    ws = [np.asarray(w, dtype=np.float64) for w, _ in layers]
+    bs = [np.asarray(b, dtype=np.float64) for _, b in layers]
+    acts = [np.asarray(latent, dtype=np.float64)]   # the input of each layer
+    pre = []
+    for li, (w, b) in enumerate(zip(ws, bs)):
+        z = acts[-1] @ w.T + b
+        pre.append(z)
+        acts.append(np.maximum(z, 0.0) if li < len(ws) - 1 else z)
+    d = np.asarray(g, dtype=np.float64)
+    grads = [None] * len(ws)
+    for li in reversed(range(len(ws))):
+        if li < len(ws) - 1:
+            d = d * (pre[li] > 0.0)
+        grads[li] = (d.T @ acts[li], d.sum(axis=0))
+        d = d @ ws[li]
+    return d, grads
+
+
+def stf_adjoint_decoder(textures, uv, filt, seed, frame, footprint, grads, lut=None, tiles=None,
+                        share_selection=False):
+    """Gradients of L through Eq. (14) and the latent decoder, given dL/dout
+    per pixel, for latent textures (stored, kind, scale, layers) that share
+    one decoder.
+
+    The weights of Eq. (14) do not depend on the texel values, so the
+    gradient with respect to each decoded texel is the texel adjoint
+    (stf_adjoint); each texel's decode is independent, so the chain rule then
+    runs through the decoder once per texel: dL/dlatent_x = J_x^T g_x, and
+    the decoder's weight gradients sum over the texels. Returns (per slot
+    dL/dstored latent [H_t, W_t, 8], the gradient with respect to the stored
+    value before its per-channel scale; per layer (dL/dW_l, dL/db_l) summed
+    over the slots)."""
+    layers = textures[0][3]
+    for t in textures:
+        if not (isinstance(t, tuple) and len(t) == 4):
+            raise ValueError("latent textures (stored, kind, scale, layers) expected")
+        if t[3] is not layers:
+            raise ValueError("every latent texture of a call shares one decoder")
+    g_tex = stf_adjoint(textures, uv, filt, seed, frame, footprint, grads, lut=lut, tiles=tiles,
+                        share_selection=share_selection)
+    dlat = []
+    total = [(np.zeros(np.shape(w)), np.zeros(np.shape(b))) for w, b in layers]
+    for (stored, kind, scale, _), g in zip(textures, g_tex):
+        lat = dequantize(stored, kind, scale)                  # [H_t, W_t, 8]
+        hit = np.any(g != 0.0, axis=-1)
+        d = np.zeros(lat.shape)
+        if np.any(hit):
+            dl, lg = mlp_backward(lat[hit], layers, g[hit])
+            sc = np.ones(lat.shape[-1]) if scale is None else np.asarray(scale, dtype=np.float64)
+            d[hit] = dl * sc                                   # latent = stored * scale
+            total = [(tw + gw, tb + gb) for (tw, tb), (gw, gb) in zip(total, lg)]
+        dlat.append(d)
+    return dlat, total
 
 
 # --------------------------------------------------------------------------
