@@ -282,7 +282,7 @@ def material_form(torch, stf, w, steps, warmup):
     2048^2, roughness R8 1024^2, mask R8 512^2), bicubic, perspective plane
     at 2x-32x. Launch times at 3840x2160 of one-tap STF, whole-tile reuse
     (independent and shared selection) and the deterministic filter (the
-    full-filter cost); then 16 frames at 1920x1080 with Halton sub-pixel
+    full-filter cost); then 16 frames at 3840x2160 with Halton sub-pixel
     jitter and frame-indexed seeds: PSNR of one-tap STF and of reuse against
     the deterministic filter, per frame (mean squared error over the frames)
     and for the 16-frame average against the average of the references."""
@@ -310,7 +310,7 @@ def material_form(torch, stf, w, steps, warmup):
     acc = {k: [None] * 4 for k in ("stf", "reuse", "ref")}
     frames = 16
     for f in range(frames):
-        uvf = torch.from_numpy(w.perspective_plane(1920, 1080, 2048, 2.0, 32.0, jitter=w.frame_jitter(f))[0]).cuda()
+        uvf = torch.from_numpy(w.perspective_plane(3840, 2160, 2048, 2.0, 32.0, jitter=w.frame_jitter(f))[0]).cuda()
         got = {"ref": stf.filter_reference(texs, uvf, "bicubic"),
                "reuse": stf.filter_reuse(texs, uvf, "tile8x8", "bicubic", 1000 + f, f),
                "stf": stf.filter(texs, uvf, "bicubic", 1000 + f, f)}
@@ -325,32 +325,27 @@ def material_form(torch, stf, w, steps, warmup):
 
     avg = {k: psnr([float(((acc[k][t] - acc["ref"][t]) ** 2).mean()) / frames ** 2 for t in range(4)])
            for k in ("stf", "reuse")}
-    res["frames_1080p"] = {"frames": frames, "psnr_per_frame_db": {"stf": psnr(mse["stf"]), "reuse": psnr(mse["reuse"])},
+    res["frames_4k"] = {"frames": frames, "screen": [3840, 2160], "psnr_per_frame_db": {"stf": psnr(mse["stf"]), "reuse": psnr(mse["reuse"])},
                            "psnr_16_frame_average_db": avg, "peak": 1.0,
                            "order": ["albedo", "normal", "roughness", "mask"]}
     return res
 
 
-def fitting_form(torch, stf, w, steps=100):
+def fitting_views(torch, w):
+    """The eight seeded 1920x1080 perspective views of the plane (2x-16x on a
+    1024^2 texture, seeded UV offsets and sub-pixel jitter) both fitting rows
+    optimise over."""
+    return [torch.from_numpy(uv).cuda() for uv in w.view_set(8, 1920, 1080, 1024, seed=5)]
+
+
+def fitting_form(torch, stf, w, views, steps=60):
     """Texture optimisation through the adjoint: a 1024^2 RGBA FP32 texture,
     initialised to 0.5, fitted with Adam (lr 0.05) to the deterministic
-    bicubic filter of a procedural target over 8 views of 1024x512 pixels at
-    2x magnification that tile the texture (2 x 4 regions of 512x256 texels,
-    seeded sub-texel offsets). Every step filters each view with whole-tile
-    reuse under a fresh seed and back-propagates through stf_backward. The
-    result is scored as the PSNR of the fitted texture's deterministic filter
-    against the target's, over the 8 views."""
-    rng = np.random.Generator(np.random.PCG64(17))
+    bicubic filter of a procedural target over the 8 perspective views. Every
+    step filters each view with whole-tile reuse under a fresh seed and
+    back-propagates through stf_backward. Scored as the PSNR of the fitted
+    texture's deterministic filter against the target's, over the views."""
     target = torch.from_numpy(w.plane_albedo(3, 1024, np.float32)).cuda()
-    px = (np.arange(1024, dtype=np.float64) + 0.5) / 2.0
-    py = (np.arange(512, dtype=np.float64) + 0.5) / 2.0
-    views = []
-    for k in range(8):
-        off = rng.random(2)
-        uv = np.empty((512, 1024, 2), np.float64)
-        uv[..., 0] = (512.0 * (k % 2) + off[0] + px[None, :]) / 1024.0
-        uv[..., 1] = (256.0 * (k // 2) + off[1] + py[:, None]) / 1024.0
-        views.append(torch.from_numpy(uv.astype(np.float32)).cuda())
     refs = [stf.filter_reference([target], uv, "bicubic")[0] for uv in views]
     tex = torch.full((1024, 1024, 4), 0.5, device="cuda", requires_grad=True)
     opt = torch.optim.Adam([tex], lr=0.05)
@@ -376,10 +371,112 @@ def fitting_form(torch, stf, w, steps=100):
         losses.append(float(loss.detach()))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"texture": "1024^2 RGBA FP32", "views": "8 x 1024x512 px at 2x", "steps": steps,
+    return {"texture": "1024^2 RGBA FP32", "views": "8 seeded 1920x1080 perspective views (2x-16x)", "steps": steps,
             "loss_first": round(losses[0], 5), "loss_last": round(losses[-1], 6),
             "psnr_initial_db": psnr0, "psnr_fitted_db": psnr_views(),
             "ms_per_step": round(dt / steps * 1e3, 2), "optimizer": "Adam lr 0.05, fresh seed per step"}
+
+
+def latent_fitting_form(torch, stf, w, views, steps=60):
+    """Neural-texture optimisation through the decoder adjoint: a 1024^2 x 8
+    FP32 latent grid (stored FP16 for each forward pass) and the 8-64-64-4
+    decoder MLP (FP32 master weights, packed to BF16 for each forward pass),
+    fitted with Adam (lr 0.01) to the deterministic bicubic filter of the
+    same target over the same 8 views; every step decodes, filters (whole-tile
+    reuse, fresh seed) and back-propagates through stf_backward_decoder.
+    Also the launch time of one backward_decoder call on the first view."""
+    target = torch.from_numpy(w.plane_albedo(3, 1024, np.float32)).cuda()
+    refs = [stf.filter_reference([target], uv, "bicubic")[0] for uv in views]
+    rng = np.random.Generator(np.random.PCG64(21))
+    lat = torch.tensor(rng.standard_normal((1024, 1024, 8)).astype(np.float32) * 0.5, device="cuda",
+                       requires_grad=True)
+    params = [torch.tensor(a, device="cuda", requires_grad=True) for layer in w.mlp_weights(9) for a in layer]
+    opt = torch.optim.Adam([lat] + params, lr=0.01)
+
+    def layers():
+        return [(params[0], params[1]), (params[2], params[3]), (params[4], params[5])]
+
+    def psnr_views():
+        with torch.no_grad():
+            ly = [(a.detach(), b.detach()) for a, b in layers()]
+            dec = stf.pack_decoder(ly)
+            stored = lat.detach().to(torch.float16)
+            mse = 0.0
+            for uv, ref in zip(views, refs):
+                f = stf.filter_reference([stored], uv, "bicubic", decoder=dec)[0]
+                mse += float(((f - ref) ** 2).mean()) / len(views)
+        return round(10.0 * float(np.log10(1.0 / mse)), 2)
+
+    psnr0 = psnr_views()
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(steps):
+        opt.zero_grad()
+        loss = 0.0
+        for k, (uv, ref) in enumerate(zip(views, refs)):
+            out = stf.stf_decoder_autograd(lat, layers(), uv, "tile8x8", "bicubic", seed=it, frame=k)
+            loss = loss + ((out - ref) ** 2).mean()
+        loss.backward()
+        opt.step()
+        losses.append(float(loss.detach()))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # one adjoint call through the decoder, timed on its own
+    ly = [(a.detach(), b.detach()) for a, b in layers()]
+    dec = stf.pack_decoder(ly)
+    stored = [lat.detach().to(torch.float16)]
+    g = [torch.randn((1080, 1920, 4), device="cuda")]
+    dl = [torch.zeros((1024, 1024, 8), device="cuda")]
+    dly = [(torch.zeros_like(a), torch.zeros_like(b)) for a, b in ly]
+    t_b = launch_time(torch, lambda: stf.backward_decoder(stored, views[0], g, ly, dec, "tile8x8", "bicubic", 0, 0,
+                                                          dlatent=dl, dlayers=dly), 20, 3, batches=3)
+    return {"latents": "1024^2 x 8 FP32 (FP16 storage)", "decoder": "8-64-64-4 FP32 master, BF16 on MFMA",
+            "views": "8 seeded 1920x1080 perspective views (2x-16x)", "steps": steps,
+            "loss_first": round(losses[0], 5), "loss_last": round(losses[-1], 6),
+            "psnr_initial_db": psnr0, "psnr_fitted_db": psnr_views(),
+            "ms_per_step": round(dt / steps * 1e3, 2), "optimizer": "Adam lr 0.01, fresh seed per step",
+            "backward_decoder_us": round(t_b * 1e6, 1)}
+
+
+SWEEP_FOOTPRINTS = ["self", "quad2x2", "wave2x2", "square3x3", "square4x4", "tile8x8", "lut_ps9"]
+
+
+def footprint_sweep(torch, stf, texs, uv, ref, alg_bytes, steps, warmup):
+    """The benchmark frame (both textures, bicubic) with every sharing
+    footprint (Sec. 4.3; the synthetic counterpart of Table 1): launch time,
+    fraction of the HBM peak for the frame's algorithmic bytes, PSNR of the
+    albedo RGB against the deterministic filter at seed 0 and averaged over
+    seeds 0-15, and the footprints no other one beats on both time and mean
+    PSNR (the Pareto set). 'lut_ps9' is a generated pseudorandom sparse
+    footprint with 9 members (Sec. S5 settings)."""
+    H, W = uv.shape[:2]
+    outs = [torch.empty((H, W, int(t.shape[2])), dtype=torch.float32, device=uv.device) for t in texs]
+    lut = stf.generate_footprints(9, 32, 1.4, 10000, 30, 0)[0]
+    rows = {}
+    for fp in SWEEP_FOOTPRINTS:
+        name, kw = ("lut", {"lut": lut}) if fp == "lut_ps9" else (fp, {})
+        if fp == "self":
+            fn = lambda: stf.filter(texs, uv, "bicubic", 0, 0, out=outs)
+        else:
+            fn = lambda name=name, kw=kw: stf.filter_reuse(texs, uv, name, "bicubic", 0, 0, out=outs, **kw)
+        t = launch_time(torch, fn, steps, warmup, batches=5)
+        ps = []
+        for seed in range(16):
+            if fp == "self":
+                o = stf.filter(texs[:1], uv, "bicubic", seed, 0)[0]
+            else:
+                o = stf.filter_reuse(texs[:1], uv, name, "bicubic", seed, 0, **kw)[0]
+            ps.append(psnr_rgb(torch, o, ref))
+        rows[fp] = {"avg_launch_us": round(t * 1e6, 2), "Mpixel_s": round(H * W / t / 1e6, 1),
+                    "hbm_frac": round(alg_bytes / t / 1e9 / HBM_PEAK_GBS, 4),
+                    "psnr_seed0_db": round(ps[0], 2), "psnr_mean16_db": round(float(np.mean(ps)), 2)}
+    pareto = [a for a in rows if not any(
+        rows[b]["avg_launch_us"] <= rows[a]["avg_launch_us"] and rows[b]["psnr_mean16_db"] >= rows[a]["psnr_mean16_db"]
+        and (rows[b]["avg_launch_us"], rows[b]["psnr_mean16_db"]) != (rows[a]["avg_launch_us"], rows[a]["psnr_mean16_db"])
+        for b in rows)]
+    return {"rows": rows, "pareto": pareto, "against": "deterministic bicubic filter, albedo RGB",
+            "note": "'self' is one-tap STF (stf_filter)"}
 
 
 def footprint_generator_form(torch, stf):
@@ -625,9 +722,13 @@ def main():
         res["backward"] = backward_form(torch, stf, texs, uv0, args.steps // 4, args.warmup // 2)
         res["latent_decoder"] = latent_form(torch, stf, w, args.steps // 2, args.warmup)
         res["shared_selection"] = shared_selection_form(torch, stf, texs, uv0, ref, args.steps // 2, args.warmup)
+        res["footprint_sweep"] = footprint_sweep(torch, stf, texs, uv0, ref, alg_bytes, args.steps // 2, args.warmup)
         res["estimators"] = estimator_sweep(torch, stf, w)
         res["footprint_generator"] = footprint_generator_form(torch, stf)
-        res["texture_fitting"] = fitting_form(torch, stf, w)
+        views = fitting_views(torch, w)
+        res["texture_fitting"] = fitting_form(torch, stf, w, views)
+        res["latent_fitting"] = latent_fitting_form(torch, stf, w, views)
+        del views
         res["materials_4k"] = material_form(torch, stf, w, args.steps // 4, args.warmup // 2)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(texs_np, uv_np)

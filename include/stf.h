@@ -284,6 +284,51 @@ typedef struct stf_mlp {
  */
 int stf_decoder_pack(const stf_mlp* mlp, void* packed, void* hip_stream);
 
+/* Gradients of the decoder's weights and biases (device FP32 arrays of the
+ * shapes in stf_mlp, accumulated). */
+typedef struct stf_mlp_grad {
+    float* w1;              /* [64][8] */
+    float* b1;              /* [64] */
+    float* w2;              /* [64][64] */
+    float* b2;              /* [64] */
+    float* w3;              /* [4][64] */
+    float* b3;              /* [4] */
+} stf_mlp_grad;
+
+/* Device workspace stf_backward_decoder needs for these textures (latent
+ * formats, power-of-two sizes), or -1 if they are invalid. */
+int64_t stf_backward_decoder_workspace_bytes(const stf_texture* tex, int32_t ntex);
+
+/*
+ * Adjoint of stf_filter_reuse over latent textures with respect to the
+ * latents and the decoder MLP (the neural-texture setting of Sec. 1 and
+ * Sec. 5.6, differentiated through Eq. (14)). The weights of Eq. (14) do not
+ * depend on texel values, so with g_x the texel adjoint of stf_backward (the
+ * gradient with respect to the decoded RGBA of texel x),
+ *     dL/dlatent_x += J_x^T g_x,   dL/dW_l, dL/db_l += sums over the texels,
+ * where J_x is the Jacobian of the decoder at latent x (ReLU derivative 1
+ * where its input is > 0, else 0).
+ *   tex       latent textures (data read: the activations are recomputed),
+ *             all with the same packed decoder as in the forward call
+ *   p, r      as the forward call being differentiated (plain Eq. (14):
+ *             no exact filtering, clamping or comparison estimator)
+ *   dout      host array of ntex device pointers, FP32 [H][W][4]
+ *   mlp       the FP32 weights the decoder was packed from: the adjoint is
+ *             that of the FP32 decoder, the forward pass's BF16/FP8 rounding
+ *             of weights and activations taken as the identity
+ *   dlatent   host array of ntex device pointers, FP32 [tex height][tex width][8]
+ *             dense, ACCUMULATED (+=): the gradient with respect to the
+ *             stored latent value before its per-channel scale
+ *   dmlp      device gradient arrays, ACCUMULATED (+=)
+ *   workspace device, >= stf_backward_decoder_workspace_bytes(tex, ntex),
+ *             256-byte aligned, owned by the caller, no initialisation needed
+ * FP32 arithmetic on the matrix cores; the texel adjoint sums with FP32
+ * atomics (order not fixed), everything after it in a fixed order.
+ */
+int stf_backward_decoder(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
+                         const stf_reuse* r, const float* const* dout, const stf_mlp* mlp, float* const* dlatent,
+                         const stf_mlp_grad* dmlp, void* workspace, int64_t workspace_bytes, void* hip_stream);
+
 /*
  * Pseudorandom sparse sharing footprints (Sec. 4.3, "Pseudorandom Sparse
  * Footprints"; generator of Sec. S5). Writes a footprint LUT for

@@ -22,6 +22,7 @@ __all__ = [
     "BILINEAR", "BICUBIC", "FOOTPRINTS", "FORMATS", "library", "lib_path", "version",
     "filter", "filter_reuse", "filter_reference", "backward", "StfError", "pack_decoder",
     "generate_footprints", "footprint_set", "stf_reuse_autograd",
+    "backward_decoder", "stf_decoder_autograd",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -57,6 +58,10 @@ class Texture(ctypes.Structure):
 class Mlp(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("w1", "b1", "w2", "b2", "w3", "b3")] + \
                [("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class MlpGrad(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("w1", "b1", "w2", "b2", "w3", "b3")]
 
 
 DECODER_BYTES = 14736
@@ -96,6 +101,7 @@ ESTIMATORS = {"wis": 0, "is": 1, "mis": 2, "pmis": 3, "regression": 4}
 _lib = None
 _SYMBOLS = ("stf_filter", "stf_filter_reuse", "stf_filter_reference", "stf_backward",
             "stf_decoder_pack", "stf_footprint_workspace_bytes", "stf_footprint_generate",
+            "stf_backward_decoder", "stf_backward_decoder_workspace_bytes",
             "stf_last_error", "stf_version")
 
 
@@ -118,6 +124,11 @@ def library() -> ctypes.CDLL:
         lib.stf_footprint_workspace_bytes.restype = ctypes.c_int64
         lib.stf_footprint_generate.argtypes = [P(FootprintParams), vp, ctypes.c_int64, vp, vp, vp]
         lib.stf_footprint_generate.restype = ctypes.c_int
+        lib.stf_backward_decoder_workspace_bytes.argtypes = [P(Texture), ctypes.c_int32]
+        lib.stf_backward_decoder_workspace_bytes.restype = ctypes.c_int64
+        lib.stf_backward_decoder.argtypes = tex_args + [P(Reuse), P(vp), P(Mlp), P(vp), P(MlpGrad), vp,
+                                                        ctypes.c_int64, vp]
+        lib.stf_backward_decoder.restype = ctypes.c_int
         for name in ("stf_filter", "stf_filter_reuse", "stf_filter_reference", "stf_backward",
                      "stf_decoder_pack", "stf_version"):
             getattr(lib, name).restype = ctypes.c_int
@@ -143,21 +154,32 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+MLP_SHAPES = [((64, 8), (64,)), ((64, 64), (64,)), ((4, 64), (4,))]
+
+
+def _mlp_arrays(layers, what="decoder"):
+    """The six arrays of [(W1 [64,8], b1), (W2 [64,64], b2), (W3 [4,64], b3)],
+    checked to be contiguous float32 GPU tensors of those shapes."""
+    import torch
+    if len(layers) != 3:
+        raise ValueError(f"{what}: three (W, b) layers expected")
+    flat = []
+    for (wt, bt), (ws, bs) in zip(layers, MLP_SHAPES):
+        for t, sh in ((wt, ws), (bt, bs)):
+            if (not isinstance(t, torch.Tensor) or tuple(t.shape) != sh or t.dtype != torch.float32
+                    or not t.is_cuda or not t.is_contiguous()):
+                raise ValueError(f"{what} arrays must be contiguous float32 GPU tensors of shape {sh}")
+            flat.append(t)
+    return flat
+
+
 def pack_decoder(layers, stream=None, precision="bf16"):
     """Pack the latent decoder MLP [(W1 [64,8], b1), (W2 [64,64], b2),
     (W3 [4,64], b3)] (float32 GPU tensors) with stf_decoder_pack for BF16 or
     FP8 matrix-core arithmetic. Returns the packed uint8 GPU tensor to pass
     as `decoder=`."""
     import torch
-    shapes = [((64, 8), (64,)), ((64, 64), (64,)), ((4, 64), (4,))]
-    if len(layers) != 3:
-        raise ValueError("three (W, b) layers expected")
-    flat = []
-    for (wt, bt), (ws, bs) in zip(layers, shapes):
-        for t, sh in ((wt, ws), (bt, bs)):
-            if tuple(t.shape) != sh or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
-                raise ValueError(f"decoder arrays must be contiguous float32 GPU tensors of shape {sh}")
-            flat.append(t)
+    flat = _mlp_arrays(layers)
     packed = torch.empty(DECODER_BYTES, dtype=torch.uint8, device=flat[0].device)
     m = Mlp(*[t.data_ptr() for t in flat], DECODER_PRECISIONS[precision], 0)
     _check(library().stf_decoder_pack(ctypes.byref(m), ctypes.c_void_p(packed.data_ptr()), _stream_handle(stream)))
@@ -376,6 +398,50 @@ def backward(textures, uv, grads, footprint="tile8x8", filter="bicubic", seed=0,
     return dtex
 
 
+def backward_decoder(textures, uv, grads, layers, decoder, footprint="tile8x8", filter="bicubic", seed=0, frame=0,
+                     lut=None, scales=None, dlatent=None, dlayers=None, share_selection=False, precision="bf16",
+                     stream=None):
+    """Adjoint of filter_reuse over latent textures through the decoder
+    (stf_backward_decoder): accumulates dL/d(stored latent) into `dlatent`
+    (float32 [H_t, W_t, 8] per texture) and the FP32 decoder's weight and
+    bias gradients into `dlayers` (same structure as `layers`, the FP32
+    weights `decoder` was packed from); both zero-initialised if not given."""
+    import torch
+    lib = library()
+    descs, chans, _keep = _texture_descs(textures, scales=scales, decoder=decoder)
+    if any(d.format not in LATENT_FORMATS for d in descs):
+        raise ValueError("backward_decoder takes latent textures (8 channels)")
+    scr = _screen(uv)
+    prm = _params(filter, seed, frame, share_selection)
+    r = _reuse(footprint, lut)
+    flat = _mlp_arrays(layers)
+    if dlayers is None:
+        dlayers = [(torch.zeros_like(wt), torch.zeros_like(bt)) for wt, bt in layers]
+    gflat = _mlp_arrays(dlayers, "gradient")
+    shapes = [(int(t.shape[0]), int(t.shape[1]), 8) for t in textures]
+    if dlatent is None:
+        dlatent = [torch.zeros(sh, dtype=torch.float32, device=uv.device) for sh in shapes]
+    else:
+        dlatent = list(dlatent)
+        _check_buffers("dlatent", dlatent, shapes, uv.device)
+    grads = list(grads)
+    H, W = int(uv.shape[0]), int(uv.shape[1])
+    _check_buffers("grads", grads, [(H, W, 4)] * len(textures), uv.device)
+    nbytes = lib.stf_backward_decoder_workspace_bytes(descs, len(textures))
+    if nbytes < 0:
+        raise StfError(lib.stf_last_error().decode())
+    ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=uv.device)
+    off = (-ws.data_ptr()) % 256
+    m = Mlp(*[t.data_ptr() for t in flat], DECODER_PRECISIONS[precision], 0)
+    mg = MlpGrad(*[t.data_ptr() for t in gflat])
+    gp = (ctypes.c_void_p * len(grads))(*[g.data_ptr() for g in grads])
+    dp = (ctypes.c_void_p * len(dlatent))(*[d.data_ptr() for d in dlatent])
+    _check(lib.stf_backward_decoder(descs, len(textures), ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(r), gp,
+                                    ctypes.byref(m), dp, ctypes.byref(mg), ctypes.c_void_p(ws.data_ptr() + off),
+                                    ctypes.c_int64(nbytes), _stream_handle(stream)))
+    return dlatent, dlayers
+
+
 def _autograd_function():
     import torch
 
@@ -402,6 +468,51 @@ def _autograd_function():
 
 
 _STFReuse = None
+_STFDecoderReuse = None
+
+
+def _decoder_autograd_function():
+    import torch
+
+    class STFDecoderReuse(torch.autograd.Function):
+        """Differentiable reuse STF of a latent grid through the decoder MLP:
+        forward = FP16 storage of the latents, stf_decoder_pack (BF16) and
+        stf_filter_reuse; backward = stf_backward_decoder (FP32 decoder,
+        rounding to FP16 and BF16 passed straight through)."""
+
+        @staticmethod
+        def forward(ctx, latents, w1, b1, w2, b2, w3, b3, uv, footprint, filter, seed, frame):
+            layers = [(w1.detach(), b1.detach()), (w2.detach(), b2.detach()), (w3.detach(), b3.detach())]
+            stored = latents.detach().to(torch.float16).contiguous()
+            dec = pack_decoder(layers)
+            ctx.save_for_backward(stored, uv, dec, w1, b1, w2, b2, w3, b3)
+            ctx.cfg = (footprint, filter, seed, frame)
+            return filter_reuse([stored], uv.detach(), footprint, filter, seed, frame, decoder=dec)[0]
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            stored, uv, dec, w1, b1, w2, b2, w3, b3 = ctx.saved_tensors
+            footprint, filt, seed, frame = ctx.cfg
+            layers = [(w1.detach(), b1.detach()), (w2.detach(), b2.detach()), (w3.detach(), b3.detach())]
+            (dlat,), dl = backward_decoder([stored], uv, [grad_out.contiguous().float()], layers, dec, footprint, filt,
+                                           seed, frame)
+            return (dlat, dl[0][0], dl[0][1], dl[1][0], dl[1][1], dl[2][0], dl[2][1],
+                    None, None, None, None, None)
+
+    return STFDecoderReuse
+
+
+def stf_decoder_autograd(latents, layers, uv, footprint="tile8x8", filter="bicubic", seed=0, frame=0):
+    """torch.autograd entry for neural textures: reuse STF of an FP32 latent
+    grid [H_t, W_t, 8] (stored as FP16 for the forward pass) decoded by the
+    MLP `layers` [(W1, b1), (W2, b2), (W3, b3)] of FP32 tensors (packed to
+    BF16 for the forward pass); differentiable with respect to the latents
+    and every weight and bias."""
+    global _STFDecoderReuse
+    if _STFDecoderReuse is None:
+        _STFDecoderReuse = _decoder_autograd_function()
+    (w1, b1), (w2, b2), (w3, b3) = layers
+    return _STFDecoderReuse.apply(latents, w1, b1, w2, b2, w3, b3, uv, footprint, filter, seed, frame)
 
 
 def stf_reuse_autograd(texture, uv, footprint="tile8x8", filter="bicubic", seed=0, frame=0):

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 
+#include "stf_decoder_backward.h"
 #include "stf_kernels.h"
 #include "stf_status.h"
 
@@ -409,6 +410,154 @@ int stf_backward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, co
     }
 #undef STF_BW
     return finish_launch("backward");
+}
+
+}  // extern "C"
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace layout of stf_backward_decoder: per texture the dense FP32
+// gradient of its decoded texels [th * tw][4], then one slot of weight
+// gradients per decoder-backward wavefront of every texture.
+struct DecBwdLayout {
+    size_t g[STF_MAX_TEXTURES];
+    int waves[STF_MAX_TEXTURES];
+    int total_waves = 0;
+    size_t partial = 0, total = 0;
+};
+
+DecBwdLayout dec_bwd_layout(const stf_texture* tex, int32_t ntex) {
+    DecBwdLayout l;
+    size_t off = 0;
+    for (int i = 0; i < ntex; ++i) {
+        const int64_t n = (int64_t)tex[i].width * tex[i].height;
+        l.g[i] = off;
+        off += align256((size_t)n * 16);
+        const int64_t blocks = (n + 63) / 64;
+        l.waves[i] = (int)std::min<int64_t>(blocks, stf::kDecBwdMaxWaves);
+        l.total_waves += l.waves[i];
+    }
+    l.partial = off;
+    l.total = off + align256((size_t)l.total_waves * stf::kGradFloats * 4);
+    return l;
+}
+
+// The latent textures of a decoder adjoint call: latent formats, one decoder.
+int check_decoder_textures(const stf_texture* tex, int32_t ntex) {
+    if (tex == nullptr) return fail(STF_EINVAL, "null texture descriptors");
+    if (ntex < 1 || ntex > STF_MAX_TEXTURES) return fail(STF_EINVAL, "ntex=%d outside 1..%d", ntex, STF_MAX_TEXTURES);
+    for (int i = 0; i < ntex; ++i) {
+        if (!is_latent(tex[i].format))
+            return fail(STF_EINVAL, "texture %d: the decoder adjoint takes latent textures only", i);
+        if (!pow2(tex[i].width) || !pow2(tex[i].height) || tex[i].width < 4 || tex[i].height < 4 ||
+            tex[i].width > 32768 || tex[i].height > 32768)
+            return fail(STF_EINVAL, "texture %d: %dx%d must be powers of two in 4..32768", i, tex[i].width,
+                        tex[i].height);
+    }
+    return STF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t stf_backward_decoder_workspace_bytes(const stf_texture* tex, int32_t ntex) {
+    stf_host::clear_error();
+    if (check_decoder_textures(tex, ntex) != STF_OK) return -1;
+    return (int64_t)dec_bwd_layout(tex, ntex).total;
+}
+
+int stf_backward_decoder(const stf_texture* tex, int32_t ntex, const stf_screen* scr, const stf_params* p,
+                         const stf_reuse* r, const float* const* dout, const stf_mlp* mlp, float* const* dlatent,
+                         const stf_mlp_grad* dmlp, void* workspace, int64_t workspace_bytes, void* hip_stream) {
+    stf_host::clear_error();
+    int rc = check_decoder_textures(tex, ntex);
+    if (rc != STF_OK) return rc;
+    stf::Args a;
+    if ((rc = prepare(tex, ntex, scr, p, true, a, true)) != STF_OK) return rc;
+    if ((rc = check_reuse(r)) != STF_OK) return rc;
+    if (r->flags & (STF_REUSE_EXACT_FILTERING | STF_REUSE_CLAMP) || r->estimator != STF_EST_WIS)
+        return fail(STF_EUNSUPPORTED, "the adjoint covers the plain Eq. (14) estimator only");
+    if (mlp == nullptr || dmlp == nullptr) return fail(STF_EINVAL, "mlp or its gradient descriptor is null");
+    const float* ws[6] = {mlp->w1, mlp->b1, mlp->w2, mlp->b2, mlp->w3, mlp->b3};
+    float* const gs[6] = {dmlp->w1, dmlp->b1, dmlp->w2, dmlp->b2, dmlp->w3, dmlp->b3};
+    for (int i = 0; i < 6; ++i) {
+        if (ws[i] == nullptr || gs[i] == nullptr) return fail(STF_EINVAL, "mlp array %d or its gradient is null", i);
+        if ((reinterpret_cast<uintptr_t>(ws[i]) & 3) || (reinterpret_cast<uintptr_t>(gs[i]) & 3))
+            return fail(STF_EINVAL, "mlp array %d or its gradient not 4-byte aligned", i);
+    }
+    if (mlp->precision != STF_DECODER_BF16 && mlp->precision != STF_DECODER_FP8)
+        return fail(STF_EINVAL, "unknown decoder precision %d", mlp->precision);
+    if (mlp->reserved != 0) return fail(STF_EINVAL, "mlp reserved field must be 0");
+    if (dout == nullptr || dlatent == nullptr) return fail(STF_EINVAL, "dout/dlatent arrays are null");
+    for (int i = 0; i < ntex; ++i) {
+        if (dout[i] == nullptr || dlatent[i] == nullptr) return fail(STF_EINVAL, "dout[%d]/dlatent[%d] is null", i, i);
+        if ((reinterpret_cast<uintptr_t>(dout[i]) & 3) || (reinterpret_cast<uintptr_t>(dlatent[i]) & 3))
+            return fail(STF_EINVAL, "dout[%d]/dlatent[%d] not 4-byte aligned", i, i);
+    }
+    const DecBwdLayout l = dec_bwd_layout(tex, ntex);
+    if (workspace == nullptr) return fail(STF_EINVAL, "workspace is null");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0) return fail(STF_EINVAL, "workspace not aligned to 256 bytes");
+    if (workspace_bytes < (int64_t)l.total)
+        return fail(STF_EINVAL, "workspace of %lld bytes, %lld needed", (long long)workspace_bytes, (long long)l.total);
+    uint8_t* wsp = static_cast<uint8_t*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+
+    // 1. the texel adjoint of every slot into its dense FP32 buffer (cleared
+    //    first); the latent scale precedes the decoder, so none applies here
+    for (int i = 0; i < ntex; ++i) {
+        float* g = reinterpret_cast<float*>(wsp + l.g[i]);
+        const int64_t n = (int64_t)tex[i].width * tex[i].height * 4;
+        hipLaunchKernelGGL(stf::zero_fill_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256),
+                           0, s, g, n);
+        a.out[i] = g;
+        a.dout[i] = dout[i];
+        a.tex[i].has_scale = 0;
+        for (int c = 0; c < 8; ++c) a.tex[i].scale[c] = 1.0f;
+    }
+    a.footprint = r->footprint;
+    a.lut = r->lut;
+    a.lut_k = r->lut_k;
+    const bool cubic = p->filter == STF_BICUBIC_BSPLINE;
+    const dim3 grid = stf::grid_of(a), block(stf::kThreads);
+#define STF_BW(F, M) hipLaunchKernelGGL((stf::backward_kernel<F, M>), grid, block, 0, s, a)
+    switch (r->footprint) {
+    case STF_FP_SELF: if (cubic) STF_BW(1, stf::kModeStf); else STF_BW(0, stf::kModeStf); break;
+    case STF_FP_QUAD2X2: if (cubic) STF_BW(1, stf::kModeQuad); else STF_BW(0, stf::kModeQuad); break;
+    case STF_FP_TILE8X8: if (cubic) STF_BW(1, stf::kModeBins); else STF_BW(0, stf::kModeBins); break;
+    default: if (cubic) STF_BW(1, stf::kModeRecords); else STF_BW(0, stf::kModeRecords); break;
+    }
+#undef STF_BW
+    // 2. through the decoder, per texture; 3. the weight gradients summed
+    float* partial = reinterpret_cast<float*>(wsp + l.partial);
+    int slot0 = 0;
+    for (int i = 0; i < ntex; ++i) {
+        stf::DecBwdArgs d;
+        d.data = static_cast<const uint8_t*>(tex[i].data);
+        d.pitch = tex[i].pitch_bytes;
+        d.tw = tex[i].width;
+        d.th = tex[i].height;
+        d.fmt = tex[i].format;
+        d.nblocks = (int)(((int64_t)d.tw * d.th + 63) / 64);
+        for (int c = 0; c < 8; ++c) d.scale[c] = tex[i].scale != nullptr ? tex[i].scale[c] : 1.0f;
+        d.g = reinterpret_cast<const float*>(wsp + l.g[i]);
+        d.w1 = mlp->w1;
+        d.b1 = mlp->b1;
+        d.w2 = mlp->w2;
+        d.b2 = mlp->b2;
+        d.w3 = mlp->w3;
+        d.dlat = dlatent[i];
+        d.partial = partial + (size_t)slot0 * stf::kGradFloats;
+        hipLaunchKernelGGL(stf::decoder_backward_kernel, dim3((unsigned)l.waves[i]), dim3(64), 0, s, d);
+        slot0 += l.waves[i];
+    }
+    stf::MlpGradPtrs o;
+    for (int i = 0; i < 6; ++i) o.p[i] = gs[i];
+    hipLaunchKernelGGL(stf::decoder_grad_reduce_kernel, dim3((stf::kGradFloats + 255) / 256), dim3(256), 0, s,
+                       static_cast<const float*>(partial), l.total_waves, o);
+    return finish_launch("decoder backward");
 }
 
 const char* stf_last_error(void) { return stf_host::last_error(); }

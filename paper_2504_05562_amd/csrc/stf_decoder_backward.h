@@ -1,0 +1,253 @@
+// Adjoint of Eq. (14) through the latent decoder MLP (the neural-texture
+// setting of Sec. 1 and Sec. 5.6): gradients with respect to the latents and
+// to the decoder's weights and biases.
+//
+// The weights of Eq. (14) do not depend on texel values, so the gradient
+// with respect to each decoded texel, g_x = dL/dD(x), is the texel adjoint
+// (backward_kernel with four channels, into a dense FP32 buffer). Each
+// texel's decode is independent, so the chain rule then runs through the
+// decoder once per texel x with g_x != 0:
+//     z1 = W1 l + b1, h1 = ReLU(z1), z2 = W2 h1 + b2, h2 = ReLU(z2), y = W3 h2 + b3
+//     d2 = (W3^T g) * [z2 > 0],  d1 = (W2^T d2) * [z1 > 0],  dL/dl = W1^T d1
+//     dW3 = sum g h2^T,  dW2 = sum d2 h1^T,  dW1 = sum d1 l^T,  db = sums of g, d2, d1
+// in FP32 with the FP32 weights (the forward pass's BF16 or FP8 rounding of
+// weights and activations is passed straight through, as in mixed-precision
+// training). One wavefront takes 64 consecutive texels of the grid at a
+// time: their activations live in LDS with the texels as columns, and every
+// product above -- the per-texel layers as well as the weight gradients,
+// which contract over the texels -- runs on v_mfma_f32_16x16x4_f32. A wave's
+// weight gradients accumulate in registers over its blocks of texels and are
+// written once to a per-wave slot; a second kernel sums the slots in a fixed
+// order, so the result does not depend on scheduling.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "stf_device.h"
+
+namespace stf {
+
+constexpr int kDbLd = 65;                          // LDS row stride (floats) of the [unit][texel] arrays
+constexpr int kGradW1 = 0, kGradB1 = kGradW1 + 64 * 8, kGradW2 = kGradB1 + 64, kGradB2 = kGradW2 + 64 * 64,
+              kGradW3 = kGradB2 + 64, kGradB3 = kGradW3 + 4 * 64, kGradFloats = kGradB3 + 4;   // 4996
+constexpr int kDecBwdMaxWaves = 2048;
+
+struct DecBwdArgs {
+    const uint8_t* data;     // latent grid, row pitch `pitch`
+    int64_t pitch;
+    int32_t tw, th, fmt;
+    int32_t nblocks;         // ceil(tw * th / 64)
+    float scale[8];          // latent = stored * scale
+    const float* g;          // dL/d(decoded texel), [th * tw][4]
+    const float* w1;         // [64][8]
+    const float* b1;         // [64]
+    const float* w2;         // [64][64]
+    const float* b2;         // [64]
+    const float* w3;         // [4][64]
+    float* dlat;             // [th * tw][8], accumulated
+    float* partial;          // [gridDim.x][kGradFloats], written
+};
+
+// Latent channels of texel t (row-major index) times their scales.
+__device__ __forceinline__ void load_latent(const DecBwdArgs& a, int64_t t, float* x) {
+    const int64_t y = t / a.tw, xx = t % a.tw;
+    const uint8_t* p = a.data + y * a.pitch;
+    if (a.fmt == STF_LATENT8_FP8) {
+        const uint2 q = *reinterpret_cast<const uint2*>(p + xx * 8);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            x[c] = fp8_e4m3(q.x >> (8 * c));
+            x[4 + c] = fp8_e4m3(q.y >> (8 * c));
+        }
+    } else {
+        const uint4 q = *reinterpret_cast<const uint4*>(p + xx * 16);
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const uint32_t bits = (w[c >> 1] >> (16 * (c & 1))) & 0xFFFFu;
+            x[c] = a.fmt == STF_LATENT8_BF16 ? bf16_bits(bits) : h2f(bits);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) x[c] *= a.scale[c];
+}
+
+// acc[i * NT + j] += A(16 i .., k) B(k, 16 j ..) over k in [0, K), K a
+// multiple of 4: MT x NT tiles of 16 x 16 on v_mfma_f32_16x16x4_f32. Lane l
+// feeds A(16 i + l % 16, k0 + l / 16) and B(k0 + l / 16, 16 j + l % 16) and
+// holds rows 16 i + 4 (l / 16) + v, v < 4, of column 16 j + l % 16 of each
+// tile. The accessors return 0 outside the operands.
+template <int MT, int NT, typename FA, typename FB>
+__device__ __forceinline__ void mfma_tiles(v4f (&acc)[MT * NT], FA A, FB B, int K) {
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+#pragma unroll 2
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        float av[MT], bv[NT];
+#pragma unroll
+        for (int i = 0; i < MT; ++i) av[i] = A(16 * i + r, k0 + q);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) bv[j] = B(k0 + q, 16 * j + r);
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[i * NT + j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i * NT + j], 0, 0, 0);
+    }
+}
+
+template <int T>
+__device__ __forceinline__ void zero_tiles(v4f (&acc)[T]) {
+#pragma unroll
+    for (int i = 0; i < T; ++i) acc[i] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+}
+
+// Calls f(row, col, value) for every element a lane holds of MT x NT tiles.
+template <int MT, int NT, typename F>
+__device__ __forceinline__ void tiles_out(const v4f (&acc)[MT * NT], F f) {
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) f(16 * i + 4 * q + v, 16 * j + r, acc[i * NT + j][v]);
+}
+
+// One wavefront per workgroup; wave w takes the blocks of 64 texels
+// w, w + gridDim.x, ...
+__global__ __launch_bounds__(64) void decoder_backward_kernel(DecBwdArgs a) {
+    __shared__ float H1[64 * kDbLd];   // h1, then d1; [unit][texel]
+    __shared__ float H2[64 * kDbLd];   // h2, then d2
+    __shared__ float GT[4 * kDbLd];    // g
+    __shared__ float XT[8 * kDbLd];    // latents
+    const int lane = threadIdx.x;
+    v4f dw2[16], dw1[4], dw3[4];
+    zero_tiles(dw2);
+    zero_tiles(dw1);
+    zero_tiles(dw3);
+    float db1 = 0.0f, db2 = 0.0f, db3 = 0.0f;      // unit `lane` (db3: lanes 0-3)
+    const int64_t ntex = (int64_t)a.tw * a.th;
+#pragma unroll 1
+    for (int blk = blockIdx.x; blk < a.nblocks; blk += gridDim.x) {
+        const int64_t t = (int64_t)blk * 64 + lane;
+        const bool in = t < ntex;
+        float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (in) g = reinterpret_cast<const float4*>(a.g)[t];
+        const bool any = g.x != 0.0f || g.y != 0.0f || g.z != 0.0f || g.w != 0.0f;
+        if (__builtin_amdgcn_ballot_w64(any) == 0) continue;          // no gradient reaches these texels
+        float x[8];
+        if (in) {
+            load_latent(a, t, x);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) x[c] = 0.0f;
+        }
+        GT[0 * kDbLd + lane] = g.x;
+        GT[1 * kDbLd + lane] = g.y;
+        GT[2 * kDbLd + lane] = g.z;
+        GT[3 * kDbLd + lane] = g.w;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) XT[c * kDbLd + lane] = x[c];
+        wave_lds_sync();
+        {   // h1 = ReLU(W1 l + b1)
+            v4f acc[16];
+            zero_tiles(acc);
+            mfma_tiles<4, 4>(acc, [&](int m, int k) { return a.w1[m * 8 + k]; },
+                             [&](int k, int n) { return XT[k * kDbLd + n]; }, 8);
+            tiles_out<4, 4>(acc, [&](int m, int n, float v) { H1[m * kDbLd + n] = fmaxf(v + a.b1[m], 0.0f); });
+        }
+        wave_lds_sync();
+        {   // h2 = ReLU(W2 h1 + b2)
+            v4f acc[16];
+            zero_tiles(acc);
+            mfma_tiles<4, 4>(acc, [&](int m, int k) { return a.w2[m * 64 + k]; },
+                             [&](int k, int n) { return H1[k * kDbLd + n]; }, 64);
+            tiles_out<4, 4>(acc, [&](int m, int n, float v) { H2[m * kDbLd + n] = fmaxf(v + a.b2[m], 0.0f); });
+        }
+        wave_lds_sync();
+        // dW3 += g h2^T (texels contracted; rows 4-15 of the tile are padding)
+        mfma_tiles<1, 4>(dw3, [&](int m, int k) { return m < 4 ? GT[m * kDbLd + k] : 0.0f; },
+                         [&](int k, int n) { return H2[n * kDbLd + k]; }, 64);
+        if (lane < 4)
+            for (int k = 0; k < 64; ++k) db3 += GT[lane * kDbLd + k];
+        wave_lds_sync();
+        {   // d2 = (W3^T g) * [z2 > 0], in place of h2
+            v4f acc[16];
+            zero_tiles(acc);
+            mfma_tiles<4, 4>(acc, [&](int m, int k) { return a.w3[k * 64 + m]; },
+                             [&](int k, int n) { return GT[k * kDbLd + n]; }, 4);
+            tiles_out<4, 4>(acc, [&](int m, int n, float v) {
+                float& h = H2[m * kDbLd + n];
+                h = h > 0.0f ? v : 0.0f;
+            });
+        }
+        wave_lds_sync();
+        // dW2 += d2 h1^T, db2 += sum d2
+        mfma_tiles<4, 4>(dw2, [&](int m, int k) { return H2[m * kDbLd + k]; },
+                         [&](int k, int n) { return H1[n * kDbLd + k]; }, 64);
+        for (int k = 0; k < 64; ++k) db2 += H2[lane * kDbLd + k];
+        wave_lds_sync();
+        {   // d1 = (W2^T d2) * [z1 > 0], in place of h1
+            v4f acc[16];
+            zero_tiles(acc);
+            mfma_tiles<4, 4>(acc, [&](int m, int k) { return a.w2[k * 64 + m]; },
+                             [&](int k, int n) { return H2[k * kDbLd + n]; }, 64);
+            tiles_out<4, 4>(acc, [&](int m, int n, float v) {
+                float& h = H1[m * kDbLd + n];
+                h = h > 0.0f ? v : 0.0f;
+            });
+        }
+        wave_lds_sync();
+        // dW1 += d1 l^T (columns 8-15 of the tile are padding), db1 += sum d1
+        mfma_tiles<4, 1>(dw1, [&](int m, int k) { return H1[m * kDbLd + k]; },
+                         [&](int k, int n) { return n < 8 ? XT[n * kDbLd + k] : 0.0f; }, 64);
+        for (int k = 0; k < 64; ++k) db1 += H1[lane * kDbLd + k];
+        {   // dL/dl = W1^T d1 (rows 8-15 padding); dL/dstored = dL/dl * scale
+            v4f acc[4];
+            zero_tiles(acc);
+            mfma_tiles<1, 4>(acc, [&](int m, int k) { return m < 8 ? a.w1[k * 8 + m] : 0.0f; },
+                             [&](int k, int n) { return H1[k * kDbLd + n]; }, 64);
+            const int64_t base = (int64_t)blk * 64;
+            tiles_out<1, 4>(acc, [&](int m, int n, float v) {
+                if (m < 8 && base + n < ntex) a.dlat[(base + n) * 8 + m] += v * a.scale[m];
+            });
+        }
+        wave_lds_sync();                                              // LDS reads done before the next block
+    }
+    float* out = a.partial + (size_t)blockIdx.x * kGradFloats;
+    tiles_out<4, 4>(dw2, [&](int m, int n, float v) { out[kGradW2 + m * 64 + n] = v; });
+    tiles_out<4, 1>(dw1, [&](int m, int n, float v) {
+        if (n < 8) out[kGradW1 + m * 8 + n] = v;
+    });
+    tiles_out<1, 4>(dw3, [&](int m, int n, float v) {
+        if (m < 4) out[kGradW3 + m * 64 + n] = v;
+    });
+    out[kGradB1 + lane] = db1;
+    out[kGradB2 + lane] = db2;
+    if (lane < 4) out[kGradB3 + lane] = db3;
+}
+
+struct MlpGradPtrs {
+    float* p[6];             // dW1, db1, dW2, db2, dW3, db3 (accumulated)
+};
+
+// Sums the per-wave slots in slot order and adds them to the outputs.
+__global__ __launch_bounds__(256) void decoder_grad_reduce_kernel(const float* partial, int nslots, MlpGradPtrs o) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kGradFloats) return;
+    float s = 0.0f;
+    for (int w = 0; w < nslots; ++w) s += partial[(size_t)w * kGradFloats + e];
+    const int starts[6] = {kGradW1, kGradB1, kGradW2, kGradB2, kGradW3, kGradB3};
+    int k = 5;
+    while (e < starts[k]) --k;
+    o.p[k][e - starts[k]] += s;
+}
+
+// Fills n floats with zero (a kernel, not a memset node: safe under graph capture).
+__global__ __launch_bounds__(256) void zero_fill_kernel(float* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+}  // namespace stf
