@@ -368,6 +368,24 @@ int64_t stf_footprint_workspace_bytes(const stf_footprint_params* p);
 int stf_footprint_generate(const stf_footprint_params* p, void* workspace, int64_t workspace_bytes, uint8_t* lut,
                            int64_t* score, void* hip_stream);
 
+/*
+ * stf_footprint_generate without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The workspace is a static device array
+ * of STF_FOOTPRINT_STATIC_BYTES per GPU, part of the library's image and held
+ * until the process ends; the call itself allocates nothing. Parameters
+ * whose workspace (stf_footprint_workspace_bytes) exceeds that size are
+ * rejected with STF_EINVAL (the paper's settings, k = 9, 32 candidates,
+ * 30 restarts, need about 0.5 MB). Same results as stf_footprint_generate.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (different streams, or several host threads) race and must be
+ * serialised by the caller; calls on different GPUs do not interact. The
+ * first call on a device resolves the array's address with that device
+ * current (STF_EHIP if that fails).
+ */
+#define STF_FOOTPRINT_STATIC_BYTES (4 << 20)
+int stf_footprint_generate_static(const stf_footprint_params* p, uint8_t* lut, int64_t* score, void* hip_stream);
+
 /* Message for the last non-OK status returned on this thread ("" if none).
  * The pointer stays valid until the next call on this thread. */
 const char* stf_last_error(void);

@@ -21,7 +21,7 @@ from typing import Sequence
 __all__ = [
     "BILINEAR", "BICUBIC", "FOOTPRINTS", "FORMATS", "library", "lib_path", "version",
     "filter", "filter_reuse", "filter_reference", "backward", "StfError", "pack_decoder",
-    "generate_footprints", "footprint_set", "stf_reuse_autograd",
+    "generate_footprints", "generate_footprints_static", "footprint_set", "stf_reuse_autograd",
     "backward_decoder", "stf_decoder_autograd",
 ]
 
@@ -101,7 +101,7 @@ ESTIMATORS = {"wis": 0, "is": 1, "mis": 2, "pmis": 3, "regression": 4}
 _lib = None
 _SYMBOLS = ("stf_filter", "stf_filter_reuse", "stf_filter_reference", "stf_backward",
             "stf_decoder_pack", "stf_footprint_workspace_bytes", "stf_footprint_generate",
-            "stf_backward_decoder", "stf_backward_decoder_workspace_bytes",
+            "stf_footprint_generate_static", "stf_backward_decoder", "stf_backward_decoder_workspace_bytes",
             "stf_last_error", "stf_version")
 
 
@@ -129,6 +129,8 @@ def library() -> ctypes.CDLL:
         lib.stf_backward_decoder.argtypes = tex_args + [P(Reuse), P(vp), P(Mlp), P(vp), P(MlpGrad), vp,
                                                         ctypes.c_int64, vp]
         lib.stf_backward_decoder.restype = ctypes.c_int
+        lib.stf_footprint_generate_static.argtypes = [P(FootprintParams), vp, vp, vp]
+        lib.stf_footprint_generate_static.restype = ctypes.c_int
         for name in ("stf_filter", "stf_filter_reuse", "stf_filter_reference", "stf_backward",
                      "stf_decoder_pack", "stf_version"):
             getattr(lib, name).restype = ctypes.c_int
@@ -204,6 +206,31 @@ def generate_footprints(k=9, n_cand=32, sigma=1.4, trials=10000, restarts=30, se
     _check(lib.stf_footprint_generate(ctypes.byref(prm), ctypes.c_void_p(ws.data_ptr() + off), ctypes.c_int64(nbytes),
                                       ctypes.c_void_p(lut.data_ptr()), ctypes.c_void_p(score.data_ptr()),
                                       _stream_handle(stream)))
+    return lut, score
+
+
+FOOTPRINT_STATIC_BYTES = 4 << 20
+
+
+def generate_footprints_static(k=9, n_cand=32, sigma=1.4, trials=10000, restarts=30, seed=0, lut=None,
+                               score=None, device="cuda", stream=None):
+    """generate_footprints through stf_footprint_generate_static: the library
+    uses its static per-GPU workspace and allocates nothing. With `lut`
+    (uint8 GPU tensor [64, k-1]) and `score` (int64 GPU tensor [1]) given,
+    this function allocates nothing either."""
+    import torch
+    if lut is None:
+        lut = torch.empty((64, int(k) - 1), dtype=torch.uint8, device=device)
+    if score is None:
+        score = torch.empty(1, dtype=torch.int64, device=device)
+    if (lut.dtype != torch.uint8 or tuple(lut.shape) != (64, int(k) - 1) or not lut.is_cuda
+            or not lut.is_contiguous()):
+        raise ValueError(f"lut must be a contiguous uint8 GPU tensor [64, {int(k) - 1}]")
+    if score.dtype != torch.int64 or score.numel() < 1 or not score.is_cuda:
+        raise ValueError("score must be an int64 GPU tensor of at least one element")
+    prm = FootprintParams(int(k), int(n_cand), float(sigma), int(trials), int(restarts), int(seed) & 0xFFFFFFFF, 0)
+    _check(library().stf_footprint_generate_static(ctypes.byref(prm), ctypes.c_void_p(lut.data_ptr()),
+                                                   ctypes.c_void_p(score.data_ptr()), _stream_handle(stream)))
     return lut, score
 
 

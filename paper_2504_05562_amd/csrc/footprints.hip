@@ -29,6 +29,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "stf.h"
 #include "stf_device.h"
@@ -255,6 +256,44 @@ int validate(const stf_footprint_params* p) {
     return STF_OK;
 }
 
+// Workspace of stf_footprint_generate_static: a file-scope device array, one
+// copy per GPU, held until the process ends. Host code never passes its name
+// to a kernel (on the host it is only a stand-in for the symbol): the device
+// address of each GPU's copy comes from hipGetSymbolAddress, resolved once per
+// device with that device current.
+__device__ __align__(256) uint8_t scratch[STF_FOOTPRINT_STATIC_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array, or nullptr with the
+// error recorded.
+void* static_scratch() {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        stf_host::fail(STF_EHIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        stf_host::fail(STF_EUNSUPPORTED, "device %d beyond the %d devices the static workspace supports", dev,
+                       kMaxDevices);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            stf_host::fail(STF_EHIP, "hipGetSymbolAddress of the static workspace failed: %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace fp
 }  // namespace stf
 
@@ -303,6 +342,22 @@ int stf_footprint_generate(const stf_footprint_params* prm, void* workspace, int
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return stf_host::fail(STF_EHIP, "footprint generator launch failed: %s", hipGetErrorString(e));
     return STF_OK;
+}
+
+int stf_footprint_generate_static(const stf_footprint_params* prm, uint8_t* lut, int64_t* score, void* hip_stream) {
+    stf_host::clear_error();
+    const int rc = stf::fp::validate(prm);
+    if (rc != STF_OK) return rc;
+    const int64_t need = (int64_t)stf::fp::layout_of(*prm).total;
+    if (need > (int64_t)STF_FOOTPRINT_STATIC_BYTES)
+        return stf_host::fail(STF_EINVAL,
+                              "parameters need a %lld-byte workspace, above the static limit of %lld bytes "
+                              "(restarts * 64 * n_cand * (k-1) must stay below it); use stf_footprint_generate",
+                              (long long)need, (long long)STF_FOOTPRINT_STATIC_BYTES);
+    void* ws = stf::fp::static_scratch();
+    if (ws == nullptr) return STF_EHIP;
+    // the kernels initialise every word of the workspace they read
+    return stf_footprint_generate(prm, ws, (int64_t)STF_FOOTPRINT_STATIC_BYTES, lut, score, hip_stream);
 }
 
 }  // extern "C"
