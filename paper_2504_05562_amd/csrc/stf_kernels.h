@@ -521,13 +521,11 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
 #pragma unroll
     for (int c = 0; c < C; ++c) Tv[c] = T.ch(c);
     if constexpr (MODE == kModeStf) {
-        if (P.valid) {
-            if (scale_out) {
+        if (scale_out) {
 #pragma unroll
-                for (int c = 0; c < C; ++c) Tv[c] *= t.scale[c];
-            }
-            store_out<C>(a.out[slot], pix, Tv);
+            for (int c = 0; c < C; ++c) Tv[c] *= t.scale[c];
         }
+        if (P.valid) store_out<C>(a.out[slot], pix, Tv);
         return;
     } else {
         // 1/p of the own pick; off-screen pixels share a pick of weight zero
@@ -1131,9 +1129,24 @@ __device__ __forceinline__ void atomic_texel(float* g, int tw, uint32_t s, const
     for (int c = 0; c < C; ++c) unsafeAtomicAdd(p + c, v[c] * scale);
 }
 
+// Workgroup merge of the whole-tile adjoint: the four tiles of a workgroup
+// sit side by side, so their bin windows overlap (fully at high
+// magnification). Each wave adds its window's sums into one kMergeW x
+// kMergeH texel area in LDS covering all four, and the workgroup flushes that
+// area with one global atomic per touched texel and channel, instead of each
+// wave flushing its own window: the global FP32 atomics, which bound this
+// kernel, drop by the overlap. A workgroup whose windows do not fit the area
+// (or whose waves fall back to records) flushes per wave.
+constexpr int kMergeW = 32, kMergeH = 16;
+
+struct MergeArea {
+    float* v;                // [kMergeH * kMergeW][C] sums
+    int* info;               // per wave: ok, base_x, base_y
+};
+
 template <int FILT, int MODE, int C>
 __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
-                                              uint32_t hx, uint32_t hy, float* lds) {
+                                              uint32_t hx, uint32_t hy, float* lds, MergeArea merge = {}) {
     constexpr int N = SelCtx<FILT>::N;
     const TexArg t = a.tex[slot];
     const int lane = lane_id();
@@ -1178,14 +1191,16 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
             }
         } else {
             bool use_bins = false;
+            int base_x = 0, base_y = 0;
+            const int ij = lane & 15, kp = lane >> 4;
+            v4f acc[C];
+            float* Nb = lds;
             if constexpr (MODE == kModeBins) {
-                int base_x, base_y;
                 uint32_t rx, ry;
                 use_bins = bin_window<N>(P, ctx.x.base, ctx.y.base, mx, my, t.w, t.h, base_x, base_y, rx, ry);
                 if (use_bins) {
                     // LDS: Nb float [kBins] (sum of 1/p per texel), N64 u64 [kBins]
                     // (its exact integer accumulator, as in the forward pass)
-                    float* Nb = lds;
                     uint64_t* N64 = reinterpret_cast<uint64_t*>(lds + kBwdN64Offset);
                     for (int i = lane; i < kBins; i += 64) N64[i] = 0ull;
                     for (int i = lane; i < kBins; i += 64) Nb[i] = 0.0f;
@@ -1207,7 +1222,7 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
 #pragma unroll
                     for (int b = 0; b < N; ++b)
 #pragma unroll
-                        for (int aa = 0; aa < N; ++aa) B += ctx.wxy[b * N + aa] * Nb[bin0 + b * kBinG + aa];
+                        for (int aa = 0; aa < N; ++aa) B += (ctx.x.w(aa) * ctx.y.w(b)) * Nb[bin0 + b * kBinG + aa];
                     // Sum over the tile's pixels of f_c(x) q_c for every texel x of the
                     // window (q_c = dL/dout_c / B_c): with f_c(x) = wy_c(row) wx_c(col)
                     // it is the rank-64 product  Wy diag(q) Wx^T , run on the matrix
@@ -1234,8 +1249,6 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                                 make_float4(rr[4 * k], rr[4 * k + 1], rr[4 * k + 2], rr[4 * k + 3]);
                     }
                     wave_lds_sync();
-                    const int ij = lane & 15, kp = lane >> 4;
-                    v4f acc[C];
 #pragma unroll
                     for (int c = 0; c < C; ++c) acc[c] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll 1
@@ -1259,23 +1272,6 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                         for (int c = 0; c < C; ++c)
                             acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, wb * rr[1 + 2 * N + c], acc[c], 0, 0, 0);
                     }
-                    // flush: lane holds window rows 4 (l / 16) + v, column l % 16
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int i = 4 * kp + v;
-                        if (i < kBinG && ij < kBinG) {
-                            const float nx = Nb[i * kBinG + ij];
-                            if (nx != 0.0f) {
-                                const uint32_t tx = (uint32_t)(base_x + ij) & mx;
-                                const uint32_t ty = (uint32_t)(base_y + i) & my;
-                                float q[C];
-#pragma unroll
-                                for (int c = 0; c < C; ++c) q[c] = acc[c][v];
-                                atomic_texel<C>(grad, t.w, tx | (ty << 16), q, nx);
-                            }
-                        }
-                    }
-                    wave_lds_sync();
                 }
             }
             if (!use_bins) {
@@ -1308,6 +1304,86 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                 }
                 wave_lds_sync();
             }
+            if constexpr (MODE == kModeBins) {
+                // every wave of the workgroup reaches the barriers below, whichever
+                // path it took; only waves with bins and an on-screen pixel add
+                // lane holds window rows 4 (l / 16) + v, column l % 16
+                const int wave = threadIdx.x >> 6;
+                const bool contributes = use_bins && __builtin_amdgcn_ballot_w64(P.valid) != 0;
+                if (lane == 0) {
+                    merge.info[wave * 4 + 0] = contributes ? 1 : 0;
+                    merge.info[wave * 4 + 1] = base_x;
+                    merge.info[wave * 4 + 2] = base_y;
+                }
+                __syncthreads();
+                // the union of the contributing windows (offsets taken modulo the texture
+                // size relative to the first one); the same result in every thread
+                int ref = -1, lo_x = 0, hi_x = 0, lo_y = 0, hi_y = 0;
+                for (int w = 0; w < kWavesPerGroup; ++w) {
+                    if (!merge.info[w * 4]) continue;
+                    if (ref < 0) ref = w;
+                    const int dx = wrapped_offset(merge.info[w * 4 + 1], merge.info[ref * 4 + 1], mx);
+                    const int dy = wrapped_offset(merge.info[w * 4 + 2], merge.info[ref * 4 + 2], my);
+                    lo_x = min(lo_x, dx); hi_x = max(hi_x, dx);
+                    lo_y = min(lo_y, dy); hi_y = max(hi_y, dy);
+                }
+                const bool merged = ref >= 0 && hi_x - lo_x + kBinG <= kMergeW && hi_y - lo_y + kBinG <= kMergeH;
+                if (merged) {
+                    const int ux = merge.info[ref * 4 + 1] + lo_x, uy = merge.info[ref * 4 + 2] + lo_y;
+                    for (int e = threadIdx.x; e < kMergeW * kMergeH * C; e += kThreads) merge.v[e] = 0.0f;
+                    __syncthreads();
+                    if (contributes) {
+                        // this window's corner in the area: its offset from the reference window,
+                        // as the union was formed (in [0, kMergeW - kBinG] x [0, kMergeH - kBinG])
+                        const int ox = wrapped_offset(base_x, merge.info[ref * 4 + 1], mx) - lo_x;
+                        const int oy = wrapped_offset(base_y, merge.info[ref * 4 + 2], my) - lo_y;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = 4 * kp + v;
+                            if (i < kBinG && ij < kBinG) {
+                                const float nx = Nb[i * kBinG + ij];
+                                if (nx != 0.0f) {
+                                    float* m = merge.v + ((oy + i) * kMergeW + ox + ij) * C;
+#pragma unroll
+                                    for (int c = 0; c < C; ++c) atomicAdd(m + c, acc[c][v] * nx);
+                                }
+                            }
+                        }
+                    }
+                    __syncthreads();
+                    for (int e = threadIdx.x; e < kMergeW * kMergeH; e += kThreads) {
+                        float q[C];
+                        bool any = false;
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            q[c] = merge.v[e * C + c];
+                            any = any || q[c] != 0.0f;
+                        }
+                        if (any) {
+                            const uint32_t tx = (uint32_t)(ux + e % kMergeW) & mx;
+                            const uint32_t ty = (uint32_t)(uy + e / kMergeW) & my;
+                            atomic_texel<C>(grad, t.w, tx | (ty << 16), q, 1.0f);
+                        }
+                    }
+                } else if (contributes) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = 4 * kp + v;
+                        if (i < kBinG && ij < kBinG) {
+                            const float nx = Nb[i * kBinG + ij];
+                            if (nx != 0.0f) {
+                                const uint32_t tx = (uint32_t)(base_x + ij) & mx;
+                                const uint32_t ty = (uint32_t)(base_y + i) & my;
+                                float q[C];
+#pragma unroll
+                                for (int c = 0; c < C; ++c) q[c] = acc[c][v];
+                                atomic_texel<C>(grad, t.w, tx | (ty << 16), q, nx);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();             // merge area and window read before the next slot
+            }
         }
     }
 }
@@ -1317,8 +1393,21 @@ template <int FILT, int MODE>
 __global__ __launch_bounds__(kThreads, (MODE == kModeBins ? 4 : 1)) void backward_kernel(Args a) {
     constexpr int kPerWave = kBwdLdsFloatsPerWave > kLdsFloatsPerWave ? kBwdLdsFloatsPerWave : kLdsFloatsPerWave;
     __shared__ __align__(16) float lds_all[kWavesPerGroup * kPerWave];
+    constexpr bool kMerge = MODE == kModeBins;
+    __shared__ __align__(16) float merge_v[kMerge ? kMergeW * kMergeH * 4 : 4];
+    __shared__ int merge_info[kWavesPerGroup * 4];
+    const MergeArea merge{merge_v, merge_info};
     Pixel P;
-    if (!setup_pixel(a, P)) return;
+    if constexpr (kMerge) {
+        // the whole-tile adjoint merges per workgroup behind barriers: a wave whose
+        // tile column is off screen stays (every lane off screen, nothing added)
+        place_pixel(a, blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6), blockIdx.y, P);
+        const v2f uv = load_uv(a, P.px, P.py);
+        P.u = uv.x;
+        P.v = uv.y;
+    } else {
+        if (!setup_pixel(a, P)) return;
+    }
     float* lds = lds_all + (threadIdx.x >> 6) * kPerWave;
     SelCtx<FILT> ctx;
     for (int slot = 0; slot < a.ntex; ++slot) {
@@ -1326,9 +1415,9 @@ __global__ __launch_bounds__(kThreads, (MODE == kModeBins ? 4 : 1)) void backwar
         keyed_uniforms(a, P, slot, hx, hy);
         ctx.update(P, a.tex[slot].w, a.tex[slot].h);
         const int ch = a.tex[slot].ch;
-        if (ch == 4) backward_slot<FILT, MODE, 4>(a, slot, P, ctx, hx, hy, lds);
-        else if (ch == 2) backward_slot<FILT, MODE, 2>(a, slot, P, ctx, hx, hy, lds);
-        else backward_slot<FILT, MODE, 1>(a, slot, P, ctx, hx, hy, lds);
+        if (ch == 4) backward_slot<FILT, MODE, 4>(a, slot, P, ctx, hx, hy, lds, merge);
+        else if (ch == 2) backward_slot<FILT, MODE, 2>(a, slot, P, ctx, hx, hy, lds, merge);
+        else backward_slot<FILT, MODE, 1>(a, slot, P, ctx, hx, hy, lds, merge);
     }
 }
 

@@ -40,6 +40,51 @@ def test_backward_matches_oracle_adjoint(filt, fp, float_sums):
     assert np.max(np.abs(got - want)) <= 1e-5 * scale, np.max(np.abs(got - want)) / scale
 
 
+def _adjoint_case(tex, uv, g, fp, filt, seed, frame, lut=None):
+    H, W = uv.shape[:2]
+    got = stf.backward([dev(tex)], dev(uv), [dev(g)], fp, filt, seed, frame,
+                       lut=dev(lut) if lut is not None else None)[0].cpu().numpy()
+    tiles = o.all_tiles(W, H)
+    px = tiles[:, 0:1] * 8 + (np.arange(64) % 8)[None]
+    py = tiles[:, 1:2] * 8 + (np.arange(64) // 8)[None]
+    valid = (px < W) & (py < H)
+    gt = np.where(valid[..., None], g[np.minimum(py, H - 1), np.minimum(px, W - 1)], 0.0)
+    ftag = o.BICUBIC if filt == "bicubic" else o.BILINEAR
+    want = o.stf_adjoint([tex], uv, ftag, seed, frame, fp, [gt], lut=lut)[0]
+    scale = np.abs(want).max()
+    return np.max(np.abs(got - want)) / scale
+
+
+@pytest.mark.parametrize("fp", ["wave2x2", "square4x4", "lut"])
+def test_backward_other_footprints(fp):
+    rng = np.random.default_rng(12)
+    tex = rng.random((64, 64, 4)).astype(np.float32)
+    uv = w.small_screen(53, 37, 64, 3.0, offset_seed=3)
+    g = rng.standard_normal(uv.shape[:2] + (4,)).astype(np.float32)
+    lut = rng.integers(0, 64, (64, 8)).astype(np.uint8) if fp == "lut" else None
+    assert _adjoint_case(tex, uv, g, fp, "bicubic", 7, 1, lut) <= 1e-5
+
+
+@pytest.mark.parametrize("filt", ["bilinear", "bicubic"])
+def test_backward_perspective_with_fallback_waves(filt):
+    """A perspective plane from strong magnification down to minification:
+    near the top the tile's supports leave the 12x12 bin window and those
+    waves take the record fallback (checked here with the oracle's own
+    coordinates), next to waves whose windows merge per workgroup."""
+    rng = np.random.default_rng(4)
+    tex = rng.random((256, 256, 4)).astype(np.float32)
+    uv, _, _, _ = w.perspective_plane(160, 96, 256, 0.25, 8.0)
+    n, d = (4, 1) if filt == "bicubic" else (2, 0)
+    i0x, _ = o.split_coord(o.texel_float_coord(uv[..., 0], 256))
+    i0y, _ = o.split_coord(o.texel_float_coord(uv[..., 1], 256))
+    sx = (i0x[:96, :160] - d).reshape(12, 8, 20, 8).swapaxes(1, 2).reshape(12, 20, 64)
+    sy = (i0y[:96, :160] - d).reshape(12, 8, 20, 8).swapaxes(1, 2).reshape(12, 20, 64)
+    spread = np.maximum(sx.max(-1) - sx.min(-1), sy.max(-1) - sy.min(-1))
+    assert np.any(spread > 12 - n) and np.any(spread <= 12 - n)     # both paths occur
+    g = rng.standard_normal((96, 160, 4)).astype(np.float32)
+    assert _adjoint_case(tex, uv, g, "tile8x8", filt, 3, 0) <= 1e-5
+
+
 def test_backward_central_differences_32x32():
     rng = np.random.default_rng(8)
     tex = rng.random((32, 32, 4)).astype(np.float32)
