@@ -110,6 +110,22 @@ __device__ __forceinline__ int member_id(int fp, int lx, int ly, int m, const ui
     }
 }
 
+// Window footprints as origin (ox, oy) and size n on the tile: the members
+// are the n x n tile pixels from the origin (member_id in row-major order).
+__device__ __forceinline__ void window_of(int fp, int lx, int ly, int& ox, int& oy, int& n) {
+    switch (fp) {
+    case STF_FP_QUAD2X2: ox = lx & ~1; oy = ly & ~1; n = 2; break;
+    case STF_FP_WAVE2X2:
+        ox = min(max(lx - ((ly + (lx >> 1)) & 1), 0), 6);
+        oy = min(max(ly - ((lx + (ly >> 1)) & 1), 0), 6);
+        n = 2;
+        break;
+    case STF_FP_SQUARE3X3: ox = min(max(lx - 1, 0), 5); oy = min(max(ly - 1, 0), 5); n = 3; break;
+    case STF_FP_SQUARE4X4: ox = min(max(lx - 1, 0), 4); oy = min(max(ly - 1, 0), 4); n = 4; break;
+    default: ox = 0; oy = 0; n = 8; break;     // STF_FP_TILE8X8
+    }
+}
+
 __device__ __forceinline__ int footprint_size(int fp, int lut_k) {
     switch (fp) {
     case STF_FP_QUAD2X2: case STF_FP_WAVE2X2: return 4;
@@ -629,12 +645,9 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
                 for (int c = 0; c < C; ++c) pad[c] = Tv[c];
                 val[P.q] = make_float4(pad[0], pad[1], pad[2], pad[3]);
                 wave_lds_sync();
-                const int fp = (MODE == kModeBins) ? (int)STF_FP_TILE8X8 : a.footprint;
-                const int K = footprint_size(fp, a.lut_k);
                 if constexpr (EF) cov.add(ctx, (uint32_t)kx, (uint32_t)ky, Tv);
-                for (int m = 0; m < K; ++m) {
-                    const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
-                    if (j == P.q) continue;          // the own pick is already counted
+                auto member = [&](int j) {
+                    if (j == P.q) return;            // the own pick is already counted
                     const uint2 mj = meta[j];
                     const float4 vj = val[j];
                     const float Ti[4] = {vj.x, vj.y, vj.z, vj.w};
@@ -642,6 +655,27 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
                     if constexpr (EF) {
                         if (__uint_as_float(mj.y) != 0.0f) cov.add_pick(ctx, mj.x, Ti, mx, my);
                     }
+                };
+                if constexpr (MODE == kModeBins) {   // record fallback of the whole tile
+                    for (int m = 0; m < 64; ++m) {
+                        if (m == P.q) continue;
+                        const uint2 mj = meta[m];
+                        const float4 vj = val[m];
+                        const float Ti[4] = {vj.x, vj.y, vj.z, vj.w};
+                        accumulate<FILT, C>(ctx, mj.x, __uint_as_float(mj.y), Ti, mx, my, Tv, B, acc);
+                        if constexpr (EF) {
+                            if (__uint_as_float(mj.y) != 0.0f) cov.add_pick(ctx, mj.x, Ti, mx, my);
+                        }
+                    }
+                } else if (a.footprint == STF_FP_LUT) {
+                    for (int m = 0; m < a.lut_k; ++m) member(a.lut[P.q * a.lut_k + m] & 63);
+                } else {
+                    // square windows: origin and size once per pixel, then the rows and
+                    // columns of the window (wave-uniform trip counts)
+                    int ox, oy, n;
+                    window_of(a.footprint, P.lx, P.ly, ox, oy, n);
+                    for (int wy = 0; wy < n; ++wy)
+                        for (int wx = 0; wx < n; ++wx) member((oy + wy) * 8 + ox + wx);
                 }
                 if constexpr (EF) covered = cov.covered(ctx);
                 wave_lds_sync();
