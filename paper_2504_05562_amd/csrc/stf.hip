@@ -420,12 +420,13 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workspace layout of stf_backward_decoder: per texture the dense FP32
 // gradient of its decoded texels [th * tw][4], then one slot of weight
-// gradients per decoder-backward wavefront of every texture.
+// gradients per decoder-backward wavefront of every texture, then the
+// partial sums of the reduction's first step.
 struct DecBwdLayout {
     size_t g[STF_MAX_TEXTURES];
     int waves[STF_MAX_TEXTURES];
     int total_waves = 0;
-    size_t partial = 0, total = 0;
+    size_t partial = 0, level2 = 0, total = 0;
 };
 
 DecBwdLayout dec_bwd_layout(const stf_texture* tex, int32_t ntex) {
@@ -435,12 +436,13 @@ DecBwdLayout dec_bwd_layout(const stf_texture* tex, int32_t ntex) {
         const int64_t n = (int64_t)tex[i].width * tex[i].height;
         l.g[i] = off;
         off += align256((size_t)n * 16);
-        const int64_t blocks = (n + 63) / 64;
+        const int64_t blocks = (n + stf::kDbN - 1) / stf::kDbN;
         l.waves[i] = (int)std::min<int64_t>(blocks, stf::kDecBwdMaxWaves);
         l.total_waves += l.waves[i];
     }
     l.partial = off;
-    l.total = off + align256((size_t)l.total_waves * stf::kGradFloats * 4);
+    l.level2 = off + align256((size_t)l.total_waves * stf::kGradFloats * 4);
+    l.total = l.level2 + align256((size_t)stf::kReduceSplits * stf::kGradFloats * 4);
     return l;
 }
 
@@ -540,7 +542,7 @@ int stf_backward_decoder(const stf_texture* tex, int32_t ntex, const stf_screen*
         d.tw = tex[i].width;
         d.th = tex[i].height;
         d.fmt = tex[i].format;
-        d.nblocks = (int)(((int64_t)d.tw * d.th + 63) / 64);
+        d.nblocks = (int)(((int64_t)d.tw * d.th + stf::kDbN - 1) / stf::kDbN);
         for (int c = 0; c < 8; ++c) d.scale[c] = tex[i].scale != nullptr ? tex[i].scale[c] : 1.0f;
         d.g = reinterpret_cast<const float*>(wsp + l.g[i]);
         d.w1 = mlp->w1;
@@ -555,8 +557,11 @@ int stf_backward_decoder(const stf_texture* tex, int32_t ntex, const stf_screen*
     }
     stf::MlpGradPtrs o;
     for (int i = 0; i < 6; ++i) o.p[i] = gs[i];
+    float* level2 = reinterpret_cast<float*>(wsp + l.level2);
+    hipLaunchKernelGGL(stf::decoder_grad_partial_kernel, dim3((stf::kGradFloats + 255) / 256, stf::kReduceSplits),
+                       dim3(256), 0, s, static_cast<const float*>(partial), l.total_waves, level2);
     hipLaunchKernelGGL(stf::decoder_grad_reduce_kernel, dim3((stf::kGradFloats + 255) / 256), dim3(256), 0, s,
-                       static_cast<const float*>(partial), l.total_waves, o);
+                       static_cast<const float*>(level2), o);
     return finish_launch("decoder backward");
 }
 

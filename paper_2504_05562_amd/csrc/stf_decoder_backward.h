@@ -12,7 +12,7 @@
 //     dW3 = sum g h2^T,  dW2 = sum d2 h1^T,  dW1 = sum d1 l^T,  db = sums of g, d2, d1
 // in FP32 with the FP32 weights (the forward pass's BF16 or FP8 rounding of
 // weights and activations is passed straight through, as in mixed-precision
-// training). One wavefront takes 64 consecutive texels of the grid at a
+// training). One wavefront takes kDbN consecutive texels of the grid at a
 // time: their activations live in LDS with the texels as columns, and every
 // product above -- the per-texel layers as well as the weight gradients,
 // which contract over the texels -- runs on v_mfma_f32_16x16x4_f32. A wave's
@@ -28,7 +28,8 @@
 
 namespace stf {
 
-constexpr int kDbLd = 65;                          // LDS row stride (floats) of the [unit][texel] arrays
+constexpr int kDbN = 32;                           // texels per block (the columns of the products)
+constexpr int kDbLd = kDbN + 1;                    // LDS row stride (floats) of the [unit][texel] arrays
 constexpr int kGradW1 = 0, kGradB1 = kGradW1 + 64 * 8, kGradW2 = kGradB1 + 64, kGradB2 = kGradW2 + 64 * 64,
               kGradW3 = kGradB2 + 64, kGradB3 = kGradW3 + 4 * 64, kGradFloats = kGradB3 + 4;   // 4996
 constexpr int kDecBwdMaxWaves = 2048;
@@ -37,7 +38,7 @@ struct DecBwdArgs {
     const uint8_t* data;     // latent grid, row pitch `pitch`
     int64_t pitch;
     int32_t tw, th, fmt;
-    int32_t nblocks;         // ceil(tw * th / 64)
+    int32_t nblocks;         // ceil(tw * th / kDbN)
     float scale[8];          // latent = stored * scale
     const float* g;          // dL/d(decoded texel), [th * tw][4]
     const float* w1;         // [64][8]
@@ -114,14 +115,16 @@ __device__ __forceinline__ void tiles_out(const v4f (&acc)[MT * NT], F f) {
             for (int v = 0; v < 4; ++v) f(16 * i + 4 * q + v, 16 * j + r, acc[i * NT + j][v]);
 }
 
-// One wavefront per workgroup; wave w takes the blocks of 64 texels
-// w, w + gridDim.x, ...
-__global__ __launch_bounds__(64) void decoder_backward_kernel(DecBwdArgs a) {
+// One wavefront per workgroup; wave w takes the blocks of kDbN texels
+// w, w + gridDim.x, ... Blocks of 32 texels keep the LDS arrays at 18.5 KB
+// and the transient accumulators at 8 tiles, so that two waves fit a SIMD.
+__global__ __launch_bounds__(64, 2) void decoder_backward_kernel(DecBwdArgs a) {
     __shared__ float H1[64 * kDbLd];   // h1, then d1; [unit][texel]
     __shared__ float H2[64 * kDbLd];   // h2, then d2
     __shared__ float GT[4 * kDbLd];    // g
     __shared__ float XT[8 * kDbLd];    // latents
     const int lane = threadIdx.x;
+    constexpr int NT = kDbN / 16;      // column tiles of the per-texel products
     v4f dw2[16], dw1[4], dw3[4];
     zero_tiles(dw2);
     zero_tiles(dw1);
@@ -130,8 +133,8 @@ __global__ __launch_bounds__(64) void decoder_backward_kernel(DecBwdArgs a) {
     const int64_t ntex = (int64_t)a.tw * a.th;
 #pragma unroll 1
     for (int blk = blockIdx.x; blk < a.nblocks; blk += gridDim.x) {
-        const int64_t t = (int64_t)blk * 64 + lane;
-        const bool in = t < ntex;
+        const int64_t t = (int64_t)blk * kDbN + lane;
+        const bool in = lane < kDbN && t < ntex;
         float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (in) g = reinterpret_cast<const float4*>(a.g)[t];
         const bool any = g.x != 0.0f || g.y != 0.0f || g.z != 0.0f || g.w != 0.0f;
@@ -143,41 +146,43 @@ __global__ __launch_bounds__(64) void decoder_backward_kernel(DecBwdArgs a) {
 #pragma unroll
             for (int c = 0; c < 8; ++c) x[c] = 0.0f;
         }
-        GT[0 * kDbLd + lane] = g.x;
-        GT[1 * kDbLd + lane] = g.y;
-        GT[2 * kDbLd + lane] = g.z;
-        GT[3 * kDbLd + lane] = g.w;
+        if (lane < kDbN) {
+            GT[0 * kDbLd + lane] = g.x;
+            GT[1 * kDbLd + lane] = g.y;
+            GT[2 * kDbLd + lane] = g.z;
+            GT[3 * kDbLd + lane] = g.w;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) XT[c * kDbLd + lane] = x[c];
+            for (int c = 0; c < 8; ++c) XT[c * kDbLd + lane] = x[c];
+        }
         wave_lds_sync();
         {   // h1 = ReLU(W1 l + b1)
-            v4f acc[16];
+            v4f acc[4 * NT];
             zero_tiles(acc);
-            mfma_tiles<4, 4>(acc, [&](int m, int k) { return a.w1[m * 8 + k]; },
-                             [&](int k, int n) { return XT[k * kDbLd + n]; }, 8);
-            tiles_out<4, 4>(acc, [&](int m, int n, float v) { H1[m * kDbLd + n] = fmaxf(v + a.b1[m], 0.0f); });
+            mfma_tiles<4, NT>(acc, [&](int m, int k) { return a.w1[m * 8 + k]; },
+                              [&](int k, int n) { return XT[k * kDbLd + n]; }, 8);
+            tiles_out<4, NT>(acc, [&](int m, int n, float v) { H1[m * kDbLd + n] = fmaxf(v + a.b1[m], 0.0f); });
         }
         wave_lds_sync();
         {   // h2 = ReLU(W2 h1 + b2)
-            v4f acc[16];
+            v4f acc[4 * NT];
             zero_tiles(acc);
-            mfma_tiles<4, 4>(acc, [&](int m, int k) { return a.w2[m * 64 + k]; },
-                             [&](int k, int n) { return H1[k * kDbLd + n]; }, 64);
-            tiles_out<4, 4>(acc, [&](int m, int n, float v) { H2[m * kDbLd + n] = fmaxf(v + a.b2[m], 0.0f); });
+            mfma_tiles<4, NT>(acc, [&](int m, int k) { return a.w2[m * 64 + k]; },
+                              [&](int k, int n) { return H1[k * kDbLd + n]; }, 64);
+            tiles_out<4, NT>(acc, [&](int m, int n, float v) { H2[m * kDbLd + n] = fmaxf(v + a.b2[m], 0.0f); });
         }
         wave_lds_sync();
         // dW3 += g h2^T (texels contracted; rows 4-15 of the tile are padding)
         mfma_tiles<1, 4>(dw3, [&](int m, int k) { return m < 4 ? GT[m * kDbLd + k] : 0.0f; },
-                         [&](int k, int n) { return H2[n * kDbLd + k]; }, 64);
+                         [&](int k, int n) { return H2[n * kDbLd + k]; }, kDbN);
         if (lane < 4)
-            for (int k = 0; k < 64; ++k) db3 += GT[lane * kDbLd + k];
+            for (int k = 0; k < kDbN; ++k) db3 += GT[lane * kDbLd + k];
         wave_lds_sync();
         {   // d2 = (W3^T g) * [z2 > 0], in place of h2
-            v4f acc[16];
+            v4f acc[4 * NT];
             zero_tiles(acc);
-            mfma_tiles<4, 4>(acc, [&](int m, int k) { return a.w3[k * 64 + m]; },
-                             [&](int k, int n) { return GT[k * kDbLd + n]; }, 4);
-            tiles_out<4, 4>(acc, [&](int m, int n, float v) {
+            mfma_tiles<4, NT>(acc, [&](int m, int k) { return a.w3[k * 64 + m]; },
+                              [&](int k, int n) { return GT[k * kDbLd + n]; }, 4);
+            tiles_out<4, NT>(acc, [&](int m, int n, float v) {
                 float& h = H2[m * kDbLd + n];
                 h = h > 0.0f ? v : 0.0f;
             });
@@ -185,15 +190,15 @@ __global__ __launch_bounds__(64) void decoder_backward_kernel(DecBwdArgs a) {
         wave_lds_sync();
         // dW2 += d2 h1^T, db2 += sum d2
         mfma_tiles<4, 4>(dw2, [&](int m, int k) { return H2[m * kDbLd + k]; },
-                         [&](int k, int n) { return H1[n * kDbLd + k]; }, 64);
-        for (int k = 0; k < 64; ++k) db2 += H2[lane * kDbLd + k];
+                         [&](int k, int n) { return H1[n * kDbLd + k]; }, kDbN);
+        for (int k = 0; k < kDbN; ++k) db2 += H2[lane * kDbLd + k];
         wave_lds_sync();
         {   // d1 = (W2^T d2) * [z1 > 0], in place of h1
-            v4f acc[16];
+            v4f acc[4 * NT];
             zero_tiles(acc);
-            mfma_tiles<4, 4>(acc, [&](int m, int k) { return a.w2[k * 64 + m]; },
-                             [&](int k, int n) { return H2[k * kDbLd + n]; }, 64);
-            tiles_out<4, 4>(acc, [&](int m, int n, float v) {
+            mfma_tiles<4, NT>(acc, [&](int m, int k) { return a.w2[k * 64 + m]; },
+                              [&](int k, int n) { return H2[k * kDbLd + n]; }, 64);
+            tiles_out<4, NT>(acc, [&](int m, int n, float v) {
                 float& h = H1[m * kDbLd + n];
                 h = h > 0.0f ? v : 0.0f;
             });
@@ -201,15 +206,15 @@ __global__ __launch_bounds__(64) void decoder_backward_kernel(DecBwdArgs a) {
         wave_lds_sync();
         // dW1 += d1 l^T (columns 8-15 of the tile are padding), db1 += sum d1
         mfma_tiles<4, 1>(dw1, [&](int m, int k) { return H1[m * kDbLd + k]; },
-                         [&](int k, int n) { return n < 8 ? XT[n * kDbLd + k] : 0.0f; }, 64);
-        for (int k = 0; k < 64; ++k) db1 += H1[lane * kDbLd + k];
+                         [&](int k, int n) { return n < 8 ? XT[n * kDbLd + k] : 0.0f; }, kDbN);
+        for (int k = 0; k < kDbN; ++k) db1 += H1[lane * kDbLd + k];
         {   // dL/dl = W1^T d1 (rows 8-15 padding); dL/dstored = dL/dl * scale
-            v4f acc[4];
+            v4f acc[NT];
             zero_tiles(acc);
-            mfma_tiles<1, 4>(acc, [&](int m, int k) { return m < 8 ? a.w1[k * 8 + m] : 0.0f; },
-                             [&](int k, int n) { return H1[k * kDbLd + n]; }, 64);
-            const int64_t base = (int64_t)blk * 64;
-            tiles_out<1, 4>(acc, [&](int m, int n, float v) {
+            mfma_tiles<1, NT>(acc, [&](int m, int k) { return m < 8 ? a.w1[k * 8 + m] : 0.0f; },
+                              [&](int k, int n) { return H1[k * kDbLd + n]; }, 64);
+            const int64_t base = (int64_t)blk * kDbN;
+            tiles_out<1, NT>(acc, [&](int m, int n, float v) {
                 if (m < 8 && base + n < ntex) a.dlat[(base + n) * 8 + m] += v * a.scale[m];
             });
         }
@@ -232,12 +237,25 @@ struct MlpGradPtrs {
     float* p[6];             // dW1, db1, dW2, db2, dW3, db3 (accumulated)
 };
 
-// Sums the per-wave slots in slot order and adds them to the outputs.
-__global__ __launch_bounds__(256) void decoder_grad_reduce_kernel(const float* partial, int nslots, MlpGradPtrs o) {
+// The per-wave slots are summed in two fixed-order steps, so that many
+// threads share the reads: kReduceSplits partial sums per gradient element
+// (slots split + k * kReduceSplits), then their sum added to the outputs.
+constexpr int kReduceSplits = 64;
+
+__global__ __launch_bounds__(256) void decoder_grad_partial_kernel(const float* partial, int nslots, float* level2) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= kGradFloats) return;
     float s = 0.0f;
-    for (int w = 0; w < nslots; ++w) s += partial[(size_t)w * kGradFloats + e];
+    for (int w = blockIdx.y; w < nslots; w += kReduceSplits) s += partial[(size_t)w * kGradFloats + e];
+    level2[(size_t)blockIdx.y * kGradFloats + e] = s;
+}
+
+__global__ __launch_bounds__(256) void decoder_grad_reduce_kernel(const float* level2, MlpGradPtrs o) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kGradFloats) return;
+    float s = 0.0f;
+#pragma unroll 8
+    for (int w = 0; w < kReduceSplits; ++w) s += level2[(size_t)w * kGradFloats + e];
     const int starts[6] = {kGradW1, kGradB1, kGradW2, kGradB2, kGradW3, kGradB3};
     int k = 5;
     while (e < starts[k]) --k;

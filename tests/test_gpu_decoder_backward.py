@@ -134,7 +134,7 @@ def test_decoder_adjoint_matches_oracle(filt, fp, kind):
 
 
 def stf_waves(size):
-    return min((size * size + 63) // 64, 2048)
+    return min((size * size + 31) // 32, 2048)         # one block of 32 texels per step
 
 
 def test_accumulates_and_two_slots():
