@@ -121,6 +121,23 @@ def summarize_pmc(fetch_csv: str, write_csv: str, sq_csv: str | None = None, out
     return d
 
 
+def summarize_trace(trace_csv: str) -> dict:
+    """Per-kernel dispatch count, median, average, minimum and maximum
+    duration (ns) from a rocprofv3 --kernel-trace CSV (the median is the
+    figure the measurement plan asks for: at least 50 launches)."""
+    import csv
+    by = {}
+    for r in csv.DictReader(open(trace_csv)):
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        by.setdefault(r["Kernel_Name"], []).append(d)
+    out = {}
+    for k, v in by.items():
+        v = sorted(v)
+        out[k] = {"calls": len(v), "median_ns": v[len(v) // 2] if len(v) % 2 else (v[len(v) // 2 - 1] + v[len(v) // 2]) / 2,
+                  "average_ns": round(sum(v) / len(v), 1), "min_ns": v[0], "max_ns": v[-1]}
+    return out
+
+
 def copy_probe(torch, dev, nbytes=512 << 20, reps=5):
     """Device-to-device copy of a buffer larger than the last-level cache:
     the achievable HBM rate (read + write bytes / time) and the reference
@@ -544,8 +561,9 @@ def latent_form(torch, stf, w, steps, warmup):
             "mfma_bf16_peak_tflops": 2500.0}
 
 
-def profile_launches(torch, stf, w, which, n=5):
-    """n launches of one secondary workload, for kernel traces and counters."""
+def profile_launches(torch, stf, w, which, n=50):
+    """n launches of one secondary workload, for kernel traces (medians over
+    at least 50 launches) and counters."""
     dev = torch.device("cuda:0")
     if which == "backward":
         uv = torch.from_numpy(w.perspective_plane(1920, 1080, 2048, 2.0, 32.0)[0]).to(dev)
@@ -563,6 +581,17 @@ def profile_launches(torch, stf, w, which, n=5):
             stf.filter_reuse(texs, uv, "tile8x8", "bicubic", 0, 0, out=outs)
             stf.filter_reuse(texs, uv, "tile8x8", "bicubic", 0, 0, out=outs, share_selection=True)
         stf.filter_reference(texs, uv, "bicubic", out=outs)
+    elif which == "decoder_backward":
+        uv = torch.from_numpy(w.view_set(1, 1920, 1080, 1024, seed=5)[0]).to(dev)
+        rng = np.random.Generator(np.random.PCG64(21))
+        lat = [torch.from_numpy((rng.standard_normal((1024, 1024, 8)) * 0.5).astype(np.float16)).to(dev)]
+        layers = [(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)) for a, b in w.mlp_weights(9)]
+        dec = stf.pack_decoder(layers)
+        g = [torch.randn((1080, 1920, 4), device=dev)]
+        dl = [torch.zeros((1024, 1024, 8), device=dev)]
+        dly = [(torch.zeros_like(a), torch.zeros_like(b)) for a, b in layers]
+        for _ in range(n):
+            stf.backward_decoder(lat, uv, g, layers, dec, "tile8x8", "bicubic", 0, 0, dlatent=dl, dlayers=dly)
     else:
         uv = torch.from_numpy(w.perspective_plane(1920, 1080, 1024, 4.0, 16.0)[0]).to(dev)
         lat = w.latent_grid(0, 1024).astype(np.float64)
@@ -588,14 +617,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision, backward and latent-decoder comparisons")
-    ap.add_argument("--profile", choices=["latent", "backward", "materials"],
-                    help="only run 5 launches of the latent-decoder, backward or 4K four-texture workload "
+    ap.add_argument("--profile", choices=["latent", "backward", "materials", "decoder_backward"],
+                    help="only run 50 launches of the latent-decoder, backward, decoder-backward or 4K four-texture workload "
                          "(for rocprofv3) and exit")
     ap.add_argument("--summarize-pmc", nargs="+", metavar="CSV",
                     help="write the per-launch traffic summary from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-trace", metavar="CSV",
+                    help="print per-kernel launch statistics (median included) of a rocprofv3 kernel trace and exit")
     args = ap.parse_args()
     if args.summarize_pmc:
         print(json.dumps(summarize_pmc(*args.summarize_pmc)))
+        return
+    if args.summarize_trace:
+        print(json.dumps(summarize_trace(args.summarize_trace), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
