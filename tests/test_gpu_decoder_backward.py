@@ -76,15 +76,15 @@ def magnitudes(lat, layers, G):
     return ml, per_texel, amb
 
 
-CASES = [("bicubic", "tile8x8", "f16"), ("bicubic", "quad2x2", "fp8"), ("bilinear", "square3x3", "bf16"),
-         ("bicubic", "self", "f16"), ("bilinear", "tile8x8", "fp8")]
+CASES = [("bicubic", "tile8x8", "f16", 32), ("bicubic", "quad2x2", "fp8", 32), ("bilinear", "square3x3", "bf16", 32),
+         ("bicubic", "self", "f16", 32), ("bilinear", "tile8x8", "fp8", 32),
+         ("bicubic", "tile8x8", "f16", 4)]        # 16 texels: one partial block of the decoder adjoint
 
 
-@pytest.mark.parametrize("filt,fp,kind", CASES)
-def test_decoder_adjoint_matches_oracle(filt, fp, kind):
+@pytest.mark.parametrize("filt,fp,kind,size", CASES)
+def test_decoder_adjoint_matches_oracle(filt, fp, kind, size):
     rng = np.random.default_rng(11)
-    size = 32
-    lat = w.latent_grid(2, size).astype(np.float64)
+    lat = w.latent_grid(2, max(size, 8))[:size, :size].astype(np.float64)
     scale = w.amax_scale(lat, kind) if kind == "fp8" else rng.uniform(0.5, 2.0, 8).astype(np.float32).astype(np.float64)
     stored = w.quantize(lat, kind, scale)
     layers32 = w.mlp_weights(4)
