@@ -296,7 +296,11 @@ typedef struct stf_mlp_grad {
 } stf_mlp_grad;
 
 /* Device workspace stf_backward_decoder needs for these textures (latent
- * formats, power-of-two sizes), or -1 if they are invalid. */
+ * formats, power-of-two sizes), or -1 if they are invalid: per texture a
+ * dense FP32 texel gradient (16 bytes per texel) and the list of its blocks
+ * of 32 texels that a gradient reaches (about 4 bytes per block), then per-wave
+ * weight-gradient slots (about 20 KB per wave, at most 2048 waves per
+ * texture). */
 int64_t stf_backward_decoder_workspace_bytes(const stf_texture* tex, int32_t ntex);
 
 /*

@@ -424,6 +424,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // partial sums of the reduction's first step.
 struct DecBwdLayout {
     size_t g[STF_MAX_TEXTURES];
+    size_t list[STF_MAX_TEXTURES], count[STF_MAX_TEXTURES];   // the block mask follows g directly
     int waves[STF_MAX_TEXTURES];
     int total_waves = 0;
     size_t partial = 0, level2 = 0, total = 0;
@@ -434,9 +435,13 @@ DecBwdLayout dec_bwd_layout(const stf_texture* tex, int32_t ntex) {
     size_t off = 0;
     for (int i = 0; i < ntex; ++i) {
         const int64_t n = (int64_t)tex[i].width * tex[i].height;
-        l.g[i] = off;
-        off += align256((size_t)n * 16);
         const int64_t blocks = (n + stf::kDbN - 1) / stf::kDbN;
+        l.g[i] = off;                                   // n * 16 is a multiple of 256 (n >= 16, a power of two)
+        off += align256((size_t)n * 16 + (size_t)(blocks + 31) / 32 * 4);
+        l.list[i] = off;
+        off += align256((size_t)blocks * 4);
+        l.count[i] = off;
+        off += 256;
         l.waves[i] = (int)std::min<int64_t>(blocks, stf::kDecBwdMaxWaves);
         l.total_waves += l.waves[i];
     }
@@ -511,7 +516,8 @@ int stf_backward_decoder(const stf_texture* tex, int32_t ntex, const stf_screen*
     //    first); the latent scale precedes the decoder, so none applies here
     for (int i = 0; i < ntex; ++i) {
         float* g = reinterpret_cast<float*>(wsp + l.g[i]);
-        const int64_t n = (int64_t)tex[i].width * tex[i].height * 4;
+        const int64_t texels = (int64_t)tex[i].width * tex[i].height;
+        const int64_t n = texels * 4 + ((texels + stf::kDbN - 1) / stf::kDbN + 31) / 32;   // g, then the block mask
         hipLaunchKernelGGL(stf::zero_fill_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256),
                            0, s, g, n);
         a.out[i] = g;
@@ -532,8 +538,11 @@ int stf_backward_decoder(const stf_texture* tex, int32_t ntex, const stf_screen*
     default: if (cubic) STF_BW(1, stf::kModeRecords); else STF_BW(0, stf::kModeRecords); break;
     }
 #undef STF_BW
-    // 2. through the decoder, per texture; 3. the weight gradients summed
+    // 2. per texture: the blocks some gradient reaches, listed in order, then
+    //    through the decoder; 3. the weight gradients summed
     float* partial = reinterpret_cast<float*>(wsp + l.partial);
+    stf::SlotRanges ranges;
+    ranges.ntex = ntex;
     int slot0 = 0;
     for (int i = 0; i < ntex; ++i) {
         stf::DecBwdArgs d;
@@ -545,6 +554,18 @@ int stf_backward_decoder(const stf_texture* tex, int32_t ntex, const stf_screen*
         d.nblocks = (int)(((int64_t)d.tw * d.th + stf::kDbN - 1) / stf::kDbN);
         for (int c = 0; c < 8; ++c) d.scale[c] = tex[i].scale != nullptr ? tex[i].scale[c] : 1.0f;
         d.g = reinterpret_cast<const float*>(wsp + l.g[i]);
+        uint32_t* mask = reinterpret_cast<uint32_t*>(wsp + l.g[i] + (size_t)d.tw * d.th * 16);
+        int32_t* list = reinterpret_cast<int32_t*>(wsp + l.list[i]);
+        int32_t* count = reinterpret_cast<int32_t*>(wsp + l.count[i]);
+        hipLaunchKernelGGL(stf::decoder_block_mask_kernel, dim3((unsigned)((d.nblocks + 7) / 8)), dim3(256), 0, s, d.g,
+                           (int64_t)d.tw * d.th, d.nblocks, mask);
+        hipLaunchKernelGGL(stf::decoder_block_list_kernel, dim3(1), dim3(stf::kListThreads), 0, s,
+                           static_cast<const uint32_t*>(mask), d.nblocks, list, count);
+        d.list = list;
+        d.count = count;
+        ranges.off[i] = slot0;
+        ranges.waves[i] = l.waves[i];
+        ranges.count[i] = count;
         d.w1 = mlp->w1;
         d.b1 = mlp->b1;
         d.w2 = mlp->w2;
@@ -559,7 +580,7 @@ int stf_backward_decoder(const stf_texture* tex, int32_t ntex, const stf_screen*
     for (int i = 0; i < 6; ++i) o.p[i] = gs[i];
     float* level2 = reinterpret_cast<float*>(wsp + l.level2);
     hipLaunchKernelGGL(stf::decoder_grad_partial_kernel, dim3((stf::kGradFloats + 255) / 256, stf::kReduceSplits),
-                       dim3(256), 0, s, static_cast<const float*>(partial), l.total_waves, level2);
+                       dim3(256), 0, s, static_cast<const float*>(partial), ranges, level2);
     hipLaunchKernelGGL(stf::decoder_grad_reduce_kernel, dim3((stf::kGradFloats + 255) / 256), dim3(256), 0, s,
                        static_cast<const float*>(level2), o);
     return finish_launch("decoder backward");

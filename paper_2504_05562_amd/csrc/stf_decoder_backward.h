@@ -15,10 +15,13 @@
 // training). One wavefront takes kDbN consecutive texels of the grid at a
 // time: their activations live in LDS with the texels as columns, and every
 // product above -- the per-texel layers as well as the weight gradients,
-// which contract over the texels -- runs on v_mfma_f32_16x16x4_f32. A wave's
-// weight gradients accumulate in registers over its blocks of texels and are
-// written once to a per-wave slot; a second kernel sums the slots in a fixed
-// order, so the result does not depend on scheduling.
+// which contract over the texels -- runs on v_mfma_f32_16x16x4_f32. Only
+// blocks that some gradient reaches are visited: a view covers a small part
+// of the grid, so the blocks with g != 0 are first listed in increasing
+// order and dealt out round-robin, which gives every wave the same number of
+// blocks to within one. A wave's weight gradients accumulate in registers
+// over its blocks and are written once to a per-wave slot; a last kernel sums
+// the slots in a fixed order, so the result does not depend on scheduling.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -33,12 +36,15 @@ constexpr int kDbLd = kDbN + 1;                    // LDS row stride (floats) of
 constexpr int kGradW1 = 0, kGradB1 = kGradW1 + 64 * 8, kGradW2 = kGradB1 + 64, kGradB2 = kGradW2 + 64 * 64,
               kGradW3 = kGradB2 + 64, kGradB3 = kGradW3 + 4 * 64, kGradFloats = kGradB3 + 4;   // 4996
 constexpr int kDecBwdMaxWaves = 2048;
+constexpr int kListThreads = 1024;                 // the one workgroup that lists the active blocks
 
 struct DecBwdArgs {
     const uint8_t* data;     // latent grid, row pitch `pitch`
     int64_t pitch;
     int32_t tw, th, fmt;
     int32_t nblocks;         // ceil(tw * th / kDbN)
+    const int32_t* list;     // indices of the blocks with some g != 0, increasing
+    const int32_t* count;    // their number
     float scale[8];          // latent = stored * scale
     const float* g;          // dL/d(decoded texel), [th * tw][4]
     const float* w1;         // [64][8]
@@ -115,8 +121,57 @@ __device__ __forceinline__ void tiles_out(const v4f (&acc)[MT * NT], F f) {
             for (int v = 0; v < 4; ++v) f(16 * i + 4 * q + v, 16 * j + r, acc[i * NT + j][v]);
 }
 
-// One wavefront per workgroup; wave w takes the blocks of kDbN texels
-// w, w + gridDim.x, ... Blocks of 32 texels keep the LDS arrays at 18.5 KB
+// Marks the blocks of kDbN texels that some gradient reaches: one bit per
+// block in `mask` (cleared beforehand). Each half wave reads one block's g
+// (16 bytes per texel); a wave's two blocks share a mask word, set with one
+// atomic OR. Grid: ceil(nblocks / 8) workgroups of 256.
+__global__ __launch_bounds__(256) void decoder_block_mask_kernel(const float* g, int64_t ntex, int nblocks,
+                                                                 uint32_t* mask) {
+    static_assert(kDbN == 32, "one block per half wave");
+    const int lane = threadIdx.x & 63;
+    const int blk0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 2;     // even: both blocks in one word
+    const int blk = blk0 + (lane >> 5);
+    const int64_t t = (int64_t)blk * kDbN + (lane & 31);
+    bool any = false;
+    if (blk < nblocks && t < ntex) {
+        const float4 v = reinterpret_cast<const float4*>(g)[t];
+        any = v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f;
+    }
+    const uint64_t m = __builtin_amdgcn_ballot_w64(any);
+    const uint32_t bits = ((uint32_t)m != 0u ? 1u : 0u) | ((m >> 32) != 0u ? 2u : 0u);
+    if (lane == 0 && bits != 0u) atomicOr(&mask[blk0 >> 5], bits << (blk0 & 31));
+}
+
+// Indices of the marked blocks in increasing order, and their number: one
+// workgroup of kListThreads. Thread i takes the i-th contiguous run of mask
+// words (one word per thread up to 32 768 blocks), the runs' bit counts are
+// scanned in LDS, then every thread writes its run's indices at its offset.
+__global__ __launch_bounds__(kListThreads) void decoder_block_list_kernel(const uint32_t* mask, int nblocks,
+                                                                          int32_t* list, int32_t* count) {
+    __shared__ int32_t scan[kListThreads];
+    const int i = threadIdx.x;
+    const int nwords = (nblocks + 31) / 32;
+    const int run = (nwords + kListThreads - 1) / kListThreads;
+    const int lo = min(i * run, nwords), hi = min(lo + run, nwords);
+    int n = 0;
+#pragma unroll 4
+    for (int j = lo; j < hi; ++j) n += __builtin_popcount(mask[j]);
+    scan[i] = n;
+    __syncthreads();
+    for (int d = 1; d < kListThreads; d <<= 1) {      // inclusive scan (Hillis-Steele)
+        const int v = i >= d ? scan[i - d] : 0;
+        __syncthreads();
+        scan[i] += v;
+        __syncthreads();
+    }
+    int o = scan[i] - n;
+    for (int j = lo; j < hi; ++j)
+        for (uint32_t m = mask[j]; m != 0u; m &= m - 1u) list[o++] = j * 32 + __builtin_ctz(m);
+    if (i == kListThreads - 1) *count = scan[i];
+}
+
+// One wavefront per workgroup; wave w takes the listed blocks w,
+// w + gridDim.x, ... Blocks of 32 texels keep the LDS arrays at 18.5 KB
 // and the transient accumulators at 8 tiles, so that two waves fit a SIMD.
 __global__ __launch_bounds__(64, 2) void decoder_backward_kernel(DecBwdArgs a) {
     __shared__ float H1[64 * kDbLd];   // h1, then d1; [unit][texel]
@@ -131,14 +186,15 @@ __global__ __launch_bounds__(64, 2) void decoder_backward_kernel(DecBwdArgs a) {
     zero_tiles(dw3);
     float db1 = 0.0f, db2 = 0.0f, db3 = 0.0f;      // unit `lane` (db3: lanes 0-3)
     const int64_t ntex = (int64_t)a.tw * a.th;
+    const int nlisted = *a.count;
+    if ((int)blockIdx.x >= nlisted) return;          // no block for this wave: its slot is not read
 #pragma unroll 1
-    for (int blk = blockIdx.x; blk < a.nblocks; blk += gridDim.x) {
+    for (int k = blockIdx.x; k < nlisted; k += gridDim.x) {
+        const int blk = a.list[k];
         const int64_t t = (int64_t)blk * kDbN + lane;
         const bool in = lane < kDbN && t < ntex;
         float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (in) g = reinterpret_cast<const float4*>(a.g)[t];
-        const bool any = g.x != 0.0f || g.y != 0.0f || g.z != 0.0f || g.w != 0.0f;
-        if (__builtin_amdgcn_ballot_w64(any) == 0) continue;          // no gradient reaches these texels
         float x[8];
         if (in) {
             load_latent(a, t, x);
@@ -239,14 +295,25 @@ struct MlpGradPtrs {
 
 // The per-wave slots are summed in two fixed-order steps, so that many
 // threads share the reads: kReduceSplits partial sums per gradient element
-// (slots split + k * kReduceSplits), then their sum added to the outputs.
+// (slots split + k * kReduceSplits of each texture), then their sum added to
+// the outputs. Texture i's slots start at slot off[i]; only its first
+// min(waves[i], *count[i]) waves had blocks and wrote their slots.
 constexpr int kReduceSplits = 64;
 
-__global__ __launch_bounds__(256) void decoder_grad_partial_kernel(const float* partial, int nslots, float* level2) {
+struct SlotRanges {
+    int32_t ntex;
+    int32_t off[STF_MAX_TEXTURES], waves[STF_MAX_TEXTURES];
+    const int32_t* count[STF_MAX_TEXTURES];
+};
+
+__global__ __launch_bounds__(256) void decoder_grad_partial_kernel(const float* partial, SlotRanges r, float* level2) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= kGradFloats) return;
     float s = 0.0f;
-    for (int w = blockIdx.y; w < nslots; w += kReduceSplits) s += partial[(size_t)w * kGradFloats + e];
+    for (int i = 0; i < r.ntex; ++i) {
+        const int n = min(r.waves[i], *r.count[i]);
+        for (int w = blockIdx.y; w < n; w += kReduceSplits) s += partial[(size_t)(r.off[i] + w) * kGradFloats + e];
+    }
     level2[(size_t)blockIdx.y * kGradFloats + e] = s;
 }
 

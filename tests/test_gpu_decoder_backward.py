@@ -7,7 +7,7 @@ decoder with the error bound the texel-adjoint tests use, 1e-5 of
 G_x = sum_c sum_i a_ci |dL/dout_c| (the adjoint of |dL/dout|; the a_ci are
 non-negative). Then every product runs in FP32 with exact products and
 sequential FP32 sums of K terms (error gamma(K) of the sum of absolute
-terms): K = 4, 64, 64 for d2, d1 and dL/dl, and 64 texels per block, the
+terms): K = 4, 64, 64 for d2, d1 and dL/dl, and 32 texels per block, the
 blocks of a wave and the waves for the weight gradients. So each output is
 compared with REL_CHAIN (plus gamma of the summation depth for the weight
 gradients) times its magnitude: the same backward pass run on |W|, G_x and
@@ -78,7 +78,8 @@ def magnitudes(lat, layers, G):
 
 CASES = [("bicubic", "tile8x8", "f16", 32), ("bicubic", "quad2x2", "fp8", 32), ("bilinear", "square3x3", "bf16", 32),
          ("bicubic", "self", "f16", 32), ("bilinear", "tile8x8", "fp8", 32),
-         ("bicubic", "tile8x8", "f16", 4)]        # 16 texels: one partial block of the decoder adjoint
+         ("bicubic", "tile8x8", "f16", 4),        # 16 texels: one partial block of the decoder adjoint
+         ("bicubic", "tile8x8", "bf16", 256)]     # 2048 blocks, a few dozen reached: a sparse block list
 
 
 @pytest.mark.parametrize("filt,fp,kind,size", CASES)
@@ -131,6 +132,22 @@ def test_decoder_adjoint_matches_oracle(filt, fp, kind, size):
             gg = dl[li][which].cpu().numpy().astype(np.float64)
             e = np.abs(gg - want[li][which])
             assert np.all(e <= tol), f"layer {li} {'bW'[which]}: worst {np.max(e / tol):.3g}x the bound"
+
+
+def test_zero_gradient_visits_no_block():
+    # no block is listed: the latent and weight gradients stay as they were
+    layers32 = w.mlp_weights(3)
+    dlayers_t = [(dev(a), dev(b)) for a, b in layers32]
+    dec = stf.pack_decoder(dlayers_t)
+    tex = dev(w.latent_grid(1, 64).astype(np.float16))
+    uv = dev(w.small_screen(40, 24, 64, 2.0, offset_seed=2))
+    dl = torch.full((64, 64, 8), 0.25, device="cuda")
+    dly = [(torch.full_like(a, 0.5), torch.full_like(b, -0.5)) for a, b in dlayers_t]
+    stf.backward_decoder([tex], uv, [torch.zeros((24, 40, 4), device="cuda")], dlayers_t, dec, "tile8x8", "bicubic",
+                         1, 0, dlatent=[dl], dlayers=dly)
+    torch.cuda.synchronize()
+    assert bool((dl == 0.25).all())
+    assert all(bool((a == 0.5).all()) and bool((b == -0.5).all()) for a, b in dly)
 
 
 def stf_waves(size):
