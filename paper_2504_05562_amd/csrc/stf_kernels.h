@@ -48,12 +48,16 @@ enum Mode { kModeStf = 0, kModeQuad = 1, kModeRecords = 2, kModeBins = 3 };
 // 64-bit fixed-point accumulators, or records (64 x {s, r} + 64 x 16 B).
 constexpr int kAccFloatOffset = kBinRecords * 5;
 constexpr int kLdsFloatsPerWave = kAccFloatOffset + kBinRecords * 2;
-// backward bins: Nb float [kBins], then (8-byte aligned) u64 [kBins], then
-// (16-byte aligned) one 16-float record per tile pixel for the matrix cores
-constexpr int kBwdN64Offset = (kBins + 1) & ~1;
-constexpr int kBwdRecOffset = (kBwdN64Offset + kBins * 2 + 3) & ~3;
-constexpr int kBwdLdsFloatsPerWave = kBwdRecOffset + 64 * 16;
-static_assert(kBwdRecOffset % 4 == 0 && kLdsFloatsPerWave % 4 == 0, "16-byte aligned LDS records");
+// backward bins: Nb float [kBins], then (16-byte aligned) u64 [kBins]; once
+// the sums are converted, the same place holds one row record per tile pixel
+// for the matrix cores: its weights along the window's rows and columns, zero
+// outside its support (kBinG each), and its four scaled gradients.
+constexpr int kBwdN64Offset = (kBins + 3) & ~3;
+constexpr int kBwdRowFloats = 2 * kBinG + 4;
+constexpr int kBwdLdsFloatsPerWave =
+    kBwdN64Offset + (kBins * 2 > 64 * kBwdRowFloats ? kBins * 2 : 64 * kBwdRowFloats);
+static_assert(kBwdN64Offset % 4 == 0 && kBwdRowFloats % 4 == 0 && kLdsFloatsPerWave % 4 == 0,
+              "16-byte aligned LDS records");
 
 struct Pixel {
     int px, py;          // screen pixel
@@ -1263,48 +1267,41 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                     // cores: window rows x window columns (12 x 12 in a 16 x 16 tile),
                     // K = the 64 pixels, four per v_mfma_f32_16x16x4_f32 (A[i][k] and
                     // B[k][j] of lane l: i = j = l % 16, k = l / 16). Each pixel first
-                    // publishes its support start, weights and q in LDS.
-                    float* rec = lds + kBwdRecOffset;               // [64][16]
+                    // publishes its row record (over the converted 64-bit sums): its
+                    // weight at every window row and column, zero outside its support
+                    // (off-screen pixels: all zero), then q. Lanes of tile rows and
+                    // columns 12-15 read the next entries; those outputs are never used.
+                    float* rows = lds + kBwdN64Offset;              // [64][kBwdRowFloats]
                     {
+                        float* own = rows + P.q * kBwdRowFloats;
                         const float inv = P.valid ? fast_rcp(B) : 0.0f;
-                        float rr[16];
-                        rr[0] = __uint_as_float(P.valid ? (rx | (ry << 8)) : 0xFFFFu);   // off-screen: no support
+                        float4* o4 = reinterpret_cast<float4*>(own);
 #pragma unroll
-                        for (int b = 0; b < N; ++b) rr[1 + b] = ctx.y.w(b);
+                        for (int k = 0; k < 2 * kBinG / 4; ++k) o4[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                        if (P.valid) {
 #pragma unroll
-                        for (int b = 0; b < N; ++b) rr[1 + N + b] = ctx.x.w(b);
+                            for (int b = 0; b < N; ++b) own[ry + b] = ctx.y.w(b);
 #pragma unroll
-                        for (int c = 0; c < C; ++c) rr[1 + 2 * N + c] = g[c] * inv;
+                            for (int b = 0; b < N; ++b) own[kBinG + rx + b] = ctx.x.w(b);
+                        }
+                        float qv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                        for (int k = 1 + 2 * N + C; k < 16; ++k) rr[k] = 0.0f;
-#pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            reinterpret_cast<float4*>(rec)[P.q * 4 + k] =
-                                make_float4(rr[4 * k], rr[4 * k + 1], rr[4 * k + 2], rr[4 * k + 3]);
+                        for (int c = 0; c < C; ++c) qv[c] = g[c] * inv;
+                        o4[2 * kBinG / 4] = make_float4(qv[0], qv[1], qv[2], qv[3]);
                     }
                     wave_lds_sync();
 #pragma unroll
                     for (int c = 0; c < C; ++c) acc[c] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 1
+#pragma unroll 2
                     for (int m = 0; m < 16; ++m) {
-                        const float4* rp = reinterpret_cast<const float4*>(rec) + (4 * m + kp) * 4;
-                        float rr[16];
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const float4 v = rp[k];
-                            rr[4 * k] = v.x; rr[4 * k + 1] = v.y; rr[4 * k + 2] = v.z; rr[4 * k + 3] = v.w;
-                        }
-                        const uint32_t st = __float_as_uint(rr[0]);
-                        const int dy = ij - (int)(st >> 8), dx = ij - (int)(st & 0xFFu);
-                        float wa = 0.0f, wb = 0.0f;
-#pragma unroll
-                        for (int b = 0; b < N; ++b) {
-                            wa = dy == b ? rr[1 + b] : wa;
-                            wb = dx == b ? rr[1 + N + b] : wb;
-                        }
+                        const float* rp = rows + (4 * m + kp) * kBwdRowFloats;
+                        const float wa = rp[ij];
+                        const float wb = rp[kBinG + ij];
+                        const float4 q = *reinterpret_cast<const float4*>(rp + 2 * kBinG);
+                        const float qc[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
                         for (int c = 0; c < C; ++c)
-                            acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, wb * rr[1 + 2 * N + c], acc[c], 0, 0, 0);
+                            acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, wb * qc[c], acc[c], 0, 0, 0);
                     }
                 }
             }
@@ -1425,7 +1422,7 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
 // The whole-tile adjoint is budgeted for four waves per SIMD (128 VGPRs).
 template <int FILT, int MODE>
 __global__ __launch_bounds__(kThreads, (MODE == kModeBins ? 4 : 1)) void backward_kernel(Args a) {
-    constexpr int kPerWave = kBwdLdsFloatsPerWave > kLdsFloatsPerWave ? kBwdLdsFloatsPerWave : kLdsFloatsPerWave;
+    constexpr int kPerWave = MODE == kModeBins ? kBwdLdsFloatsPerWave : 128;   // bins, or 64 {s, r} records
     __shared__ __align__(16) float lds_all[kWavesPerGroup * kPerWave];
     constexpr bool kMerge = MODE == kModeBins;
     __shared__ __align__(16) float merge_v[kMerge ? kMergeW * kMergeH * 4 : 4];
