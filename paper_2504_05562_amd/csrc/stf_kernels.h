@@ -835,8 +835,63 @@ __device__ __forceinline__ void forward_tile(const Args& a, Pixel& P, float* lds
     }
 }
 
+// One-tap STF without a decoder exchanges nothing between lanes, so it does
+// not need 8x8 tiles: its waves take kOneTapPixels runs of 64 consecutive
+// pixels of one screen row, whose UV reads and output writes are contiguous
+// (whole cache lines, where an 8x8 tile writes 8-pixel row pieces: half lines
+// of RG32F). Each lane carries its pixels through the phases together --
+// every UV, then every pick and texel request, then every decode and store
+// -- so that a wave has that many times the loads of one pixel in flight.
+template <int MODE, bool DEC>
+constexpr bool kRowLinear = MODE == kModeStf && !DEC;
+constexpr int kOneTapPixels = 2;
+
+template <int FILT, int NT, int K>
+__device__ __forceinline__ void onetap_pixels(const Args& a, const Pixel (&P)[K]) {
+    TexArg t[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) t[i] = a.tex[i];
+    SlotPick pk[K][NT];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        SelCtx<FILT> ctx;
+        uint4 hq;
+        uint32_t hxs[NT], hys[NT];
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+            uint32_t hx, hy;
+            slot_uniforms(a, P[k], i, hq, hx, hy);
+            ctx.update(P[k], t[i].w, t[i].h);
+#pragma unroll
+            for (int j = 0; j < i; ++j) {            // shared selection, as in forward_tile
+                const bool lead = a.leader[i] == j;
+                hx = lead ? hxs[j] : hx;
+                hy = lead ? hys[j] : hy;
+            }
+            hxs[i] = hx;
+            hys[i] = hy;
+            pk[k][i] = pick_slot<FILT>(t[i], ctx, hx, hy);
+        }
+    }
+    SelCtx<FILT> unused;                             // one-tap passes read only the pick
+    BinGeom<AxisCtx<FILT>::N> geom;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+            switch (payload_of(t[i].fmt)) {
+            case kF16x4: slot_pass<FILT, kModeStf, kF16x4>(a, t[i], i, P[k], unused, geom, pk[k][i], nullptr); break;
+            case kF16x2: slot_pass<FILT, kModeStf, kF16x2>(a, t[i], i, P[k], unused, geom, pk[k][i], nullptr); break;
+            case kF32x1: slot_pass<FILT, kModeStf, kF32x1>(a, t[i], i, P[k], unused, geom, pk[k][i], nullptr); break;
+            case kLatent: break;                     // latents need the decoder kernels
+            default: slot_pass<FILT, kModeStf, kF32x4>(a, t[i], i, P[k], unused, geom, pk[k][i], nullptr); break;
+            }
+        }
+}
+
 // Workgroup (x, y) filters tile columns 4x .. 4x+3 (one per wave) over tile
-// rows kForwardRows<DEC> * y onward.
+// rows kForwardRows<DEC> * y onward; row-linear kernels: pixels
+// 256 K x .. 256 K (x + 1) - 1 of screen row y (K = kOneTapPixels).
 template <int FILT, int MODE, int NT, bool DEC, bool EF>
 __global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, NT, DEC, EF>)) void forward_kernel(Args a) {
     // per-wave LDS: records or bins; with a decoder also the deduplicating decode's scratch
@@ -847,6 +902,28 @@ __global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, NT, DEC, EF>)) void 
     if constexpr (DEC) {                       // before any wave of the group can leave
         stage_decoder(a.dec, dec);
         __syncthreads();
+    }
+    if constexpr (kRowLinear<MODE, DEC>) {
+        constexpr int K = kOneTapPixels;
+        const int x0 = (blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6)) * (64 * K);
+        if (x0 >= a.sw) return;                // whole wave off screen
+        Pixel P[K];
+        v2f uv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            P[k].px = x0 + 64 * k + lane_id();
+            P[k].py = blockIdx.y;
+            P[k].lx = P[k].ly = P[k].q = 0;    // no tile: nothing is exchanged
+            P[k].valid = P[k].px < a.sw;
+            uv[k] = load_uv(a, P[k].px, P[k].py);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            P[k].u = uv[k].x;
+            P[k].v = uv[k].y;
+        }
+        onetap_pixels<FILT, NT, K>(a, P);
+        return;
     }
     constexpr int kRows = kForwardRows<DEC>;
     const int tx = blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6);
@@ -1460,9 +1537,12 @@ inline dim3 grid_of(const Args& a) {
                 (unsigned)((a.sh + kTile - 1) / kTile));
 }
 
-// Forward kernels: kForwardRows<DEC> tile rows per workgroup.
-template <bool DEC>
+// Forward kernels: kForwardRows<DEC> tile rows per workgroup, or 256
+// kOneTapPixels pixels of one screen row.
+template <int MODE, bool DEC>
 inline dim3 grid_forward(const Args& a) {
+    if constexpr (kRowLinear<MODE, DEC>)
+        return dim3((unsigned)((a.sw + kThreads * kOneTapPixels - 1) / (kThreads * kOneTapPixels)), (unsigned)a.sh);
     const int rows = (a.sh + kTile - 1) / kTile;
     return dim3((unsigned)((a.sw + kTile * kWavesPerGroup - 1) / (kTile * kWavesPerGroup)),
                 (unsigned)((rows + kForwardRows<DEC> - 1) / kForwardRows<DEC>));
@@ -1470,7 +1550,7 @@ inline dim3 grid_forward(const Args& a) {
 
 template <int FILT, int MODE, bool DEC, bool EF>
 void launch_nt(const Args& a, hipStream_t s) {
-    const dim3 g = grid_forward<DEC>(a), b(kThreads);
+    const dim3 g = grid_forward<MODE, DEC>(a), b(kThreads);
     switch (a.ntex) {
     case 1: hipLaunchKernelGGL((forward_kernel<FILT, MODE, 1, DEC, EF>), g, b, 0, s, a); break;
     case 2: hipLaunchKernelGGL((forward_kernel<FILT, MODE, 2, DEC, EF>), g, b, 0, s, a); break;
