@@ -230,7 +230,8 @@ int stf_filter_reference(const stf_texture* tex, int32_t ntex, const stf_screen*
  *     dL/dT[x] += sum_c sum_{i in S(c), x_i = x} a_ci dL/dout_c.
  *   tex    descriptors of the forward textures (data may be NULL: only size
  *          and format are used)
- *   dout   host array of ntex device pointers, FP32 [H][W][C_t]
+ *   dout   host array of ntex device pointers, FP32 [H][W][C_t], each aligned to
+ *          4 * C_t bytes (one pixel's channels are read as one vector)
  *   dtex   host array of ntex device pointers, FP32 [tex height][tex width][C_t],
  *          dense (pitch = width * C_t * 4); ACCUMULATED into (+=), so clear
  *          it first for a plain gradient. Summation order is not fixed
@@ -316,7 +317,7 @@ int64_t stf_backward_decoder_workspace_bytes(const stf_texture* tex, int32_t nte
  *             all with the same packed decoder as in the forward call
  *   p, r      as the forward call being differentiated (plain Eq. (14):
  *             no exact filtering, clamping or comparison estimator)
- *   dout      host array of ntex device pointers, FP32 [H][W][4]
+ *   dout      host array of ntex device pointers, FP32 [H][W][4], 16-byte aligned
  *   mlp       the FP32 weights the decoder was packed from: the adjoint is
  *             that of the FP32 decoder, the forward pass's BF16/FP8 rounding
  *             of weights and activations taken as the identity

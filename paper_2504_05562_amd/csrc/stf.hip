@@ -383,8 +383,9 @@ int stf_backward(const stf_texture* tex, int32_t ntex, const stf_screen* scr, co
     if (dout == nullptr || dtex == nullptr) return fail(STF_EINVAL, "dout/dtex arrays are null");
     for (int i = 0; i < ntex; ++i) {
         if (dout[i] == nullptr || dtex[i] == nullptr) return fail(STF_EINVAL, "dout[%d]/dtex[%d] is null", i, i);
-        if ((reinterpret_cast<uintptr_t>(dout[i]) & 3) || (reinterpret_cast<uintptr_t>(dtex[i]) & 3))
-            return fail(STF_EINVAL, "dout[%d]/dtex[%d] not 4-byte aligned", i, i);
+        const uintptr_t va = (uintptr_t)(4 * a.tex[i].ch) - 1;     // dout is read one pixel vector at a time
+        if ((reinterpret_cast<uintptr_t>(dout[i]) & va) || (reinterpret_cast<uintptr_t>(dtex[i]) & 3))
+            return fail(STF_EINVAL, "dout[%d] not %d-byte or dtex[%d] not 4-byte aligned", i, 4 * a.tex[i].ch, i);
         a.out[i] = dtex[i];
         a.dout[i] = dout[i];
     }
@@ -501,8 +502,8 @@ int stf_backward_decoder(const stf_texture* tex, int32_t ntex, const stf_screen*
     if (dout == nullptr || dlatent == nullptr) return fail(STF_EINVAL, "dout/dlatent arrays are null");
     for (int i = 0; i < ntex; ++i) {
         if (dout[i] == nullptr || dlatent[i] == nullptr) return fail(STF_EINVAL, "dout[%d]/dlatent[%d] is null", i, i);
-        if ((reinterpret_cast<uintptr_t>(dout[i]) & 3) || (reinterpret_cast<uintptr_t>(dlatent[i]) & 3))
-            return fail(STF_EINVAL, "dout[%d]/dlatent[%d] not 4-byte aligned", i, i);
+        if ((reinterpret_cast<uintptr_t>(dout[i]) & 15) || (reinterpret_cast<uintptr_t>(dlatent[i]) & 3))
+            return fail(STF_EINVAL, "dout[%d] not 16-byte or dlatent[%d] not 4-byte aligned", i, i);
     }
     const DecBwdLayout l = dec_bwd_layout(tex, ntex);
     if (workspace == nullptr) return fail(STF_EINVAL, "workspace is null");

@@ -1261,7 +1261,8 @@ struct MergeArea {
 
 template <int FILT, int MODE, int C>
 __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
-                                              uint32_t hx, uint32_t hy, float* lds, MergeArea merge = {}) {
+                                              uint32_t hx, uint32_t hy, const float4& gin, float* lds,
+                                              MergeArea merge = {}) {
     constexpr int N = SelCtx<FILT>::N;
     const TexArg t = a.tex[slot];
     const int lane = lane_id();
@@ -1273,9 +1274,10 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
     const uint32_t s = sx | (sy << 16);
     float* grad = a.out[slot];                              // dL/dT, [th][tw][C]
     const int64_t pix = (int64_t)P.py * a.sw + P.px;
+    const float gv[4] = {gin.x, gin.y, gin.z, gin.w};
     float g[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) g[c] = P.valid ? a.dout[slot][pix * C + c] * t.scale[c] : 0.0f;
+    for (int c = 0; c < C; ++c) g[c] = gv[c] * t.scale[c];
 
     if constexpr (MODE == kModeStf) {
         if (P.valid) atomic_texel<C>(grad, t.w, s, g, 1.0f);
@@ -1496,6 +1498,25 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
     }
 }
 
+// dL/dout of this lane's pixel for one slot (channels beyond the slot's
+// count zero; off-screen pixels zero): one 4-, 8- or 16-byte load.
+__device__ __forceinline__ float4 load_dout(const Args& a, int slot, const Pixel& P) {
+    float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (!P.valid) return g;
+    const int64_t pix = (int64_t)P.py * a.sw + P.px;
+    const int ch = a.tex[slot].ch;
+    if (ch == 4) {
+        g = reinterpret_cast<const float4*>(a.dout[slot])[pix];
+    } else if (ch == 2) {
+        const float2 v = reinterpret_cast<const float2*>(a.dout[slot])[pix];
+        g.x = v.x;
+        g.y = v.y;
+    } else {
+        g.x = a.dout[slot][pix];
+    }
+    return g;
+}
+
 // The whole-tile adjoint is budgeted for four waves per SIMD (128 VGPRs).
 template <int FILT, int MODE>
 __global__ __launch_bounds__(kThreads, (MODE == kModeBins ? 4 : 1)) void backward_kernel(Args a) {
@@ -1518,14 +1539,19 @@ __global__ __launch_bounds__(kThreads, (MODE == kModeBins ? 4 : 1)) void backwar
     }
     float* lds = lds_all + (threadIdx.x >> 6) * kPerWave;
     SelCtx<FILT> ctx;
+    // dL/dout of the pixel, one vector load per slot, the next slot's
+    // requested before the current slot's work
+    float4 gcur = load_dout(a, 0, P), gnext = gcur;
     for (int slot = 0; slot < a.ntex; ++slot) {
+        if (slot + 1 < a.ntex) gnext = load_dout(a, slot + 1, P);
         uint32_t hx, hy;
         keyed_uniforms(a, P, slot, hx, hy);
         ctx.update(P, a.tex[slot].w, a.tex[slot].h);
         const int ch = a.tex[slot].ch;
-        if (ch == 4) backward_slot<FILT, MODE, 4>(a, slot, P, ctx, hx, hy, lds, merge);
-        else if (ch == 2) backward_slot<FILT, MODE, 2>(a, slot, P, ctx, hx, hy, lds, merge);
-        else backward_slot<FILT, MODE, 1>(a, slot, P, ctx, hx, hy, lds, merge);
+        if (ch == 4) backward_slot<FILT, MODE, 4>(a, slot, P, ctx, hx, hy, gcur, lds, merge);
+        else if (ch == 2) backward_slot<FILT, MODE, 2>(a, slot, P, ctx, hx, hy, gcur, lds, merge);
+        else backward_slot<FILT, MODE, 1>(a, slot, P, ctx, hx, hy, gcur, lds, merge);
+        gcur = gnext;
     }
 }
 

@@ -112,6 +112,24 @@ def test_validation_counts_and_nulls():
     assert b"lut" in lib.stf_last_error()
 
 
+def test_backward_gradient_alignment():
+    # dL/dout is read as one vector of the slot's channels per pixel: RGBA
+    # needs 16-byte alignment; the gradient texels need 4
+    lib = stf.library()
+    tex, scr, prm = _good()
+    plain = stf.Reuse(5, 0, None, 0, 0)
+    dtex = (ctypes.c_void_p * 1)(8192)
+    for bad in (4100, 4104, 4108):
+        dout = (ctypes.c_void_p * 1)(bad)
+        assert lib.stf_backward(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(plain), dout, dtex,
+                                None) == -1
+        assert b"16-byte" in lib.stf_last_error()
+    dout = (ctypes.c_void_p * 1)(4096)
+    odd = (ctypes.c_void_p * 1)(8194)
+    assert lib.stf_backward(tex, 1, ctypes.byref(scr), ctypes.byref(prm), ctypes.byref(plain), dout, odd, None) == -1
+    assert b"aligned" in lib.stf_last_error()
+
+
 def test_latent_and_decoder_validation():
     lib = stf.library()
     tex, scr, prm = _good()
