@@ -669,25 +669,39 @@ def main():
             stf.filter(texs, uv, "bicubic", seed=0, frame=0, out=outs)
 
     def timed(kind):
+        """Wall and device time of exactly args.steps launches, queued on the
+        stream one by one (eager) and as one HIP graph of the same launches
+        (captured after the warm-up, replayed once untimed, then timed)."""
         for i in range(args.warmup):
             run(kind, i)
         torch.cuda.synchronize()
         stream = torch.cuda.current_stream()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        gc.disable()                       # no collector pause while the launches are queued
-        t0 = time.perf_counter()
-        ev0.record(stream)
-        for i in range(args.steps):
-            run(kind, i)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        gc.enable()
-        return wall, ev0.elapsed_time(ev1) / 1e3
 
-    wall_r, gpu_r = timed("reuse")
-    wall_s, gpu_s = timed("stf")
+        def clocked(body):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            gc.disable()                   # no collector pause while the launches are queued
+            t0 = time.perf_counter()
+            ev0.record(stream)
+            body()
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            gc.enable()
+            return wall, ev0.elapsed_time(ev1) / 1e3
+
+        eager = clocked(lambda: [run(kind, i) for i in range(args.steps)])
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for i in range(args.steps):
+                run(kind, i)
+        graph.replay()
+        torch.cuda.synchronize()
+        replayed = clocked(graph.replay)
+        return replayed, eager
+
+    (wall_r, gpu_r), (wall_re, gpu_re) = timed("reuse")
+    (wall_s, gpu_s), (wall_se, gpu_se) = timed("stf")
 
     # distinct texels fetched per frame (from the selection the kernel reports)
     _, sel = stf.filter_reuse(texs, uv0, "tile8x8", "bicubic", seed=0, frame=0, sel=True)
@@ -742,6 +756,15 @@ def main():
             "avg_launch_us": round(launch_s * 1e6, 3),
             "frac_of_copy_probe": round(achieved / probe["gbs"], 4), "copy_probe_gbs": probe["gbs"],
             "valu_issue": valu_issue(launch_s),
+        },
+        "timing": "one HIP graph of the timed launches, replayed once after an untimed replay; "
+                  "eager_stream: the same launches queued one by one",
+        "eager_stream": {
+            "value": round(px * args.steps / wall_re / 1e6, 1), "unit": "Mpixel/s",
+            "ms_per_step": round(wall_re / args.steps * 1e3, 5),
+            "avg_launch_us": round(gpu_re / args.steps * 1e6, 3),
+            "stf_1sample_value": round(px * args.steps / wall_se / 1e6, 1),
+            "stf_1sample_avg_launch_us": round(gpu_se / args.steps * 1e6, 3),
         },
         "stf_1sample": {
             "value": round(px * args.steps / wall_s / 1e6, 1), "unit": "Mpixel/s",
