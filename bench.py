@@ -540,8 +540,11 @@ def latent_form(torch, stf, w, steps, warmup):
     px = H * W
 
     def row(t, decodes):
+        # the flops of `decodes` decodes per pixel over the launch time: the rate a
+        # per-pixel decoder would need; the kernels decode each distinct texel of a
+        # wave once, so they execute fewer (the latent profile counts them)
         return {"avg_launch_us": round(t * 1e6, 2), "Mpixel_s": round(px / t / 1e6, 1),
-                "decode_tflops": round(px * decodes * DECODE_FLOPS_PER_TEXEL / t / 1e12, 1)}
+                "decode_equivalent_tflops": round(px * decodes * DECODE_FLOPS_PER_TEXEL / t / 1e12, 1)}
 
     t_r8 = launch_time(torch, lambda: stf.filter_reuse(tex, uv, "tile8x8", "bicubic", 0, 0, out=[out], scales=scales,
                                                        decoder=dec8), steps, warmup, batches=5)
