@@ -48,16 +48,17 @@ enum Mode { kModeStf = 0, kModeQuad = 1, kModeRecords = 2, kModeBins = 3 };
 // 64-bit fixed-point accumulators, or records (64 x {s, r} + 64 x 16 B).
 constexpr int kAccFloatOffset = kBinRecords * 5;
 constexpr int kLdsFloatsPerWave = kAccFloatOffset + kBinRecords * 2;
-// backward bins: Nb float [kBins], then (16-byte aligned) u64 [kBins]; once
-// the sums are converted, the same place holds one row record per tile pixel
-// for the matrix cores: its weights along the window's rows and columns, zero
-// outside its support (kBinG each), and its four scaled gradients.
-constexpr int kBwdN64Offset = (kBins + 3) & ~3;
+// backward bins, per wave: Nb float [kBins] (the sums of 1/p), and a wide
+// area that first holds their exact u64 accumulators and, once they are
+// converted, one row record per tile pixel for the matrix cores: its weights
+// along the window's rows and columns, zero outside its support (kBinG
+// each), and its four scaled gradients. The workgroup's wide areas are
+// contiguous; after the products they hold the workgroup's merge area.
+constexpr int kBwdNbFloats = (kBins + 3) & ~3;
 constexpr int kBwdRowFloats = 2 * kBinG + 4;
-constexpr int kBwdLdsFloatsPerWave =
-    kBwdN64Offset + (kBins * 2 > 64 * kBwdRowFloats ? kBins * 2 : 64 * kBwdRowFloats);
-static_assert(kBwdN64Offset % 4 == 0 && kBwdRowFloats % 4 == 0 && kLdsFloatsPerWave % 4 == 0,
-              "16-byte aligned LDS records");
+constexpr int kBwdWideFloats = kBins * 2 > 64 * kBwdRowFloats ? kBins * 2 : 64 * kBwdRowFloats;
+static_assert(kBwdNbFloats % 4 == 0 && kBwdRowFloats % 4 == 0 && kBwdWideFloats % 4 == 0 &&
+              kLdsFloatsPerWave % 4 == 0, "16-byte aligned LDS records");
 
 struct Pixel {
     int px, py;          // screen pixel
@@ -1255,8 +1256,9 @@ __device__ __forceinline__ void atomic_texel(float* g, int tw, uint32_t s, const
 constexpr int kMergeW = 32, kMergeH = 16;
 
 struct MergeArea {
-    float* v;                // [kMergeH * kMergeW][C] sums
+    float* v;                // [kMergeH * kMergeW][C] sums (over the workgroup's wide areas)
     int* info;               // per wave: ok, base_x, base_y
+    float* wide;             // this wave's wide area (kBwdWideFloats)
 };
 
 template <int FILT, int MODE, int C>
@@ -1318,7 +1320,7 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                 if (use_bins) {
                     // LDS: Nb float [kBins] (sum of 1/p per texel), N64 u64 [kBins]
                     // (its exact integer accumulator, as in the forward pass)
-                    uint64_t* N64 = reinterpret_cast<uint64_t*>(lds + kBwdN64Offset);
+                    uint64_t* N64 = reinterpret_cast<uint64_t*>(merge.wide);
                     for (int i = lane; i < kBins; i += 64) N64[i] = 0ull;
                     for (int i = lane; i < kBins; i += 64) Nb[i] = 0.0f;
                     const int my_bin = (int)(ry + ky) * kBinG + (int)(rx + kx);
@@ -1350,7 +1352,7 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                     // weight at every window row and column, zero outside its support
                     // (off-screen pixels: all zero), then q. Lanes of tile rows and
                     // columns 12-15 read the next entries; those outputs are never used.
-                    float* rows = lds + kBwdN64Offset;              // [64][kBwdRowFloats]
+                    float* rows = merge.wide;                       // [64][kBwdRowFloats]
                     {
                         float* own = rows + P.q * kBwdRowFloats;
                         const float inv = P.valid ? fast_rcp(B) : 0.0f;
@@ -1440,6 +1442,7 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                 const bool merged = ref >= 0 && hi_x - lo_x + kBinG <= kMergeW && hi_y - lo_y + kBinG <= kMergeH;
                 if (merged) {
                     const int ux = merge.info[ref * 4 + 1] + lo_x, uy = merge.info[ref * 4 + 2] + lo_y;
+                    // every wave has passed the barrier above, so no row record is read any more
                     for (int e = threadIdx.x; e < kMergeW * kMergeH * C; e += kThreads) merge.v[e] = 0.0f;
                     __syncthreads();
                     if (contributes) {
@@ -1517,15 +1520,19 @@ __device__ __forceinline__ float4 load_dout(const Args& a, int slot, const Pixel
     return g;
 }
 
-// The whole-tile adjoint is budgeted for four waves per SIMD (128 VGPRs).
+// The whole-tile adjoint is budgeted for kBwdWaves waves per SIMD.
+constexpr int kBwdWaves = 5;
+
 template <int FILT, int MODE>
-__global__ __launch_bounds__(kThreads, (MODE == kModeBins ? 4 : 1)) void backward_kernel(Args a) {
-    constexpr int kPerWave = MODE == kModeBins ? kBwdLdsFloatsPerWave : 128;   // bins, or 64 {s, r} records
-    __shared__ __align__(16) float lds_all[kWavesPerGroup * kPerWave];
+__global__ __launch_bounds__(kThreads, (MODE == kModeBins ? kBwdWaves : 1)) void backward_kernel(Args a) {
     constexpr bool kMerge = MODE == kModeBins;
-    __shared__ __align__(16) float merge_v[kMerge ? kMergeW * kMergeH * 4 : 4];
+    constexpr int kPerWave = kMerge ? kBwdNbFloats : 128;       // bin sums, or 64 {s, r} records
+    static_assert(!kMerge || kMergeW * kMergeH * 4 <= kWavesPerGroup * kBwdWideFloats, "merge area fits");
+    __shared__ __align__(16) float lds_all[kWavesPerGroup * (kPerWave + (kMerge ? kBwdWideFloats : 0))];
     __shared__ int merge_info[kWavesPerGroup * 4];
-    const MergeArea merge{merge_v, merge_info};
+    float* wide_all = lds_all + kWavesPerGroup * kPerWave;
+    const MergeArea merge{kMerge ? wide_all : nullptr, merge_info,
+                          kMerge ? wide_all + (threadIdx.x >> 6) * kBwdWideFloats : nullptr};
     Pixel P;
     if constexpr (kMerge) {
         // the whole-tile adjoint merges per workgroup behind barriers: a wave whose
