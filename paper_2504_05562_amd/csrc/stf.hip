@@ -426,8 +426,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct DecBwdLayout {
     size_t g[STF_MAX_TEXTURES];
     size_t list[STF_MAX_TEXTURES], count[STF_MAX_TEXTURES];   // the block mask follows g directly
-    int waves[STF_MAX_TEXTURES];
-    int total_waves = 0;
+    int groups[STF_MAX_TEXTURES];     // workgroups of the decoder kernel, one weight-gradient slot each
+    int total_groups = 0;
     size_t partial = 0, level2 = 0, total = 0;
 };
 
@@ -443,11 +443,12 @@ DecBwdLayout dec_bwd_layout(const stf_texture* tex, int32_t ntex) {
         off += align256((size_t)blocks * 4);
         l.count[i] = off;
         off += 256;
-        l.waves[i] = (int)std::min<int64_t>(blocks, stf::kDecBwdMaxWaves);
-        l.total_waves += l.waves[i];
+        const int64_t waves = std::min<int64_t>(blocks, stf::kDecBwdMaxWaves);
+        l.groups[i] = (int)((waves + stf::kDbWaves - 1) / stf::kDbWaves);
+        l.total_groups += l.groups[i];
     }
     l.partial = off;
-    l.level2 = off + align256((size_t)l.total_waves * stf::kGradFloats * 4);
+    l.level2 = off + align256((size_t)l.total_groups * stf::kGradFloats * 4);
     l.total = l.level2 + align256((size_t)stf::kReduceSplits * stf::kGradFloats * 4);
     return l;
 }
@@ -558,14 +559,14 @@ int stf_backward_decoder(const stf_texture* tex, int32_t ntex, const stf_screen*
         uint32_t* mask = reinterpret_cast<uint32_t*>(wsp + l.g[i] + (size_t)d.tw * d.th * 16);
         int32_t* list = reinterpret_cast<int32_t*>(wsp + l.list[i]);
         int32_t* count = reinterpret_cast<int32_t*>(wsp + l.count[i]);
-        hipLaunchKernelGGL(stf::decoder_block_mask_kernel, dim3((unsigned)((d.nblocks + 7) / 8)), dim3(256), 0, s, d.g,
+        hipLaunchKernelGGL(stf::decoder_block_mask_kernel, dim3((unsigned)((d.nblocks + 15) / 16)), dim3(256), 0, s, d.g,
                            (int64_t)d.tw * d.th, d.nblocks, mask);
         hipLaunchKernelGGL(stf::decoder_block_list_kernel, dim3(1), dim3(stf::kListThreads), 0, s,
                            static_cast<const uint32_t*>(mask), d.nblocks, list, count);
         d.list = list;
         d.count = count;
         ranges.off[i] = slot0;
-        ranges.waves[i] = l.waves[i];
+        ranges.groups[i] = l.groups[i];
         ranges.count[i] = count;
         d.w1 = mlp->w1;
         d.b1 = mlp->b1;
@@ -574,8 +575,8 @@ int stf_backward_decoder(const stf_texture* tex, int32_t ntex, const stf_screen*
         d.w3 = mlp->w3;
         d.dlat = dlatent[i];
         d.partial = partial + (size_t)slot0 * stf::kGradFloats;
-        hipLaunchKernelGGL(stf::decoder_backward_kernel, dim3((unsigned)l.waves[i]), dim3(64), 0, s, d);
-        slot0 += l.waves[i];
+        hipLaunchKernelGGL(stf::decoder_backward_kernel, dim3((unsigned)l.groups[i]), dim3(64 * stf::kDbWaves), 0, s, d);
+        slot0 += l.groups[i];
     }
     stf::MlpGradPtrs o;
     for (int i = 0; i < 6; ++i) o.p[i] = gs[i];

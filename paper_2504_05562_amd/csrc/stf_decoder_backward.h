@@ -15,13 +15,15 @@
 // training). One wavefront takes kDbN consecutive texels of the grid at a
 // time: their activations live in LDS with the texels as columns, and every
 // product above -- the per-texel layers as well as the weight gradients,
-// which contract over the texels -- runs on v_mfma_f32_16x16x4_f32. Only
-// blocks that some gradient reaches are visited: a view covers a small part
-// of the grid, so the blocks with g != 0 are first listed in increasing
-// order and dealt out round-robin, which gives every wave the same number of
-// blocks to within one. A wave's weight gradients accumulate in registers
-// over its blocks and are written once to a per-wave slot; a last kernel sums
-// the slots in a fixed order, so the result does not depend on scheduling.
+// which contract over the texels -- runs on v_mfma_f32_16x16x4_f32, with the
+// weights read from one LDS copy per workgroup. Only blocks that some
+// gradient reaches are visited: a view covers a small part of the grid, so
+// the blocks with g != 0 are first listed in increasing order and dealt out
+// round-robin, which gives every wave the same number of blocks to within
+// one. A wave's weight gradients accumulate in registers over its blocks;
+// the waves of a workgroup add them into one slot in wave order, and the
+// last kernels sum the slots in a fixed order, so the result does not
+// depend on scheduling.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,11 +33,12 @@
 
 namespace stf {
 
-constexpr int kDbN = 32;                           // texels per block (the columns of the products)
+constexpr int kDbN = 16;                           // texels per block (the columns of the products)
 constexpr int kDbLd = kDbN + 1;                    // LDS row stride (floats) of the [unit][texel] arrays
+constexpr int kDbWaves = 4;                        // waves per workgroup, sharing one LDS copy of the weights
 constexpr int kGradW1 = 0, kGradB1 = kGradW1 + 64 * 8, kGradW2 = kGradB1 + 64, kGradB2 = kGradW2 + 64 * 64,
               kGradW3 = kGradB2 + 64, kGradB3 = kGradW3 + 4 * 64, kGradFloats = kGradB3 + 4;   // 4996
-constexpr int kDecBwdMaxWaves = 2048;
+constexpr int kDecBwdMaxWaves = 2048;                       // per texture, in workgroups of kDbWaves
 constexpr int kListThreads = 1024;                 // the one workgroup that lists the active blocks
 
 struct DecBwdArgs {
@@ -122,23 +125,25 @@ __device__ __forceinline__ void tiles_out(const v4f (&acc)[MT * NT], F f) {
 }
 
 // Marks the blocks of kDbN texels that some gradient reaches: one bit per
-// block in `mask` (cleared beforehand). Each half wave reads one block's g
-// (16 bytes per texel); a wave's two blocks share a mask word, set with one
-// atomic OR. Grid: ceil(nblocks / 8) workgroups of 256.
+// block in `mask` (cleared beforehand). Each quarter wave reads one block's
+// g (16 bytes per texel); a wave's four blocks share a mask word, set with
+// one atomic OR. Grid: ceil(nblocks / 16) workgroups of 256.
 __global__ __launch_bounds__(256) void decoder_block_mask_kernel(const float* g, int64_t ntex, int nblocks,
                                                                  uint32_t* mask) {
-    static_assert(kDbN == 32, "one block per half wave");
+    static_assert(kDbN == 16, "one block per quarter wave");
     const int lane = threadIdx.x & 63;
-    const int blk0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 2;     // even: both blocks in one word
-    const int blk = blk0 + (lane >> 5);
-    const int64_t t = (int64_t)blk * kDbN + (lane & 31);
+    const int blk0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;     // a multiple of 4: one mask word
+    const int blk = blk0 + (lane >> 4);
+    const int64_t t = (int64_t)blk * kDbN + (lane & 15);
     bool any = false;
     if (blk < nblocks && t < ntex) {
         const float4 v = reinterpret_cast<const float4*>(g)[t];
         any = v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f;
     }
     const uint64_t m = __builtin_amdgcn_ballot_w64(any);
-    const uint32_t bits = ((uint32_t)m != 0u ? 1u : 0u) | ((m >> 32) != 0u ? 2u : 0u);
+    uint32_t bits = 0u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bits |= ((m >> (16 * q)) & 0xFFFFull) != 0ull ? 1u << q : 0u;
     if (lane == 0 && bits != 0u) atomicOr(&mask[blk0 >> 5], bits << (blk0 & 31));
 }
 
@@ -170,15 +175,40 @@ __global__ __launch_bounds__(kListThreads) void decoder_block_list_kernel(const 
     if (i == kListThreads - 1) *count = scan[i];
 }
 
-// One wavefront per workgroup; wave w takes the listed blocks w,
-// w + gridDim.x, ... Blocks of 32 texels keep the LDS arrays at 18.5 KB
-// and the transient accumulators at 8 tiles, so that two waves fit a SIMD.
-__global__ __launch_bounds__(64, 2) void decoder_backward_kernel(DecBwdArgs a) {
-    __shared__ float H1[64 * kDbLd];   // h1, then d1; [unit][texel]
-    __shared__ float H2[64 * kDbLd];   // h2, then d2
-    __shared__ float GT[4 * kDbLd];    // g
-    __shared__ float XT[8 * kDbLd];    // latents
-    const int lane = threadIdx.x;
+// Workgroups of kDbWaves waves; wave w of the launch (workgroup-major) takes
+// the listed blocks w, w + kDbWaves * gridDim.x, ... The workgroup stages the
+// decoder's FP32 weights in LDS once (the operands of every per-texel
+// product), and each wave keeps its block's activations there with the
+// texels as columns. A wave's weight gradients accumulate in registers over
+// its blocks; at the end the waves add them into one slot per workgroup, in
+// wave order, through LDS.
+constexpr int kW1Ld = 9, kW2Ld = 65, kW3Ld = 65;   // padded LDS rows of the weights
+constexpr int kDbWeightFloats = 64 * kW1Ld + 64 * kW2Ld + 4 * kW3Ld + 64 + 64;
+constexpr int kDbWaveFloats = 2 * 64 * kDbLd + 4 * kDbLd + 8 * kDbLd;    // H1, H2, GT, XT
+static_assert(kDbWaves * kDbWaveFloats + kDbWeightFloats >= kGradFloats, "the slot sum fits the LDS");
+
+__global__ __launch_bounds__(64 * kDbWaves, 2) void decoder_backward_kernel(DecBwdArgs a) {
+    __shared__ float lds[kDbWeightFloats + kDbWaves * kDbWaveFloats];
+    float* W1s = lds;                                  // [64][kW1Ld]   W1 (64 x 8)
+    float* W2s = W1s + 64 * kW1Ld;                     // [64][kW2Ld]   W2 (64 x 64)
+    float* W3s = W2s + 64 * kW2Ld;                     // [4][kW3Ld]    W3 (4 x 64)
+    float* B1s = W3s + 4 * kW3Ld;                      // [64]
+    float* B2s = B1s + 64;                             // [64]
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float* H1 = lds + kDbWeightFloats + wave * kDbWaveFloats;   // h1, then d1; [unit][texel]
+    float* H2 = H1 + 64 * kDbLd;                                 // h2, then d2
+    float* GT = H2 + 64 * kDbLd;                                 // g
+    float* XT = GT + 4 * kDbLd;                                  // latents
+    const int nlisted = *a.count;
+    if ((int)blockIdx.x * kDbWaves >= nlisted) return;          // no block for the workgroup: no slot
+    for (int i = threadIdx.x; i < 64 * 64; i += 64 * kDbWaves) W2s[(i >> 6) * kW2Ld + (i & 63)] = a.w2[i];
+    for (int i = threadIdx.x; i < 64 * 8; i += 64 * kDbWaves) W1s[(i >> 3) * kW1Ld + (i & 7)] = a.w1[i];
+    for (int i = threadIdx.x; i < 4 * 64; i += 64 * kDbWaves) W3s[(i >> 6) * kW3Ld + (i & 63)] = a.w3[i];
+    if (threadIdx.x < 64) {
+        B1s[threadIdx.x] = a.b1[threadIdx.x];
+        B2s[threadIdx.x] = a.b2[threadIdx.x];
+    }
+    __syncthreads();
     constexpr int NT = kDbN / 16;      // column tiles of the per-texel products
     v4f dw2[16], dw1[4], dw3[4];
     zero_tiles(dw2);
@@ -186,10 +216,9 @@ __global__ __launch_bounds__(64, 2) void decoder_backward_kernel(DecBwdArgs a) {
     zero_tiles(dw3);
     float db1 = 0.0f, db2 = 0.0f, db3 = 0.0f;      // unit `lane` (db3: lanes 0-3)
     const int64_t ntex = (int64_t)a.tw * a.th;
-    const int nlisted = *a.count;
-    if ((int)blockIdx.x >= nlisted) return;          // no block for this wave: its slot is not read
+    const int stride = (int)gridDim.x * kDbWaves;
 #pragma unroll 1
-    for (int k = blockIdx.x; k < nlisted; k += gridDim.x) {
+    for (int k = (int)blockIdx.x * kDbWaves + wave; k < nlisted; k += stride) {
         const int blk = a.list[k];
         const int64_t t = (int64_t)blk * kDbN + lane;
         const bool in = lane < kDbN && t < ntex;
@@ -214,17 +243,17 @@ __global__ __launch_bounds__(64, 2) void decoder_backward_kernel(DecBwdArgs a) {
         {   // h1 = ReLU(W1 l + b1)
             v4f acc[4 * NT];
             zero_tiles(acc);
-            mfma_tiles<4, NT>(acc, [&](int m, int k) { return a.w1[m * 8 + k]; },
+            mfma_tiles<4, NT>(acc, [&](int m, int k) { return W1s[m * kW1Ld + k]; },
                               [&](int k, int n) { return XT[k * kDbLd + n]; }, 8);
-            tiles_out<4, NT>(acc, [&](int m, int n, float v) { H1[m * kDbLd + n] = fmaxf(v + a.b1[m], 0.0f); });
+            tiles_out<4, NT>(acc, [&](int m, int n, float v) { H1[m * kDbLd + n] = fmaxf(v + B1s[m], 0.0f); });
         }
         wave_lds_sync();
         {   // h2 = ReLU(W2 h1 + b2)
             v4f acc[4 * NT];
             zero_tiles(acc);
-            mfma_tiles<4, NT>(acc, [&](int m, int k) { return a.w2[m * 64 + k]; },
+            mfma_tiles<4, NT>(acc, [&](int m, int k) { return W2s[m * kW2Ld + k]; },
                               [&](int k, int n) { return H1[k * kDbLd + n]; }, 64);
-            tiles_out<4, NT>(acc, [&](int m, int n, float v) { H2[m * kDbLd + n] = fmaxf(v + a.b2[m], 0.0f); });
+            tiles_out<4, NT>(acc, [&](int m, int n, float v) { H2[m * kDbLd + n] = fmaxf(v + B2s[m], 0.0f); });
         }
         wave_lds_sync();
         // dW3 += g h2^T (texels contracted; rows 4-15 of the tile are padding)
@@ -236,7 +265,7 @@ __global__ __launch_bounds__(64, 2) void decoder_backward_kernel(DecBwdArgs a) {
         {   // d2 = (W3^T g) * [z2 > 0], in place of h2
             v4f acc[4 * NT];
             zero_tiles(acc);
-            mfma_tiles<4, NT>(acc, [&](int m, int k) { return a.w3[k * 64 + m]; },
+            mfma_tiles<4, NT>(acc, [&](int m, int k) { return W3s[k * kW3Ld + m]; },
                               [&](int k, int n) { return GT[k * kDbLd + n]; }, 4);
             tiles_out<4, NT>(acc, [&](int m, int n, float v) {
                 float& h = H2[m * kDbLd + n];
@@ -252,7 +281,7 @@ __global__ __launch_bounds__(64, 2) void decoder_backward_kernel(DecBwdArgs a) {
         {   // d1 = (W2^T d2) * [z1 > 0], in place of h1
             v4f acc[4 * NT];
             zero_tiles(acc);
-            mfma_tiles<4, NT>(acc, [&](int m, int k) { return a.w2[k * 64 + m]; },
+            mfma_tiles<4, NT>(acc, [&](int m, int k) { return W2s[k * kW2Ld + m]; },
                               [&](int k, int n) { return H2[k * kDbLd + n]; }, 64);
             tiles_out<4, NT>(acc, [&](int m, int n, float v) {
                 float& h = H1[m * kDbLd + n];
@@ -267,7 +296,7 @@ __global__ __launch_bounds__(64, 2) void decoder_backward_kernel(DecBwdArgs a) {
         {   // dL/dl = W1^T d1 (rows 8-15 padding); dL/dstored = dL/dl * scale
             v4f acc[NT];
             zero_tiles(acc);
-            mfma_tiles<1, NT>(acc, [&](int m, int k) { return m < 8 ? a.w1[k * 8 + m] : 0.0f; },
+            mfma_tiles<1, NT>(acc, [&](int m, int k) { return m < 8 ? W1s[k * kW1Ld + m] : 0.0f; },
                               [&](int k, int n) { return H1[k * kDbLd + n]; }, 64);
             const int64_t base = (int64_t)blk * kDbN;
             tiles_out<1, NT>(acc, [&](int m, int n, float v) {
@@ -276,17 +305,31 @@ __global__ __launch_bounds__(64, 2) void decoder_backward_kernel(DecBwdArgs a) {
         }
         wave_lds_sync();                                              // LDS reads done before the next block
     }
+    // the workgroup's slot: wave 0's sums, then waves 1, 2, 3 add theirs in turn
+    // (the activation and weight arrays are free once every wave is here)
+    float* sum = lds;
+    for (int w = 0; w < kDbWaves; ++w) {
+        __syncthreads();
+        if (wave == w) {
+            auto put = [&](int e, float v) {
+                if (w == 0) sum[e] = v;
+                else sum[e] += v;
+            };
+            tiles_out<4, 4>(dw2, [&](int m, int n, float v) { put(kGradW2 + m * 64 + n, v); });
+            tiles_out<4, 1>(dw1, [&](int m, int n, float v) {
+                if (n < 8) put(kGradW1 + m * 8 + n, v);
+            });
+            tiles_out<1, 4>(dw3, [&](int m, int n, float v) {
+                if (m < 4) put(kGradW3 + m * 64 + n, v);
+            });
+            put(kGradB1 + lane, db1);
+            put(kGradB2 + lane, db2);
+            if (lane < 4) put(kGradB3 + lane, db3);
+        }
+    }
+    __syncthreads();
     float* out = a.partial + (size_t)blockIdx.x * kGradFloats;
-    tiles_out<4, 4>(dw2, [&](int m, int n, float v) { out[kGradW2 + m * 64 + n] = v; });
-    tiles_out<4, 1>(dw1, [&](int m, int n, float v) {
-        if (n < 8) out[kGradW1 + m * 8 + n] = v;
-    });
-    tiles_out<1, 4>(dw3, [&](int m, int n, float v) {
-        if (m < 4) out[kGradW3 + m * 64 + n] = v;
-    });
-    out[kGradB1 + lane] = db1;
-    out[kGradB2 + lane] = db2;
-    if (lane < 4) out[kGradB3 + lane] = db3;
+    for (int e = threadIdx.x; e < kGradFloats; e += 64 * kDbWaves) out[e] = sum[e];
 }
 
 struct MlpGradPtrs {
@@ -297,12 +340,13 @@ struct MlpGradPtrs {
 // threads share the reads: kReduceSplits partial sums per gradient element
 // (slots split + k * kReduceSplits of each texture), then their sum added to
 // the outputs. Texture i's slots start at slot off[i]; only its first
-// min(waves[i], *count[i]) waves had blocks and wrote their slots.
+// min(groups[i], ceil(*count[i] / kDbWaves)) workgroups had blocks and wrote
+// their slots.
 constexpr int kReduceSplits = 64;
 
 struct SlotRanges {
     int32_t ntex;
-    int32_t off[STF_MAX_TEXTURES], waves[STF_MAX_TEXTURES];
+    int32_t off[STF_MAX_TEXTURES], groups[STF_MAX_TEXTURES];
     const int32_t* count[STF_MAX_TEXTURES];
 };
 
@@ -311,7 +355,7 @@ __global__ __launch_bounds__(256) void decoder_grad_partial_kernel(const float* 
     if (e >= kGradFloats) return;
     float s = 0.0f;
     for (int i = 0; i < r.ntex; ++i) {
-        const int n = min(r.waves[i], *r.count[i]);
+        const int n = min(r.groups[i], (*r.count[i] + kDbWaves - 1) / kDbWaves);
         for (int w = blockIdx.y; w < n; w += kReduceSplits) s += partial[(size_t)(r.off[i] + w) * kGradFloats + e];
     }
     level2[(size_t)blockIdx.y * kGradFloats + e] = s;

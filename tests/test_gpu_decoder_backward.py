@@ -7,7 +7,7 @@ decoder with the error bound the texel-adjoint tests use, 1e-5 of
 G_x = sum_c sum_i a_ci |dL/dout_c| (the adjoint of |dL/dout|; the a_ci are
 non-negative). Then every product runs in FP32 with exact products and
 sequential FP32 sums of K terms (error gamma(K) of the sum of absolute
-terms): K = 4, 64, 64 for d2, d1 and dL/dl, and 32 texels per block, the
+terms): K = 4, 64, 64 for d2, d1 and dL/dl, and 16 texels per block, the
 blocks of a wave and the waves for the weight gradients. So each output is
 compared with REL_CHAIN (plus gamma of the summation depth for the weight
 gradients) times its magnitude: the same backward pass run on |W|, G_x and
@@ -78,19 +78,29 @@ def magnitudes(lat, layers, G):
 
 CASES = [("bicubic", "tile8x8", "f16", 32), ("bicubic", "quad2x2", "fp8", 32), ("bilinear", "square3x3", "bf16", 32),
          ("bicubic", "self", "f16", 32), ("bilinear", "tile8x8", "fp8", 32),
-         ("bicubic", "tile8x8", "f16", 4),        # 16 texels: one partial block of the decoder adjoint
+         ("bicubic", "tile8x8", "f16", 4),        # 16 texels: one block of the decoder adjoint
          ("bicubic", "tile8x8", "bf16", 256)]     # 2048 blocks, a few dozen reached: a sparse block list
 
 
 @pytest.mark.parametrize("filt,fp,kind,size", CASES)
 def test_decoder_adjoint_matches_oracle(filt, fp, kind, size):
+    _check_case(filt, fp, kind, size, (72, 40, 3.0))
+
+
+def test_decoder_adjoint_whole_grid_two_blocks_per_wave():
+    # a 256x256 view at 1x covers the 256^2 grid: 4096 blocks of 16 texels for
+    # 2048 waves, so every wave runs two blocks and every workgroup sums four
+    _check_case("bicubic", "tile8x8", "fp8", 256, (256, 256, 1.0))
+
+
+def _check_case(filt, fp, kind, size, screen):
     rng = np.random.default_rng(11)
     lat = w.latent_grid(2, max(size, 8))[:size, :size].astype(np.float64)
     scale = w.amax_scale(lat, kind) if kind == "fp8" else rng.uniform(0.5, 2.0, 8).astype(np.float32).astype(np.float64)
     stored = w.quantize(lat, kind, scale)
     layers32 = w.mlp_weights(4)
     layers = [(a.astype(np.float64), b.astype(np.float64)) for a, b in layers32]
-    uv = w.small_screen(72, 40, size, 3.0, offset_seed=5)
+    uv = w.small_screen(screen[0], screen[1], size, screen[2], offset_seed=5)
     H, W = uv.shape[:2]
     g = rng.standard_normal((H, W, 4)).astype(np.float32)
     dlayers_t = [(dev(a), dev(b)) for a, b in layers32]
@@ -151,7 +161,7 @@ def test_zero_gradient_visits_no_block():
 
 
 def stf_waves(size):
-    return min((size * size + 31) // 32, 2048)         # one block of 32 texels per step
+    return min((size * size + 15) // 16, 2048)         # one block of 16 texels per step
 
 
 def test_accumulates_and_two_slots():
