@@ -90,7 +90,7 @@ def test_small_workload_full(fp):
 
 
 @pytest.mark.parametrize("filt", ["bilinear", "bicubic"])
-@pytest.mark.parametrize("fp", ALL_FP)
+@pytest.mark.parametrize("fp", ALL_FP + [None])            # None: one-tap STF (row-linear waves)
 def test_all_footprints_ragged_screen(filt, fp):
     # 61x37: partial tiles on both axes; rotated quad at 3.3x
     tex = w.tile_texture_rgba8(3, 64)
@@ -144,6 +144,9 @@ def test_tile_bins_window_from_wave_minimum(filt, mag, seam):
 def test_tiny_inputs():
     run_case([w.tile_texture_rgba8(1, 4)], w.small_screen(1, 1, 4, 2.0), "bicubic", "tile8x8")
     run_case([w.tile_texture_rgba8(1, 4)], w.small_screen(3, 9, 4, 2.0), "bilinear", "quad2x2")
+    # one-tap STF runs row-linear: one lane of one wave, and a row shorter than a wave
+    run_case([w.tile_texture_rgba8(1, 4)], w.small_screen(1, 1, 4, 2.0), "bicubic", None)
+    run_case([w.tile_texture_rgba8(1, 4), w.r8_texture(2, 4)], w.small_screen(3, 9, 4, 2.0), "bilinear", None)
 
 
 # --------------------------------------------------------------- plane workload
@@ -412,3 +415,4 @@ def test_maximum_screen_extents(shape):
     uv[..., 0] = ((px + 0.5) / 6.0 / 64) % 1.0
     uv[..., 1] = ((py + 0.5) / 6.0 / 64) % 1.0
     run_case([tex], uv, "bilinear", "tile8x8", seed=9)
+    run_case([tex], uv, "bicubic", None, seed=10)          # one-tap: 256 row runs of 128 pixels
