@@ -146,7 +146,7 @@ def test_tiny_inputs():
     run_case([w.tile_texture_rgba8(1, 4)], w.small_screen(3, 9, 4, 2.0), "bilinear", "quad2x2")
     # one-tap STF runs row-linear: one lane of one wave, and a row shorter than a wave
     run_case([w.tile_texture_rgba8(1, 4)], w.small_screen(1, 1, 4, 2.0), "bicubic", None)
-    run_case([w.tile_texture_rgba8(1, 4), w.r8_texture(2, 4)], w.small_screen(3, 9, 4, 2.0), "bilinear", None)
+    run_case([w.tile_texture_rgba8(1, 4), w.r8_texture(2, 16)], w.small_screen(3, 9, 4, 2.0), "bilinear", None)
 
 
 # --------------------------------------------------------------- plane workload
