@@ -1261,10 +1261,36 @@ struct MergeArea {
     float* wide;             // this wave's wide area (kBwdWideFloats)
 };
 
+// A contribution w * dL/dout of this lane's pixel to texel s: added to the
+// wave's window bins in LDS when that window holds every on-screen support of
+// the wave (the workgroup then flushes the sums, one global atomic per touched
+// texel and channel), else sent to the gradient with global atomics.
+template <int C>
+struct Deposit {
+    bool bins_on;
+    float* bins;             // [kBins][C] sums, window cells row-major
+    int base_x, base_y;      // the window's corner (texture coordinates, unwrapped)
+    uint32_t mx, my;
+    float* grad;
+    int tw;
+    const float* g;
+    __device__ __forceinline__ void operator()(uint32_t s, float w) const {
+        if (bins_on) {
+            const uint32_t cx = ((s & 0xFFFFu) - (uint32_t)base_x) & mx;
+            const uint32_t cy = ((s >> 16) - (uint32_t)base_y) & my;
+            float* b = bins + (cy * kBinG + cx) * C;
+#pragma unroll
+            for (int c = 0; c < C; ++c) atomicAdd(b + c, g[c] * w);
+        } else {
+            atomic_texel<C>(grad, tw, s, g, w);
+        }
+    }
+};
+
 template <int FILT, int MODE, int C>
 __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
                                               uint32_t hx, uint32_t hy, const float4& gin, float* lds,
-                                              MergeArea merge = {}) {
+                                              MergeArea merge) {
     constexpr int N = SelCtx<FILT>::N;
     const TexArg t = a.tex[slot];
     const int lane = lane_id();
@@ -1275,18 +1301,142 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
     const uint32_t sy = (uint32_t)(ctx.y.base + ky) & my;
     const uint32_t s = sx | (sy << 16);
     float* grad = a.out[slot];                              // dL/dT, [th][tw][C]
-    const int64_t pix = (int64_t)P.py * a.sw + P.px;
     const float gv[4] = {gin.x, gin.y, gin.z, gin.w};
     float g[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) g[c] = gv[c] * t.scale[c];
+    const float r = (MODE == kModeStf || !P.valid) ? 0.0f : fast_rcp(ctx.x.wsel(kx) * ctx.y.wsel(ky));
 
-    if constexpr (MODE == kModeStf) {
-        if (P.valid) atomic_texel<C>(grad, t.w, s, g, 1.0f);
-        return;
+    // The wave's kBinG x kBinG texel window holding every on-screen support;
+    // lane l owns window cells (rows 4 (l / 16) + v, column l % 16) in vals.
+    const int ij = lane & 15, kp = lane >> 4;
+    int base_x = 0, base_y = 0;
+    uint32_t rx = 0, ry = 0;
+    const bool use_bins = bin_window<N>(P, ctx.x.base, ctx.y.base, mx, my, t.w, t.h, base_x, base_y, rx, ry);
+    float vals[4][C];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int c = 0; c < C; ++c) vals[v][c] = 0.0f;
+
+    if constexpr (MODE == kModeBins) {
+        if (use_bins) {
+            v4f acc[C];
+            float* Nb = lds;
+            // LDS: Nb float [kBins] (sum of 1/p per texel), N64 u64 [kBins]
+            // (its exact integer accumulator, as in the forward pass)
+            uint64_t* N64 = reinterpret_cast<uint64_t*>(merge.wide);
+            for (int i = lane; i < kBins; i += 64) N64[i] = 0ull;
+            for (int i = lane; i < kBins; i += 64) Nb[i] = 0.0f;
+            const int my_bin = (int)(ry + ky) * kBinG + (int)(rx + kx);
+            const bool fixed = !(a.flags & kFlagFloatBinSums) &&
+                               __builtin_amdgcn_ballot_w64(P.valid && !fixed_range(r)) == 0;
+            wave_lds_sync();
+            if (fixed) {
+                if (P.valid) atomicAdd(reinterpret_cast<unsigned long long*>(&N64[my_bin]),
+                                       (unsigned long long)fixed_r(r));
+                wave_lds_sync();
+                for (int i = lane; i < kBins; i += 64) Nb[i] = float_r(N64[i]);
+            } else {
+                if (P.valid) atomicAdd(&Nb[my_bin], r);
+            }
+            wave_lds_sync();
+            const int bin0 = (int)ry * kBinG + (int)rx;
+            float B = 0.0f;
+#pragma unroll
+            for (int b = 0; b < N; ++b)
+#pragma unroll
+                for (int aa = 0; aa < N; ++aa) B += (ctx.x.w(aa) * ctx.y.w(b)) * Nb[bin0 + b * kBinG + aa];
+            // Sum over the tile's pixels of f_c(x) q_c for every texel x of the
+            // window (q_c = dL/dout_c / B_c): with f_c(x) = wy_c(row) wx_c(col)
+            // it is the rank-64 product  Wy diag(q) Wx^T , run on the matrix
+            // cores: window rows x window columns (12 x 12 in a 16 x 16 tile),
+            // K = the 64 pixels, four per v_mfma_f32_16x16x4_f32 (A[i][k] and
+            // B[k][j] of lane l: i = j = l % 16, k = l / 16). Each pixel first
+            // publishes its row record (over the converted 64-bit sums): its
+            // weight at every window row and column, zero outside its support
+            // (off-screen pixels: all zero), then q. Lanes of tile rows and
+            // columns 12-15 read the next entries; those outputs are never used.
+            float* rows = merge.wide;                       // [64][kBwdRowFloats]
+            {
+                float* own = rows + P.q * kBwdRowFloats;
+                const float inv = P.valid ? fast_rcp(B) : 0.0f;
+                float4* o4 = reinterpret_cast<float4*>(own);
+#pragma unroll
+                for (int k = 0; k < 2 * kBinG / 4; ++k) o4[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (P.valid) {
+#pragma unroll
+                    for (int b = 0; b < N; ++b) own[ry + b] = ctx.y.w(b);
+#pragma unroll
+                    for (int b = 0; b < N; ++b) own[kBinG + rx + b] = ctx.x.w(b);
+                }
+                float qv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int c = 0; c < C; ++c) qv[c] = g[c] * inv;
+                o4[2 * kBinG / 4] = make_float4(qv[0], qv[1], qv[2], qv[3]);
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 2
+            for (int m = 0; m < 16; ++m) {
+                const float* rp = rows + (4 * m + kp) * kBwdRowFloats;
+                const float wa = rp[ij];
+                const float wb = rp[kBinG + ij];
+                const float4 q = *reinterpret_cast<const float4*>(rp + 2 * kBinG);
+                const float qc[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, wb * qc[c], acc[c], 0, 0, 0);
+            }
+            wave_lds_sync();                         // row records read before the merge reuses them
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 4 * kp + v;
+                if (i < kBinG && ij < kBinG) {
+                    const float nx = Nb[i * kBinG + ij];
+#pragma unroll
+                    for (int c = 0; c < C; ++c) vals[v][c] = acc[c][v] * nx;
+                }
+            }
+        } else {
+            // supports that leave the window: every pixel pairs with all 64 picks, global atomics
+            uint2* meta = reinterpret_cast<uint2*>(lds);
+            meta[P.q] = make_uint2(s, __float_as_uint(r));
+            wave_lds_sync();
+            float B = 1.0f;
+            for (int j = 0; j < 64; ++j) {
+                if (j == P.q) continue;
+                const uint2 mj = meta[j];
+                uint32_t dx, dy;
+                if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy))
+                    B += ctx.x.wsel(dx) * ctx.y.wsel(dy) * __uint_as_float(mj.y);
+            }
+            if (P.valid) {
+                const float inv = fast_rcp(B);
+                atomic_texel<C>(grad, t.w, s, g, inv);
+                for (int j = 0; j < 64; ++j) {
+                    if (j == P.q) continue;
+                    const uint2 mj = meta[j];
+                    const float rj = __uint_as_float(mj.y);
+                    uint32_t dx, dy;
+                    if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy) && rj != 0.0f)
+                        atomic_texel<C>(grad, t.w, mj.x, g, ctx.x.wsel(dx) * ctx.y.wsel(dy) * rj * inv);
+                }
+            }
+            wave_lds_sync();
+        }
     } else {
-        const float r = P.valid ? fast_rcp(ctx.x.wsel(kx) * ctx.y.wsel(ky)) : 0.0f;
-        if constexpr (MODE == kModeQuad) {
+        // every target texel is a pick inside the own support, so inside the window
+        float* bins = merge.wide;
+        if (use_bins) {
+            for (int i = lane; i < kBins * C; i += 64) bins[i] = 0.0f;
+            wave_lds_sync();
+        }
+        const Deposit<C> dep{use_bins, bins, base_x, base_y, mx, my, grad, t.w, g};
+        if constexpr (MODE == kModeStf) {
+            if (P.valid) dep(s, 1.0f);
+        } else if constexpr (MODE == kModeQuad) {
             uint32_t si[3];
             float ri[3];
             si[0] = quad_xor<1>(s); ri[0] = quad_xor<1>(r);
@@ -1303,202 +1453,133 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
             }
             if (P.valid) {
                 const float inv = fast_rcp(B);
-                atomic_texel<C>(grad, t.w, s, g, inv);
+                dep(s, inv);
 #pragma unroll
                 for (int m = 0; m < 3; ++m)
-                    if (in[m] && ri[m] != 0.0f) atomic_texel<C>(grad, t.w, si[m], g, f[m] * ri[m] * inv);
+                    if (in[m] && ri[m] != 0.0f) dep(si[m], f[m] * ri[m] * inv);
             }
         } else {
-            bool use_bins = false;
-            int base_x = 0, base_y = 0;
-            const int ij = lane & 15, kp = lane >> 4;
-            v4f acc[C];
-            float* Nb = lds;
-            if constexpr (MODE == kModeBins) {
-                uint32_t rx, ry;
-                use_bins = bin_window<N>(P, ctx.x.base, ctx.y.base, mx, my, t.w, t.h, base_x, base_y, rx, ry);
-                if (use_bins) {
-                    // LDS: Nb float [kBins] (sum of 1/p per texel), N64 u64 [kBins]
-                    // (its exact integer accumulator, as in the forward pass)
-                    uint64_t* N64 = reinterpret_cast<uint64_t*>(merge.wide);
-                    for (int i = lane; i < kBins; i += 64) N64[i] = 0ull;
-                    for (int i = lane; i < kBins; i += 64) Nb[i] = 0.0f;
-                    const int my_bin = (int)(ry + ky) * kBinG + (int)(rx + kx);
-                    const bool fixed = !(a.flags & kFlagFloatBinSums) &&
-                                       __builtin_amdgcn_ballot_w64(P.valid && !fixed_range(r)) == 0;
-                    wave_lds_sync();
-                    if (fixed) {
-                        if (P.valid) atomicAdd(reinterpret_cast<unsigned long long*>(&N64[my_bin]),
-                                               (unsigned long long)fixed_r(r));
-                        wave_lds_sync();
-                        for (int i = lane; i < kBins; i += 64) Nb[i] = float_r(N64[i]);
-                    } else {
-                        if (P.valid) atomicAdd(&Nb[my_bin], r);
-                    }
-                    wave_lds_sync();
-                    const int bin0 = (int)ry * kBinG + (int)rx;
-                    float B = 0.0f;
-#pragma unroll
-                    for (int b = 0; b < N; ++b)
-#pragma unroll
-                        for (int aa = 0; aa < N; ++aa) B += (ctx.x.w(aa) * ctx.y.w(b)) * Nb[bin0 + b * kBinG + aa];
-                    // Sum over the tile's pixels of f_c(x) q_c for every texel x of the
-                    // window (q_c = dL/dout_c / B_c): with f_c(x) = wy_c(row) wx_c(col)
-                    // it is the rank-64 product  Wy diag(q) Wx^T , run on the matrix
-                    // cores: window rows x window columns (12 x 12 in a 16 x 16 tile),
-                    // K = the 64 pixels, four per v_mfma_f32_16x16x4_f32 (A[i][k] and
-                    // B[k][j] of lane l: i = j = l % 16, k = l / 16). Each pixel first
-                    // publishes its row record (over the converted 64-bit sums): its
-                    // weight at every window row and column, zero outside its support
-                    // (off-screen pixels: all zero), then q. Lanes of tile rows and
-                    // columns 12-15 read the next entries; those outputs are never used.
-                    float* rows = merge.wide;                       // [64][kBwdRowFloats]
-                    {
-                        float* own = rows + P.q * kBwdRowFloats;
-                        const float inv = P.valid ? fast_rcp(B) : 0.0f;
-                        float4* o4 = reinterpret_cast<float4*>(own);
-#pragma unroll
-                        for (int k = 0; k < 2 * kBinG / 4; ++k) o4[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                        if (P.valid) {
-#pragma unroll
-                            for (int b = 0; b < N; ++b) own[ry + b] = ctx.y.w(b);
-#pragma unroll
-                            for (int b = 0; b < N; ++b) own[kBinG + rx + b] = ctx.x.w(b);
-                        }
-                        float qv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                        for (int c = 0; c < C; ++c) qv[c] = g[c] * inv;
-                        o4[2 * kBinG / 4] = make_float4(qv[0], qv[1], qv[2], qv[3]);
-                    }
-                    wave_lds_sync();
-#pragma unroll
-                    for (int c = 0; c < C; ++c) acc[c] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 2
-                    for (int m = 0; m < 16; ++m) {
-                        const float* rp = rows + (4 * m + kp) * kBwdRowFloats;
-                        const float wa = rp[ij];
-                        const float wb = rp[kBinG + ij];
-                        const float4 q = *reinterpret_cast<const float4*>(rp + 2 * kBinG);
-                        const float qc[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-                        for (int c = 0; c < C; ++c)
-                            acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, wb * qc[c], acc[c], 0, 0, 0);
-                    }
-                }
+            uint2* meta = reinterpret_cast<uint2*>(lds);
+            meta[P.q] = make_uint2(s, __float_as_uint(r));
+            wave_lds_sync();
+            const int fp = a.footprint;
+            const int K = footprint_size(fp, a.lut_k);
+            float B = 1.0f;
+            for (int m = 0; m < K; ++m) {
+                const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
+                if (j == P.q) continue;
+                const uint2 mj = meta[j];
+                uint32_t dx, dy;
+                if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy))
+                    B += ctx.x.wsel(dx) * ctx.y.wsel(dy) * __uint_as_float(mj.y);
             }
-            if (!use_bins) {
-                uint2* meta = reinterpret_cast<uint2*>(lds);
-                meta[P.q] = make_uint2(s, __float_as_uint(r));
-                wave_lds_sync();
-                const int fp = (MODE == kModeBins) ? (int)STF_FP_TILE8X8 : a.footprint;
-                const int K = footprint_size(fp, a.lut_k);
-                float B = 1.0f;
+            if (P.valid) {
+                const float inv = fast_rcp(B);
+                dep(s, inv);
                 for (int m = 0; m < K; ++m) {
                     const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
                     if (j == P.q) continue;
                     const uint2 mj = meta[j];
+                    const float rj = __uint_as_float(mj.y);
                     uint32_t dx, dy;
-                    if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy))
-                        B += ctx.x.wsel(dx) * ctx.y.wsel(dy) * __uint_as_float(mj.y);
+                    if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy) && rj != 0.0f)
+                        dep(mj.x, ctx.x.wsel(dx) * ctx.y.wsel(dy) * rj * inv);
                 }
-                if (P.valid) {
-                    const float inv = fast_rcp(B);
-                    atomic_texel<C>(grad, t.w, s, g, inv);
-                    for (int m = 0; m < K; ++m) {
-                        const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
-                        if (j == P.q) continue;
-                        const uint2 mj = meta[j];
-                        const float rj = __uint_as_float(mj.y);
-                        uint32_t dx, dy;
-                        if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy) && rj != 0.0f)
-                            atomic_texel<C>(grad, t.w, mj.x, g, ctx.x.wsel(dx) * ctx.y.wsel(dy) * rj * inv);
-                    }
-                }
-                wave_lds_sync();
             }
-            if constexpr (MODE == kModeBins) {
-                // every wave of the workgroup reaches the barriers below, whichever
-                // path it took; only waves with bins and an on-screen pixel add
-                // lane holds window rows 4 (l / 16) + v, column l % 16
-                const int wave = threadIdx.x >> 6;
-                const bool contributes = use_bins && __builtin_amdgcn_ballot_w64(P.valid) != 0;
-                if (lane == 0) {
-                    merge.info[wave * 4 + 0] = contributes ? 1 : 0;
-                    merge.info[wave * 4 + 1] = base_x;
-                    merge.info[wave * 4 + 2] = base_y;
+        }
+        wave_lds_sync();                             // every deposit in, and the records read
+        if (use_bins) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 4 * kp + v;
+                if (i < kBinG && ij < kBinG) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) vals[v][c] = bins[(i * kBinG + ij) * C + c];
                 }
-                __syncthreads();
-                // the union of the contributing windows (offsets taken modulo the texture
-                // size relative to the first one); the same result in every thread
-                int ref = -1, lo_x = 0, hi_x = 0, lo_y = 0, hi_y = 0;
-                for (int w = 0; w < kWavesPerGroup; ++w) {
-                    if (!merge.info[w * 4]) continue;
-                    if (ref < 0) ref = w;
-                    const int dx = wrapped_offset(merge.info[w * 4 + 1], merge.info[ref * 4 + 1], mx);
-                    const int dy = wrapped_offset(merge.info[w * 4 + 2], merge.info[ref * 4 + 2], my);
-                    lo_x = min(lo_x, dx); hi_x = max(hi_x, dx);
-                    lo_y = min(lo_y, dy); hi_y = max(hi_y, dy);
-                }
-                const bool merged = ref >= 0 && hi_x - lo_x + kBinG <= kMergeW && hi_y - lo_y + kBinG <= kMergeH;
-                if (merged) {
-                    const int ux = merge.info[ref * 4 + 1] + lo_x, uy = merge.info[ref * 4 + 2] + lo_y;
-                    // every wave has passed the barrier above, so no row record is read any more
-                    for (int e = threadIdx.x; e < kMergeW * kMergeH * C; e += kThreads) merge.v[e] = 0.0f;
-                    __syncthreads();
-                    if (contributes) {
-                        // this window's corner in the area: its offset from the reference window,
-                        // as the union was formed (in [0, kMergeW - kBinG] x [0, kMergeH - kBinG])
-                        const int ox = wrapped_offset(base_x, merge.info[ref * 4 + 1], mx) - lo_x;
-                        const int oy = wrapped_offset(base_y, merge.info[ref * 4 + 2], my) - lo_y;
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int i = 4 * kp + v;
-                            if (i < kBinG && ij < kBinG) {
-                                const float nx = Nb[i * kBinG + ij];
-                                if (nx != 0.0f) {
-                                    float* m = merge.v + ((oy + i) * kMergeW + ox + ij) * C;
-#pragma unroll
-                                    for (int c = 0; c < C; ++c) atomicAdd(m + c, acc[c][v] * nx);
-                                }
-                            }
-                        }
-                    }
-                    __syncthreads();
-                    for (int e = threadIdx.x; e < kMergeW * kMergeH; e += kThreads) {
-                        float q[C];
-                        bool any = false;
-#pragma unroll
-                        for (int c = 0; c < C; ++c) {
-                            q[c] = merge.v[e * C + c];
-                            any = any || q[c] != 0.0f;
-                        }
-                        if (any) {
-                            const uint32_t tx = (uint32_t)(ux + e % kMergeW) & mx;
-                            const uint32_t ty = (uint32_t)(uy + e / kMergeW) & my;
-                            atomic_texel<C>(grad, t.w, tx | (ty << 16), q, 1.0f);
-                        }
-                    }
-                } else if (contributes) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int i = 4 * kp + v;
-                        if (i < kBinG && ij < kBinG) {
-                            const float nx = Nb[i * kBinG + ij];
-                            if (nx != 0.0f) {
-                                const uint32_t tx = (uint32_t)(base_x + ij) & mx;
-                                const uint32_t ty = (uint32_t)(base_y + i) & my;
-                                float q[C];
-#pragma unroll
-                                for (int c = 0; c < C; ++c) q[c] = acc[c][v];
-                                atomic_texel<C>(grad, t.w, tx | (ty << 16), q, nx);
-                            }
-                        }
-                    }
-                }
-                __syncthreads();             // merge area and window read before the next slot
             }
         }
     }
+
+    // every wave of the workgroup reaches the barriers below, whichever
+    // path it took; only waves with bins and an on-screen pixel add
+    // lane holds window rows 4 (l / 16) + v, column l % 16
+    const int wave = threadIdx.x >> 6;
+    const bool contributes = use_bins && __builtin_amdgcn_ballot_w64(P.valid) != 0;
+    if (lane == 0) {
+        merge.info[wave * 4 + 0] = contributes ? 1 : 0;
+        merge.info[wave * 4 + 1] = base_x;
+        merge.info[wave * 4 + 2] = base_y;
+    }
+    __syncthreads();
+    // the union of the contributing windows (offsets taken modulo the texture
+    // size relative to the first one); the same result in every thread
+    int ref = -1, lo_x = 0, hi_x = 0, lo_y = 0, hi_y = 0;
+    for (int w = 0; w < kWavesPerGroup; ++w) {
+        if (!merge.info[w * 4]) continue;
+        if (ref < 0) ref = w;
+        const int dx = wrapped_offset(merge.info[w * 4 + 1], merge.info[ref * 4 + 1], mx);
+        const int dy = wrapped_offset(merge.info[w * 4 + 2], merge.info[ref * 4 + 2], my);
+        lo_x = min(lo_x, dx); hi_x = max(hi_x, dx);
+        lo_y = min(lo_y, dy); hi_y = max(hi_y, dy);
+    }
+    const bool merged = ref >= 0 && hi_x - lo_x + kBinG <= kMergeW && hi_y - lo_y + kBinG <= kMergeH;
+    if (merged) {
+        const int ux = merge.info[ref * 4 + 1] + lo_x, uy = merge.info[ref * 4 + 2] + lo_y;
+        // every wave has passed the barrier above, so no row record is read any more
+        for (int e = threadIdx.x; e < kMergeW * kMergeH * C; e += kThreads) merge.v[e] = 0.0f;
+        __syncthreads();
+        if (contributes) {
+            // this window's corner in the area: its offset from the reference window,
+            // as the union was formed (in [0, kMergeW - kBinG] x [0, kMergeH - kBinG])
+            const int ox = wrapped_offset(base_x, merge.info[ref * 4 + 1], mx) - lo_x;
+            const int oy = wrapped_offset(base_y, merge.info[ref * 4 + 2], my) - lo_y;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 4 * kp + v;
+                if (i < kBinG && ij < kBinG) {
+                    bool any = false;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) any = any || vals[v][c] != 0.0f;
+                    if (any) {
+                        float* m = merge.v + ((oy + i) * kMergeW + ox + ij) * C;
+#pragma unroll
+                        for (int c = 0; c < C; ++c) atomicAdd(m + c, vals[v][c]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kMergeW * kMergeH; e += kThreads) {
+            float q[C];
+            bool any = false;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                q[c] = merge.v[e * C + c];
+                any = any || q[c] != 0.0f;
+            }
+            if (any) {
+                const uint32_t tx = (uint32_t)(ux + e % kMergeW) & mx;
+                const uint32_t ty = (uint32_t)(uy + e / kMergeW) & my;
+                atomic_texel<C>(grad, t.w, tx | (ty << 16), q, 1.0f);
+            }
+        }
+    } else if (contributes) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 4 * kp + v;
+            if (i < kBinG && ij < kBinG) {
+                bool any = false;
+#pragma unroll
+                for (int c = 0; c < C; ++c) any = any || vals[v][c] != 0.0f;
+                if (any) {
+                    const uint32_t tx = (uint32_t)(base_x + ij) & mx;
+                    const uint32_t ty = (uint32_t)(base_y + i) & my;
+                    atomic_texel<C>(grad, t.w, tx | (ty << 16), vals[v], 1.0f);
+                }
+            }
+        }
+    }
+    __syncthreads();             // merge area and window read before the next slot
 }
 
 // dL/dout of this lane's pixel for one slot (channels beyond the slot's
@@ -1520,30 +1601,29 @@ __device__ __forceinline__ float4 load_dout(const Args& a, int slot, const Pixel
     return g;
 }
 
-// The whole-tile adjoint is budgeted for kBwdWaves waves per SIMD.
+// The adjoint kernels are budgeted for kBwdWaves waves per SIMD.
 constexpr int kBwdWaves = 5;
 
 template <int FILT, int MODE>
-__global__ __launch_bounds__(kThreads, (MODE == kModeBins ? kBwdWaves : 1)) void backward_kernel(Args a) {
-    constexpr bool kMerge = MODE == kModeBins;
-    constexpr int kPerWave = kMerge ? kBwdNbFloats : 128;       // bin sums, or 64 {s, r} records
-    static_assert(!kMerge || kMergeW * kMergeH * 4 <= kWavesPerGroup * kBwdWideFloats, "merge area fits");
-    __shared__ __align__(16) float lds_all[kWavesPerGroup * (kPerWave + (kMerge ? kBwdWideFloats : 0))];
+__global__ __launch_bounds__(kThreads, kBwdWaves) void backward_kernel(Args a) {
+    // per wave: bin sums of 1/p or 64 {s, r} records, then the wide area
+    // (window bins, row records); the wide areas of the workgroup together
+    // form the merge area
+    constexpr int kPerWave = kBwdNbFloats;
+    static_assert(kPerWave >= 128, "64 {s, r} records fit");
+    static_assert(kMergeW * kMergeH * 4 <= kWavesPerGroup * kBwdWideFloats, "merge area fits");
+    static_assert(kBins * 4 <= kBwdWideFloats, "window bins fit");
+    __shared__ __align__(16) float lds_all[kWavesPerGroup * (kPerWave + kBwdWideFloats)];
     __shared__ int merge_info[kWavesPerGroup * 4];
     float* wide_all = lds_all + kWavesPerGroup * kPerWave;
-    const MergeArea merge{kMerge ? wide_all : nullptr, merge_info,
-                          kMerge ? wide_all + (threadIdx.x >> 6) * kBwdWideFloats : nullptr};
+    const MergeArea merge{wide_all, merge_info, wide_all + (threadIdx.x >> 6) * kBwdWideFloats};
+    // the workgroup merges behind barriers: a wave whose tile column is off
+    // screen stays (every lane off screen, nothing added)
     Pixel P;
-    if constexpr (kMerge) {
-        // the whole-tile adjoint merges per workgroup behind barriers: a wave whose
-        // tile column is off screen stays (every lane off screen, nothing added)
-        place_pixel(a, blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6), blockIdx.y, P);
-        const v2f uv = load_uv(a, P.px, P.py);
-        P.u = uv.x;
-        P.v = uv.y;
-    } else {
-        if (!setup_pixel(a, P)) return;
-    }
+    place_pixel(a, blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6), blockIdx.y, P);
+    const v2f uv = load_uv(a, P.px, P.py);
+    P.u = uv.x;
+    P.v = uv.y;
     float* lds = lds_all + (threadIdx.x >> 6) * kPerWave;
     SelCtx<FILT> ctx;
     // dL/dout of the pixel, one vector load per slot, the next slot's
