@@ -1261,36 +1261,47 @@ struct MergeArea {
     float* wide;             // this wave's wide area (kBwdWideFloats)
 };
 
-// A contribution w * dL/dout of this lane's pixel to texel s: added to the
-// wave's window bins in LDS when that window holds every on-screen support of
-// the wave (the workgroup then flushes the sums, one global atomic per touched
-// texel and channel), else sent to the gradient with global atomics.
+// The rank-64 window product on the matrix cores: for every cell (row i,
+// column j) of the kBinG x kBinG window, the sum over the wave's 64 pixels k
+// of a_k(i) b_k(j) q_k (per channel), from the pixels' row records
+// {a_k at the kBinG rows, b_k at the kBinG columns, q_k}. K = the 64 pixels,
+// four per v_mfma_f32_16x16x4_f32 (A[i][k] and B[k][j] of lane l: i = j =
+// l % 16, k = l / 16); lanes of tile rows and columns 12-15 read the next
+// entries, and those outputs are never used. Cell (4 (l / 16) + v, l % 16)
+// lands in acc[c][v] of lane l.
 template <int C>
-struct Deposit {
-    bool bins_on;
-    float* bins;             // [kBins][C] sums, window cells row-major
-    int base_x, base_y;      // the window's corner (texture coordinates, unwrapped)
-    uint32_t mx, my;
-    float* grad;
-    int tw;
-    const float* g;
-    __device__ __forceinline__ void operator()(uint32_t s, float w) const {
-        if (bins_on) {
-            const uint32_t cx = ((s & 0xFFFFu) - (uint32_t)base_x) & mx;
-            const uint32_t cy = ((s >> 16) - (uint32_t)base_y) & my;
-            float* b = bins + (cy * kBinG + cx) * C;
+__device__ __forceinline__ void window_product(const float* rows, int ij, int kp, v4f* acc) {
 #pragma unroll
-            for (int c = 0; c < C; ++c) atomicAdd(b + c, g[c] * w);
-        } else {
-            atomic_texel<C>(grad, tw, s, g, w);
-        }
+    for (int c = 0; c < C; ++c) acc[c] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 2
+    for (int m = 0; m < 16; ++m) {
+        const float* rp = rows + (4 * m + kp) * kBwdRowFloats;
+        const float wa = rp[ij];
+        const float wb = rp[kBinG + ij];
+        const float4 q = *reinterpret_cast<const float4*>(rp + 2 * kBinG);
+        const float qc[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, wb * qc[c], acc[c], 0, 0, 0);
     }
-};
+}
+
+// Pixels of the wave whose window footprint holds this lane's pixel (lx, ly),
+// itself excluded: bit p for tile pixel p (row-major).
+__device__ __forceinline__ uint64_t reverse_members(int fp, int lx, int ly) {
+    uint64_t bits = 0ull;
+    for (int p = 0; p < 64; ++p) {
+        int ox, oy, n;
+        window_of(fp, p & 7, p >> 3, ox, oy, n);
+        if ((uint32_t)(lx - ox) < (uint32_t)n && (uint32_t)(ly - oy) < (uint32_t)n && p != ly * 8 + lx)
+            bits |= 1ull << p;
+    }
+    return bits;
+}
 
 template <int FILT, int MODE, int C>
 __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
                                               uint32_t hx, uint32_t hy, const float4& gin, float* lds,
-                                              MergeArea merge) {
+                                              MergeArea merge, uint64_t rev) {
     constexpr int N = SelCtx<FILT>::N;
     const TexArg t = a.tex[slot];
     const int lane = lane_id();
@@ -1349,14 +1360,10 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                 for (int aa = 0; aa < N; ++aa) B += (ctx.x.w(aa) * ctx.y.w(b)) * Nb[bin0 + b * kBinG + aa];
             // Sum over the tile's pixels of f_c(x) q_c for every texel x of the
             // window (q_c = dL/dout_c / B_c): with f_c(x) = wy_c(row) wx_c(col)
-            // it is the rank-64 product  Wy diag(q) Wx^T , run on the matrix
-            // cores: window rows x window columns (12 x 12 in a 16 x 16 tile),
-            // K = the 64 pixels, four per v_mfma_f32_16x16x4_f32 (A[i][k] and
-            // B[k][j] of lane l: i = j = l % 16, k = l / 16). Each pixel first
-            // publishes its row record (over the converted 64-bit sums): its
-            // weight at every window row and column, zero outside its support
-            // (off-screen pixels: all zero), then q. Lanes of tile rows and
-            // columns 12-15 read the next entries; those outputs are never used.
+            // it is the rank-64 product  Wy diag(q) Wx^T  (window_product).
+            // Each pixel first publishes its row record (over the converted
+            // 64-bit sums): its weight at every window row and column, zero
+            // outside its support (off-screen pixels: all zero), then q.
             float* rows = merge.wide;                       // [64][kBwdRowFloats]
             {
                 float* own = rows + P.q * kBwdRowFloats;
@@ -1376,19 +1383,7 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                 o4[2 * kBinG / 4] = make_float4(qv[0], qv[1], qv[2], qv[3]);
             }
             wave_lds_sync();
-#pragma unroll
-            for (int c = 0; c < C; ++c) acc[c] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 2
-            for (int m = 0; m < 16; ++m) {
-                const float* rp = rows + (4 * m + kp) * kBwdRowFloats;
-                const float wa = rp[ij];
-                const float wb = rp[kBinG + ij];
-                const float4 q = *reinterpret_cast<const float4*>(rp + 2 * kBinG);
-                const float qc[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-                for (int c = 0; c < C; ++c)
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa, wb * qc[c], acc[c], 0, 0, 0);
-            }
+            window_product<C>(rows, ij, kp, acc);
             wave_lds_sync();                         // row records read before the merge reuses them
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -1427,15 +1422,15 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
             wave_lds_sync();
         }
     } else {
-        // every target texel is a pick inside the own support, so inside the window
-        float* bins = merge.wide;
-        if (use_bins) {
-            for (int i = lane; i < kBins * C; i += 64) bins[i] = 0.0f;
-            wave_lds_sync();
-        }
-        const Deposit<C> dep{use_bins, bins, base_x, base_y, mx, my, grad, t.w, g};
+        // Every contribution lands on some lane's pick: pixel p adds
+        // f_p(s_j) r_j dL/dout_p / B_p to pick j of each other member j, and
+        // dL/dout_p / B_p to its own. Each lane first gathers the total of its
+        // pick (tot), then the wave deposits the 64 totals into its window
+        // cells at once.
+        float tot[C];
         if constexpr (MODE == kModeStf) {
-            if (P.valid) dep(s, 1.0f);
+#pragma unroll
+            for (int c = 0; c < C; ++c) tot[c] = P.valid ? g[c] : 0.0f;
         } else if constexpr (MODE == kModeQuad) {
             uint32_t si[3];
             float ri[3];
@@ -1443,60 +1438,137 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
             si[1] = quad_xor<2>(s); ri[1] = quad_xor<2>(r);
             si[2] = quad_xor<3>(s); ri[2] = quad_xor<3>(r);
             float B = 1.0f, f[3];
-            bool in[3];
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
                 uint32_t dx, dy;
-                in[m] = support_offset<N>(si[m], ctx.x.base, ctx.y.base, mx, my, dx, dy);
-                f[m] = ctx.x.wsel(dx) * ctx.y.wsel(dy);
-                if (in[m]) B += f[m] * ri[m];
+                const bool in = support_offset<N>(si[m], ctx.x.base, ctx.y.base, mx, my, dx, dy);
+                f[m] = in ? ctx.x.wsel(dx) * ctx.y.wsel(dy) * ri[m] : 0.0f;
+                B += f[m];
             }
-            if (P.valid) {
-                const float inv = fast_rcp(B);
-                dep(s, inv);
+            const float inv = P.valid ? fast_rcp(B) : 0.0f;
+            // lane p's coefficient for partner p ^ (m + 1) reaches that partner
+            // over the same xor exchange
 #pragma unroll
-                for (int m = 0; m < 3; ++m)
-                    if (in[m] && ri[m] != 0.0f) dep(si[m], f[m] * ri[m] * inv);
+            for (int c = 0; c < C; ++c) tot[c] = g[c] * inv;
+            {
+                const float k = f[0] * inv;
+#pragma unroll
+                for (int c = 0; c < C; ++c) tot[c] += quad_xor<1>(k * g[c]);
+            }
+            {
+                const float k = f[1] * inv;
+#pragma unroll
+                for (int c = 0; c < C; ++c) tot[c] += quad_xor<2>(k * g[c]);
+            }
+            {
+                const float k = f[2] * inv;
+#pragma unroll
+                for (int c = 0; c < C; ++c) tot[c] += quad_xor<3>(k * g[c]);
             }
         } else {
+            // LDS: meta {s, r} [64] in the wave's small area; in the wide area
+            // coef [K][64] (pixel p's f_p(s_j) r_j for its member m, zero when
+            // s_j is off its support) and q [64][4] (dL/dout_p / B_p), or for a
+            // table footprint the per-lane sums [C][64]
             uint2* meta = reinterpret_cast<uint2*>(lds);
+            float* coef = merge.wide;
+            float* qrec = merge.wide + 16 * 64;
+            float* lane_sum = merge.wide;
+            const int fp = a.footprint;
+            const bool table = fp == STF_FP_LUT;
+            if (table) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) lane_sum[c * 64 + P.q] = 0.0f;
+            }
             meta[P.q] = make_uint2(s, __float_as_uint(r));
             wave_lds_sync();
-            const int fp = a.footprint;
             const int K = footprint_size(fp, a.lut_k);
             float B = 1.0f;
             for (int m = 0; m < K; ++m) {
                 const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
-                if (j == P.q) continue;
-                const uint2 mj = meta[j];
-                uint32_t dx, dy;
-                if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy))
-                    B += ctx.x.wsel(dx) * ctx.y.wsel(dy) * __uint_as_float(mj.y);
-            }
-            if (P.valid) {
-                const float inv = fast_rcp(B);
-                dep(s, inv);
-                for (int m = 0; m < K; ++m) {
-                    const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
-                    if (j == P.q) continue;
+                float k = 0.0f;
+                if (j != P.q) {
                     const uint2 mj = meta[j];
-                    const float rj = __uint_as_float(mj.y);
                     uint32_t dx, dy;
-                    if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy) && rj != 0.0f)
-                        dep(mj.x, ctx.x.wsel(dx) * ctx.y.wsel(dy) * rj * inv);
+                    if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy))
+                        k = ctx.x.wsel(dx) * ctx.y.wsel(dy) * __uint_as_float(mj.y);
+                }
+                B += k;
+                if (!table) coef[m * 64 + P.q] = k;
+            }
+            const float inv = P.valid ? fast_rcp(B) : 0.0f;
+#pragma unroll
+            for (int c = 0; c < C; ++c) tot[c] = g[c] * inv;
+            if (table) {
+                // members of a table may repeat and need not be mutual: scatter
+                // through per-lane sums
+                if (P.valid) {
+                    for (int m = 0; m < K; ++m) {
+                        const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
+                        if (j == P.q) continue;
+                        const uint2 mj = meta[j];
+                        uint32_t dx, dy;
+                        if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy) && mj.y != 0u) {
+                            const float k = ctx.x.wsel(dx) * ctx.y.wsel(dy) * __uint_as_float(mj.y) * inv;
+#pragma unroll
+                            for (int c = 0; c < C; ++c) atomicAdd(lane_sum + c * 64 + j, k * g[c]);
+                        }
+                    }
+                }
+                wave_lds_sync();
+#pragma unroll
+                for (int c = 0; c < C; ++c) tot[c] += lane_sum[c * 64 + P.q];
+            } else {
+                // window footprints: gather from the pixels whose window holds
+                // this one (their member index follows from their window)
+                float4 q4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if constexpr (C >= 1) q4.x = tot[0];
+                if constexpr (C >= 2) q4.y = tot[1];
+                if constexpr (C >= 4) { q4.z = tot[2]; q4.w = tot[3]; }
+                reinterpret_cast<float4*>(qrec)[P.q] = q4;
+                wave_lds_sync();
+                uint64_t bits = rev;
+                while (bits) {
+                    const int p = (int)__builtin_ctzll(bits);
+                    bits &= bits - 1ull;
+                    int ox, oy, n;
+                    window_of(fp, p & 7, p >> 3, ox, oy, n);
+                    const float k = coef[((P.ly - oy) * n + (P.lx - ox)) * 64 + p];
+                    const float4 qp = reinterpret_cast<const float4*>(qrec)[p];
+                    const float qc[4] = {qp.x, qp.y, qp.z, qp.w};
+#pragma unroll
+                    for (int c = 0; c < C; ++c) tot[c] = fmaf(k, qc[c], tot[c]);
                 }
             }
+            wave_lds_sync();                     // sums and records read before the row records
         }
-        wave_lds_sync();                             // every deposit in, and the records read
         if (use_bins) {
+            // one-hot row records: pick j's window row and column, then tot_j
+            float* rows = merge.wide;
+            {
+                float* own = rows + P.q * kBwdRowFloats;
+                float4* o4 = reinterpret_cast<float4*>(own);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = 4 * kp + v;
-                if (i < kBinG && ij < kBinG) {
-#pragma unroll
-                    for (int c = 0; c < C; ++c) vals[v][c] = bins[(i * kBinG + ij) * C + c];
+                for (int k = 0; k < 2 * kBinG / 4; ++k) o4[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (P.valid) {
+                    own[((sy - (uint32_t)base_y) & my)] = 1.0f;
+                    own[kBinG + ((sx - (uint32_t)base_x) & mx)] = 1.0f;
                 }
+                float qv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int c = 0; c < C; ++c) qv[c] = tot[c];
+                o4[2 * kBinG / 4] = make_float4(qv[0], qv[1], qv[2], qv[3]);
             }
+            wave_lds_sync();
+            v4f acc[C];
+            window_product<C>(rows, ij, kp, acc);
+            wave_lds_sync();                     // row records read before the merge reuses them
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int c = 0; c < C; ++c) vals[v][c] = acc[c][v];
+        } else if (P.valid) {
+            atomic_texel<C>(grad, t.w, s, tot, 1.0f);
         }
     }
 
@@ -1605,14 +1677,14 @@ __device__ __forceinline__ float4 load_dout(const Args& a, int slot, const Pixel
 constexpr int kBwdWaves = 5;
 
 template <int FILT, int MODE>
-__global__ __launch_bounds__(kThreads, kBwdWaves) void backward_kernel(Args a) {
+__global__ __launch_bounds__(kThreads, MODE == kModeRecords ? 4 : kBwdWaves) void backward_kernel(Args a) {
     // per wave: bin sums of 1/p or 64 {s, r} records, then the wide area
     // (window bins, row records); the wide areas of the workgroup together
     // form the merge area
     constexpr int kPerWave = kBwdNbFloats;
     static_assert(kPerWave >= 128, "64 {s, r} records fit");
     static_assert(kMergeW * kMergeH * 4 <= kWavesPerGroup * kBwdWideFloats, "merge area fits");
-    static_assert(kBins * 4 <= kBwdWideFloats, "window bins fit");
+    static_assert(16 * 64 + 64 * 4 <= kBwdWideFloats, "member coefficients and totals fit");
     __shared__ __align__(16) float lds_all[kWavesPerGroup * (kPerWave + kBwdWideFloats)];
     __shared__ int merge_info[kWavesPerGroup * 4];
     float* wide_all = lds_all + kWavesPerGroup * kPerWave;
@@ -1625,6 +1697,11 @@ __global__ __launch_bounds__(kThreads, kBwdWaves) void backward_kernel(Args a) {
     P.u = uv.x;
     P.v = uv.y;
     float* lds = lds_all + (threadIdx.x >> 6) * kPerWave;
+    // window footprints: the pixels whose window holds this one, for the gather
+    uint64_t rev = 0ull;
+    if constexpr (MODE == kModeRecords) {
+        if (a.footprint != STF_FP_LUT) rev = reverse_members(a.footprint, P.lx, P.ly);
+    }
     SelCtx<FILT> ctx;
     // dL/dout of the pixel, one vector load per slot, the next slot's
     // requested before the current slot's work
@@ -1635,9 +1712,9 @@ __global__ __launch_bounds__(kThreads, kBwdWaves) void backward_kernel(Args a) {
         keyed_uniforms(a, P, slot, hx, hy);
         ctx.update(P, a.tex[slot].w, a.tex[slot].h);
         const int ch = a.tex[slot].ch;
-        if (ch == 4) backward_slot<FILT, MODE, 4>(a, slot, P, ctx, hx, hy, gcur, lds, merge);
-        else if (ch == 2) backward_slot<FILT, MODE, 2>(a, slot, P, ctx, hx, hy, gcur, lds, merge);
-        else backward_slot<FILT, MODE, 1>(a, slot, P, ctx, hx, hy, gcur, lds, merge);
+        if (ch == 4) backward_slot<FILT, MODE, 4>(a, slot, P, ctx, hx, hy, gcur, lds, merge, rev);
+        else if (ch == 2) backward_slot<FILT, MODE, 2>(a, slot, P, ctx, hx, hy, gcur, lds, merge, rev);
+        else backward_slot<FILT, MODE, 1>(a, slot, P, ctx, hx, hy, gcur, lds, merge, rev);
         gcur = gnext;
     }
 }

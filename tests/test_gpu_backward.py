@@ -65,12 +65,15 @@ def test_backward_other_footprints(fp):
     assert _adjoint_case(tex, uv, g, fp, "bicubic", 7, 1, lut) <= 1e-5
 
 
-@pytest.mark.parametrize("filt", ["bilinear", "bicubic"])
-def test_backward_perspective_with_fallback_waves(filt):
+@pytest.mark.parametrize("filt,fp", [("bilinear", "tile8x8"), ("bicubic", "tile8x8"), ("bicubic", "self"),
+                                     ("bilinear", "quad2x2"), ("bicubic", "wave2x2"), ("bicubic", "square4x4"),
+                                     ("bilinear", "lut")])
+def test_backward_perspective_with_fallback_waves(filt, fp):
     """A perspective plane from strong magnification down to minification:
     near the top the tile's supports leave the 12x12 bin window and those
-    waves take the record fallback (checked here with the oracle's own
-    coordinates), next to waves whose windows merge per workgroup."""
+    waves send their gradients with global atomics (the whole tile through
+    its record fallback; checked here with the oracle's own coordinates),
+    next to waves whose windows merge per workgroup."""
     rng = np.random.default_rng(4)
     tex = rng.random((256, 256, 4)).astype(np.float32)
     uv, _, _, _ = w.perspective_plane(160, 96, 256, 0.25, 8.0)
@@ -82,7 +85,20 @@ def test_backward_perspective_with_fallback_waves(filt):
     spread = np.maximum(sx.max(-1) - sx.min(-1), sy.max(-1) - sy.min(-1))
     assert np.any(spread > 12 - n) and np.any(spread <= 12 - n)     # both paths occur
     g = rng.standard_normal((96, 160, 4)).astype(np.float32)
-    assert _adjoint_case(tex, uv, g, "tile8x8", filt, 3, 0) <= 1e-5
+    lut = rng.integers(0, 64, (64, 5)).astype(np.uint8) if fp == "lut" else None
+    assert _adjoint_case(tex, uv, g, fp, filt, 3, 0, lut) <= 1e-5
+
+
+@pytest.mark.parametrize("fp", ["self", "quad2x2", "wave2x2", "square3x3", "lut", "tile8x8"])
+def test_backward_texture_smaller_than_window(fp):
+    """An 8x8 texture (smaller than the 12x12 window, so no wave bins its
+    gradients), wrapped over a minified screen with a ragged edge."""
+    rng = np.random.default_rng(21)
+    tex = rng.random((8, 8, 4)).astype(np.float32)
+    uv = w.small_screen(43, 21, 8, 0.7, offset_seed=2)
+    g = rng.standard_normal(uv.shape[:2] + (4,)).astype(np.float32)
+    lut = rng.integers(0, 64, (64, 6)).astype(np.uint8) if fp == "lut" else None
+    assert _adjoint_case(tex, uv, g, fp, "bilinear", 11, 2, lut) <= 1e-5
 
 
 def test_backward_central_differences_32x32():

@@ -134,16 +134,18 @@ def test_other_kernels_use_no_scratch(kernels):
         # forward kernels: above; the latent Eq. (3) kernel (16 decodes per pixel) is not budgeted
         if "forward_kernel" in name or re.search(r"reference_kernelILi\dELb1E", name):
             continue
-        # the bicubic adjoints of the record and whole-tile footprints spill a few
-        # registers at their five-wave budget (96 VGPRs)
-        limit = 32 if re.fullmatch(r"_ZN3stf15backward_kernelILi1ELi[23]EEEvNS_4ArgsE", name) else 0
+        # the bicubic whole-tile adjoint spills a few registers at its five-wave budget (96 VGPRs)
+        limit = 32 if name == "_ZN3stf15backward_kernelILi1ELi3EEEvNS_4ArgsE" else 0
         assert k[".private_segment_fixed_size"] <= limit, name
         assert not k[".uses_dynamic_stack"], name
 
 
-def test_adjoints_keep_five_waves(kernels):
+def test_adjoint_occupancy(kernels):
+    """Five waves per SIMD (96 VGPRs, five workgroups' LDS per CU); the
+    record footprints' adjoint four (128 VGPRs)."""
     for filt in (0, 1):
         for mode in range(4):
+            waves = 4 if mode == 2 else 5
             k = kernels["_ZN3stf15backward_kernelILi%dELi%dEEEvNS_4ArgsE" % (filt, mode)]
-            assert k[".vgpr_count"] + k[".agpr_count"] <= 96, (filt, mode)
-            assert k[".group_segment_fixed_size"] * 5 <= 160 * 1024, (filt, mode)   # five workgroups per CU
+            assert k[".vgpr_count"] + k[".agpr_count"] <= 512 // waves // 8 * 8, (filt, mode)
+            assert k[".group_segment_fixed_size"] * waves <= 160 * 1024, (filt, mode)
