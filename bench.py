@@ -250,8 +250,17 @@ def backward_form(torch, stf, texs, uv, steps, warmup):
     dtex = [torch.zeros((int(t.shape[0]), int(t.shape[1]), int(t.shape[2])), dtype=torch.float32, device=uv.device)
             for t in texs]
     dt = launch_time(torch, lambda: stf.backward(texs, uv, g, "tile8x8", "bicubic", 0, 0, dtex=dtex), steps, warmup, batches=5)
+    # the other footprints on the same launch (the generated LUT as in the footprint sweep)
+    lut = stf.generate_footprints(9, 32, 1.4, 10000, 30, 0)[0]
+    by_fp = {}
+    for fp in ("self", "quad2x2", "wave2x2", "square3x3", "square4x4", "lut_ps9"):
+        name, kw = ("lut", {"lut": lut}) if fp == "lut_ps9" else (fp, {})
+        t = launch_time(torch, lambda: stf.backward(texs, uv, g, name, "bicubic", 0, 0, dtex=dtex, **kw),
+                        steps, warmup, batches=3)
+        by_fp[fp] = round(t * 1e6, 1)
+    by_fp["tile8x8"] = round(dt * 1e6, 1)
     return {"avg_launch_us": round(dt * 1e6, 2), "Mpixel_s": round(H * W / dt / 1e6, 1),
-            "textures": "RGBA16F + RG16F 2048^2, FP32 gradients"}
+            "by_footprint_us": by_fp, "textures": "RGBA16F + RG16F 2048^2, FP32 gradients"}
 
 
 def shared_selection_form(torch, stf, texs, uv, ref, steps, warmup):
@@ -581,17 +590,21 @@ def latent_form(torch, stf, w, steps, warmup):
             "mfma_bf16_peak_tflops": 2500.0}
 
 
-def profile_launches(torch, stf, w, which, n=50):
+def profile_launches(torch, stf, w, which, n=50, footprint="tile8x8"):
     """n launches of one secondary workload, for kernel traces (medians over
-    at least 50 launches) and counters."""
+    at least 50 launches) and counters. `footprint` selects the adjoint's
+    footprint ('lut_ps9': the footprint sweep's generated table)."""
     dev = torch.device("cuda:0")
     if which == "backward":
         uv = torch.from_numpy(w.perspective_plane(1920, 1080, 2048, 2.0, 32.0)[0]).to(dev)
         texs = [torch.from_numpy(w.plane_albedo(0, 2048)).to(dev), torch.from_numpy(w.plane_normal(0, 2048)).to(dev)]
         g = [torch.randn((1080, 1920, int(t.shape[2])), device=dev) for t in texs]
         dtex = [torch.zeros((2048, 2048, int(t.shape[2])), device=dev) for t in texs]
+        kw = {}
+        if footprint == "lut_ps9":
+            footprint, kw = "lut", {"lut": stf.generate_footprints(9, 32, 1.4, 10000, 30, 0)[0]}
         for _ in range(n):
-            stf.backward(texs, uv, g, "tile8x8", "bicubic", 0, 0, dtex=dtex)
+            stf.backward(texs, uv, g, footprint, "bicubic", 0, 0, dtex=dtex, **kw)
     elif which == "materials":
         texs = [torch.from_numpy(np.ascontiguousarray(t)).to(dev) for t in w.material_set(0)]
         uv = torch.from_numpy(w.perspective_plane(3840, 2160, 2048, 2.0, 32.0)[0]).to(dev)
@@ -640,6 +653,9 @@ def main():
     ap.add_argument("--profile", choices=["latent", "backward", "materials", "decoder_backward"],
                     help="only run 50 launches of the latent-decoder, backward, decoder-backward or 4K four-texture workload "
                          "(for rocprofv3) and exit")
+    ap.add_argument("--footprint", default="tile8x8",
+                    choices=["self", "quad2x2", "wave2x2", "square3x3", "square4x4", "lut_ps9", "tile8x8"],
+                    help="footprint of the --profile backward launches")
     ap.add_argument("--summarize-pmc", nargs="+", metavar="CSV",
                     help="write the per-launch traffic summary from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--summarize-trace", metavar="CSV",
@@ -666,7 +682,7 @@ def main():
     stf.library()
     dev = torch.device("cuda:0")
     if args.profile:
-        profile_launches(torch, stf, w, args.profile)
+        profile_launches(torch, stf, w, args.profile, footprint=args.footprint)
         return
 
     uv_np, _, _, info = w.perspective_plane(1920, 1080, 2048, 2.0, 32.0)
