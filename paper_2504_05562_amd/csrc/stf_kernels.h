@@ -1298,10 +1298,74 @@ __device__ __forceinline__ uint64_t reverse_members(int fp, int lx, int ly) {
     return bits;
 }
 
+// Tables of at most kRevMaxK entries per pixel are gathered like the windows.
+constexpr int kRevMaxK = 16;
+
+// Where each lane's pick receives contributions from, for the gather of the
+// record footprints: window footprints as a mask of pixels, tables as a list
+// of coefficient indices m * 64 + p (pixel p's entry m names this pixel) in
+// LDS, ascending, so that the sums have a fixed order.
+struct Reverse {
+    uint64_t bits = 0ull;
+    const uint16_t* list = nullptr;
+    int at = 0, n = 0;
+};
+
+// The lists of a table footprint for the wave (once per launch): count the
+// entries naming each pixel (LDS integer atomics), prefix sums over the
+// pixels, place the entries, then each pixel sorts its own list. `tmp` holds
+// 128 ints of the wave's LDS.
+__device__ __forceinline__ void build_reverse_table(const Args& a, const Pixel& P, int* tmp, uint16_t* list,
+                                                    Reverse& rev) {
+    const int K = a.lut_k;
+    const uint8_t* row = a.lut + P.q * K;
+    int* cnt = tmp;
+    int* scan = tmp + 64;
+    cnt[P.q] = 0;
+    wave_lds_sync();
+    for (int m = 0; m < K; ++m) {
+        const int j = row[m] & 63;
+        if (j != P.q) atomicAdd(&cnt[j], 1);
+    }
+    wave_lds_sync();
+    const int n = cnt[P.q];
+    int v = n;                                    // inclusive prefix over the pixel ids
+    scan[P.q] = v;
+    wave_lds_sync();
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = P.q >= d ? scan[P.q - d] : 0;
+        wave_lds_sync();
+        v += t;
+        scan[P.q] = v;
+        wave_lds_sync();
+    }
+    const int at = v - n;
+    cnt[P.q] = at;                                // placement cursor
+    wave_lds_sync();
+    for (int m = 0; m < K; ++m) {
+        const int j = row[m] & 63;
+        if (j != P.q) list[atomicAdd(&cnt[j], 1)] = (uint16_t)(m * 64 + P.q);
+    }
+    wave_lds_sync();
+    for (int i = 1; i < n; ++i) {                 // insertion sort of the own list
+        const uint16_t x = list[at + i];
+        int k = i - 1;
+        while (k >= 0 && list[at + k] > x) {
+            list[at + k + 1] = list[at + k];
+            --k;
+        }
+        list[at + k + 1] = x;
+    }
+    wave_lds_sync();
+    rev.list = list;
+    rev.at = at;
+    rev.n = n;
+}
+
 template <int FILT, int MODE, int C>
 __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
                                               uint32_t hx, uint32_t hy, const float4& gin, float* lds,
-                                              MergeArea merge, uint64_t rev) {
+                                              MergeArea merge, const Reverse& rev) {
     constexpr int N = SelCtx<FILT>::N;
     const TexArg t = a.tex[slot];
     const int lane = lane_id();
@@ -1469,13 +1533,13 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
             // LDS: meta {s, r} [64] in the wave's small area; in the wide area
             // coef [K][64] (pixel p's f_p(s_j) r_j for its member m, zero when
             // s_j is off its support) and q [64][4] (dL/dout_p / B_p), or for a
-            // table footprint the per-lane sums [C][64]
+            // table of more than kRevMaxK entries the per-lane sums [C][64]
             uint2* meta = reinterpret_cast<uint2*>(lds);
             float* coef = merge.wide;
             float* qrec = merge.wide + 16 * 64;
             float* lane_sum = merge.wide;
             const int fp = a.footprint;
-            const bool table = fp == STF_FP_LUT;
+            const bool table = fp == STF_FP_LUT && a.lut_k > kRevMaxK;     // scattered
             if (table) {
 #pragma unroll
                 for (int c = 0; c < C; ++c) lane_sum[c * 64 + P.q] = 0.0f;
@@ -1500,8 +1564,7 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
 #pragma unroll
             for (int c = 0; c < C; ++c) tot[c] = g[c] * inv;
             if (table) {
-                // members of a table may repeat and need not be mutual: scatter
-                // through per-lane sums
+                // long tables: scatter through per-lane sums
                 if (P.valid) {
                     for (int m = 0; m < K; ++m) {
                         const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
@@ -1519,15 +1582,24 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
 #pragma unroll
                 for (int c = 0; c < C; ++c) tot[c] += lane_sum[c * 64 + P.q];
             } else {
-                // window footprints: gather from the pixels whose window holds
-                // this one (their member index follows from their window)
+                // gather from the pixels that name this one: windows (the
+                // member index follows from the naming pixel's window) or the
+                // table's lists (entries may repeat)
                 float4 q4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 if constexpr (C >= 1) q4.x = tot[0];
                 if constexpr (C >= 2) q4.y = tot[1];
                 if constexpr (C >= 4) { q4.z = tot[2]; q4.w = tot[3]; }
                 reinterpret_cast<float4*>(qrec)[P.q] = q4;
                 wave_lds_sync();
-                uint64_t bits = rev;
+                for (int e = 0; e < rev.n; ++e) {
+                    const int idx = rev.list[rev.at + e];
+                    const float k = coef[idx];
+                    const float4 qp = reinterpret_cast<const float4*>(qrec)[idx & 63];
+                    const float qc[4] = {qp.x, qp.y, qp.z, qp.w};
+#pragma unroll
+                    for (int c = 0; c < C; ++c) tot[c] = fmaf(k, qc[c], tot[c]);
+                }
+                uint64_t bits = rev.bits;
                 while (bits) {
                     const int p = (int)__builtin_ctzll(bits);
                     bits &= bits - 1ull;
@@ -1697,10 +1769,15 @@ __global__ __launch_bounds__(kThreads, MODE == kModeRecords ? 4 : kBwdWaves) voi
     P.u = uv.x;
     P.v = uv.y;
     float* lds = lds_all + (threadIdx.x >> 6) * kPerWave;
-    // window footprints: the pixels whose window holds this one, for the gather
-    uint64_t rev = 0ull;
+    // record footprints: where each pick's contributions come from, for the gather
+    __shared__ uint16_t rev_lists[MODE == kModeRecords ? kWavesPerGroup * 64 * kRevMaxK : 1];
+    Reverse rev;
     if constexpr (MODE == kModeRecords) {
-        if (a.footprint != STF_FP_LUT) rev = reverse_members(a.footprint, P.lx, P.ly);
+        if (a.footprint != STF_FP_LUT)
+            rev.bits = reverse_members(a.footprint, P.lx, P.ly);
+        else if (a.lut_k <= kRevMaxK)
+            build_reverse_table(a, P, reinterpret_cast<int*>(lds), rev_lists + (threadIdx.x >> 6) * 64 * kRevMaxK,
+                                rev);
     }
     SelCtx<FILT> ctx;
     // dL/dout of the pixel, one vector load per slot, the next slot's

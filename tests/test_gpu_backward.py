@@ -55,13 +55,16 @@ def _adjoint_case(tex, uv, g, fp, filt, seed, frame, lut=None):
     return np.max(np.abs(got - want)) / scale
 
 
-@pytest.mark.parametrize("fp", ["wave2x2", "square4x4", "lut"])
-def test_backward_other_footprints(fp):
+@pytest.mark.parametrize("fp,lut_k", [("wave2x2", 0), ("square4x4", 0), ("lut", 8), ("lut", 16), ("lut", 24)])
+def test_backward_other_footprints(fp, lut_k):
+    """Tables of up to 16 entries are gathered through per-pixel lists, longer
+    ones scattered through per-lane sums; random tables repeat entries and
+    name the pixel itself."""
     rng = np.random.default_rng(12)
     tex = rng.random((64, 64, 4)).astype(np.float32)
     uv = w.small_screen(53, 37, 64, 3.0, offset_seed=3)
     g = rng.standard_normal(uv.shape[:2] + (4,)).astype(np.float32)
-    lut = rng.integers(0, 64, (64, 8)).astype(np.uint8) if fp == "lut" else None
+    lut = rng.integers(0, 64, (64, lut_k)).astype(np.uint8) if fp == "lut" else None
     assert _adjoint_case(tex, uv, g, fp, "bicubic", 7, 1, lut) <= 1e-5
 
 
