@@ -10,7 +10,7 @@
 #include <string>
 
 #include "stf_decoder_backward.h"
-#include "stf_kernels.h"
+#include "stf_backward.h"
 #include "stf_status.h"
 
 // The whole-tile kernels keep their 64-bit sums zero between textures of one
