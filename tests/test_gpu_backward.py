@@ -104,6 +104,39 @@ def test_backward_texture_smaller_than_window(fp):
     assert _adjoint_case(tex, uv, g, fp, "bilinear", 11, 2, lut) <= 1e-5
 
 
+@pytest.mark.parametrize("fp", ["tile8x8", "self", "quad2x2", "square3x3", "lut"])
+def test_backward_full_frame_sampled_tiles(fp):
+    """The benchmarked launch (1920x1080 plane at 2x-32x, 2048^2 RGBA16F +
+    RG16F, bicubic) with dL/dout zero except on 48 sampled tiles: the adjoint
+    is linear in dL/dout, so the whole 2048^2 gradient of both textures must
+    equal the oracle adjoint of those tiles alone."""
+    uv = w.perspective_plane()[0]
+    texs = [w.plane_albedo(), w.plane_normal()]
+    H, W = uv.shape[:2]
+    rng = np.random.default_rng(31)
+    tiles_all = o.all_tiles(W, H)
+    tiles = tiles_all[np.sort(rng.choice(len(tiles_all), 48, replace=False))]
+    px = tiles[:, 0:1] * 8 + (np.arange(64) % 8)[None]
+    py = tiles[:, 1:2] * 8 + (np.arange(64) // 8)[None]
+    full, gt = [], []
+    for t in texs:
+        c = t.shape[2]
+        vals = rng.standard_normal((len(tiles), 64, c)).astype(np.float32)
+        g = np.zeros((H, W, c), np.float32)
+        g[py, px] = vals
+        full.append(g)
+        gt.append(vals)
+    lut = rng.integers(0, 64, (64, 9)).astype(np.uint8) if fp == "lut" else None
+    got = stf.backward([dev(t) for t in texs], dev(uv), [dev(g) for g in full], fp, "bicubic", 0, 0,
+                       lut=dev(lut) if lut is not None else None)
+    want = o.stf_adjoint(texs, uv, o.BICUBIC, 0, 0, fp, gt, lut=lut, tiles=tiles)
+    for slot in range(2):
+        gv = got[slot].cpu().numpy()
+        scale = np.abs(want[slot]).max()
+        assert scale > 0
+        assert np.max(np.abs(gv - want[slot])) <= 1e-5 * scale, (slot, np.max(np.abs(gv - want[slot])) / scale)
+
+
 def test_backward_central_differences_32x32():
     rng = np.random.default_rng(8)
     tex = rng.random((32, 32, 4)).astype(np.float32)
