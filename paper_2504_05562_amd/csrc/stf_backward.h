@@ -83,6 +83,69 @@ __device__ __forceinline__ void window_product(const float* rows, int ij, int kp
     }
 }
 
+// Sum of the wave's 64 pick totals per window cell: the rank-64 product of
+// one-hot rows (the pick's window row) and one-hot columns carrying the
+// totals, on v_mfma_f32_16x16x32_bf16. Each total is split exactly into
+// three BF16 parts (hi + mid + lo = the FP32 value: every part takes the
+// next 8 significant bits of the remainder), so the products are exact and
+// only the FP32 accumulation rounds; K = 64 pixels x 3 parts = 6 products
+// of 32 per channel, against 16 FP32 products of 4. LDS (the wave's wide
+// area): the picks' window rows and columns [64] bytes each (0xFF for pixels
+// off the screen, which match no cell), then the parts [C][3][64] BF16.
+// Lane l holds k-values 8 (l / 16) .. + 7 of each product for window row
+// (A) and column (B) l % 16, the same k in A and B, whatever order the
+// hardware sums them in; cell (4 (l / 16) + v, l % 16) lands in acc[c][v].
+template <int C>
+__device__ __forceinline__ void onehot_window_sum(float* wide, const Pixel& P, uint32_t cx, uint32_t cy,
+                                                  const float* tot, int ij, int kp, v4f* acc) {
+    uint8_t* rowv = reinterpret_cast<uint8_t*>(wide);
+    uint8_t* colv = rowv + 64;
+    uint16_t* part = reinterpret_cast<uint16_t*>(rowv + 128);
+    rowv[P.q] = P.valid ? (uint8_t)cy : (uint8_t)0xFF;
+    colv[P.q] = P.valid ? (uint8_t)cx : (uint8_t)0xFF;
+#pragma unroll
+    for (int c = 0; c < C; c += 2) {
+        // two channels per conversion (round to nearest even)
+        f32x2 x = {tot[c], c + 1 < C ? tot[c + 1] : 0.0f};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t b = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf16x2));
+            part[(c * 3 + k) * 64 + P.q] = (uint16_t)(b & 0xFFFFu);
+            if (c + 1 < C) part[((c + 1) * 3 + k) * 64 + P.q] = (uint16_t)(b >> 16);
+            const f32x2 h = {__uint_as_float(b << 16), __uint_as_float(b & 0xFFFF0000u)};
+            x = x - h;                               // exact: the remainder has at most 16 significant bits
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int k0 = 32 * t + 8 * kp;
+        const uint2 r8 = *reinterpret_cast<const uint2*>(rowv + k0);
+        const uint2 c8 = *reinterpret_cast<const uint2*>(colv + k0);
+        u32x4 a, m;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const uint32_t rw = (h < 2 ? r8.x : r8.y) >> (16 * (h & 1));
+            const uint32_t cw = (h < 2 ? c8.x : c8.y) >> (16 * (h & 1));
+            a[h] = (((rw & 0xFFu) == (uint32_t)ij) ? 0x3F80u : 0u) |
+                   ((((rw >> 8) & 0xFFu) == (uint32_t)ij) ? 0x3F800000u : 0u);      // BF16 1.0
+            m[h] = (((cw & 0xFFu) == (uint32_t)ij) ? 0xFFFFu : 0u) |
+                   ((((cw >> 8) & 0xFFu) == (uint32_t)ij) ? 0xFFFF0000u : 0u);
+        }
+        const bf16x8 av = __builtin_bit_cast(bf16x8, a);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const u32x4 v = *reinterpret_cast<const u32x4*>(part + (c * 3 + k) * 64 + k0) & m;
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, v), acc[c], 0, 0, 0);
+            }
+    }
+    wave_lds_sync();                               // read before the merge reuses the area
+}
+
 // Pixels of the wave whose window footprint holds this lane's pixel (lx, ly),
 // itself excluded: bit p for tile pixel p (row-major).
 __device__ __forceinline__ uint64_t reverse_members(int fp, int lx, int ly) {
@@ -413,26 +476,9 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
             wave_lds_sync();                     // sums and records read before the row records
         }
         if (use_bins) {
-            // one-hot row records: pick j's window row and column, then tot_j
-            float* rows = merge.wide;
-            {
-                float* own = rows + P.q * kBwdRowFloats;
-                float4* o4 = reinterpret_cast<float4*>(own);
-#pragma unroll
-                for (int k = 0; k < 2 * kBinG / 4; ++k) o4[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (P.valid) {
-                    own[((sy - (uint32_t)base_y) & my)] = 1.0f;
-                    own[kBinG + ((sx - (uint32_t)base_x) & mx)] = 1.0f;
-                }
-                float qv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-                for (int c = 0; c < C; ++c) qv[c] = tot[c];
-                o4[2 * kBinG / 4] = make_float4(qv[0], qv[1], qv[2], qv[3]);
-            }
-            wave_lds_sync();
             v4f acc[C];
-            window_product<C>(rows, ij, kp, acc);
-            wave_lds_sync();                     // row records read before the merge reuses them
+            onehot_window_sum<C>(merge.wide, P, (sx - (uint32_t)base_x) & mx, (sy - (uint32_t)base_y) & my, tot,
+                                 ij, kp, acc);
 #pragma unroll
             for (int v = 0; v < 4; ++v)
 #pragma unroll
