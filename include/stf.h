@@ -236,6 +236,8 @@ int stf_filter_reference(const stf_texture* tex, int32_t ntex, const stf_screen*
  *          dense (pitch = width * C_t * 4); ACCUMULATED into (+=), so clear
  *          it first for a plain gradient. Summation order is not fixed
  *          (floating-point atomics): results agree to rounding, not bits.
+ *          dL/dout must be finite: the per-window sums multiply exact zeros
+ *          by it, so an infinity or NaN can reach other texels of a window.
  * Same p and r as the forward call being differentiated. Latent formats
  * are rejected (STF_EUNSUPPORTED). A per-channel scale multiplies dL/dout,
  * so dtex is the gradient with respect to the texel before its scale.
@@ -298,10 +300,11 @@ typedef struct stf_mlp_grad {
 
 /* Device workspace stf_backward_decoder needs for these textures (latent
  * formats, power-of-two sizes), or -1 if they are invalid: per texture a
- * dense FP32 texel gradient (16 bytes per texel) and the list of its blocks
- * of 32 texels that a gradient reaches (about 4 bytes per block), then per-wave
- * weight-gradient slots (about 20 KB per wave, at most 2048 waves per
- * texture). */
+ * dense FP32 texel gradient (16 bytes per texel) followed by one bit per
+ * block of 16 texels, and the list of the blocks a gradient reaches (4 bytes
+ * per block); then one weight-gradient slot (about 20 KB) per workgroup of
+ * the decoder kernel (at most 512 per texture) and the partial sums of their
+ * reduction. */
 int64_t stf_backward_decoder_workspace_bytes(const stf_texture* tex, int32_t ntex);
 
 /*
