@@ -8,12 +8,15 @@
 
 namespace stf {
 
-// backward bins, per wave: Nb float [kBins] (the sums of 1/p), and a wide
-// area that first holds their exact u64 accumulators and, once they are
+// LDS per wave: a small area (the whole tile's Nb float [kBins], the sums of
+// 1/p; or 64 {s, r} records) and a wide area. For the whole tile the wide
+// area first holds the exact u64 accumulators of Nb and, once they are
 // converted, one row record per tile pixel for the matrix cores: its weights
 // along the window's rows and columns, zero outside its support (kBinG
-// each), and its four scaled gradients. The workgroup's wide areas are
-// contiguous; after the products they hold the workgroup's merge area.
+// each), and its four scaled gradients. For the other footprints it holds
+// the members' coefficients and the pixels' scaled gradients of the gather,
+// then the one-hot operands of the window sum. The workgroup's wide areas
+// are contiguous; after the products they hold the workgroup's merge area.
 constexpr int kBwdNbFloats = (kBins + 3) & ~3;
 constexpr int kBwdRowFloats = 2 * kBinG + 4;
 constexpr int kBwdWideFloats = kBins * 2 > 64 * kBwdRowFloats ? kBins * 2 : 64 * kBwdRowFloats;
@@ -43,19 +46,19 @@ __device__ __forceinline__ void atomic_texel(float* g, int tw, uint32_t s, const
     for (int c = 0; c < C; ++c) unsafeAtomicAdd(p + c, v[c] * scale);
 }
 
-// Workgroup merge of the whole-tile adjoint: the four tiles of a workgroup
-// sit side by side, so their bin windows overlap (fully at high
-// magnification). Each wave adds its window's sums into one kMergeW x
+// Workgroup merge of the adjoint windows: the four tiles of a workgroup sit
+// side by side, so their bin windows overlap (fully at high magnification). Each wave adds its window's sums into one kMergeW x
 // kMergeH texel area in LDS covering all four, and the workgroup flushes that
 // area with one global atomic per touched texel and channel, instead of each
 // wave flushing its own window: the global FP32 atomics, which bound this
 // kernel, drop by the overlap. A workgroup whose windows do not fit the area
-// (or whose waves fall back to records) flushes per wave.
+// flushes per wave; waves whose supports leave their window send their
+// gradients with global atomics and take no part.
 constexpr int kMergeW = 32, kMergeH = 16;
 
 struct MergeArea {
     float* v;                // [kMergeH * kMergeW][C] sums (over the workgroup's wide areas)
-    int* info;               // per wave: ok, base_x, base_y
+    int* info;               // per wave: contributes, base_x, base_y
     float* wide;             // this wave's wide area (kBwdWideFloats)
 };
 
@@ -113,7 +116,7 @@ __device__ __forceinline__ void onehot_window_sum(float* wide, const Pixel& P, u
             part[(c * 3 + k) * 64 + P.q] = (uint16_t)(b & 0xFFFFu);
             if (c + 1 < C) part[((c + 1) * 3 + k) * 64 + P.q] = (uint16_t)(b >> 16);
             const f32x2 h = {__uint_as_float(b << 16), __uint_as_float(b & 0xFFFF0000u)};
-            x = x - h;                               // exact: the remainder has at most 16 significant bits
+            x = x - h;     // exact: at most 16, then 8 significant bits remain, so the third part is exact
         }
     }
     wave_lds_sync();
@@ -400,8 +403,8 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
             float* qrec = merge.wide + 16 * 64;
             float* lane_sum = merge.wide;
             const int fp = a.footprint;
-            const bool table = fp == STF_FP_LUT && a.lut_k > kRevMaxK;     // scattered
-            if (table) {
+            const bool scatter = fp == STF_FP_LUT && a.lut_k > kRevMaxK;     // long tables
+            if (scatter) {
 #pragma unroll
                 for (int c = 0; c < C; ++c) lane_sum[c * 64 + P.q] = 0.0f;
             }
@@ -419,13 +422,13 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                         k = ctx.x.wsel(dx) * ctx.y.wsel(dy) * __uint_as_float(mj.y);
                 }
                 B += k;
-                if (!table) coef[m * 64 + P.q] = k;
+                if (!scatter) coef[m * 64 + P.q] = k;
             }
             const float inv = P.valid ? fast_rcp(B) : 0.0f;
 #pragma unroll
             for (int c = 0; c < C; ++c) tot[c] = g[c] * inv;
-            if (table) {
-                // long tables: scatter through per-lane sums
+            if (scatter) {
+                // long tables: through per-lane sums
                 if (P.valid) {
                     for (int m = 0; m < K; ++m) {
                         const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
@@ -473,7 +476,7 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                     for (int c = 0; c < C; ++c) tot[c] = fmaf(k, qc[c], tot[c]);
                 }
             }
-            wave_lds_sync();                     // sums and records read before the row records
+            wave_lds_sync();                     // read before the window sum reuses the area
         }
         if (use_bins) {
             v4f acc[C];
