@@ -1,4 +1,4 @@
-"""The filter calls under HIP graph capture (the benchmark times its launches
+"""The filter and adjoint calls under HIP graph capture (the benchmark times its launches
 as one graph): the library launches on the caller's stream and allocates
 nothing, so the calls can be captured. Every replay -- with eager work,
 cleared outputs and synchronisations between the replays -- must equal the
@@ -59,3 +59,33 @@ def test_graph_replays_equal_eager(kind):
         for k, outs in enumerate(sets):
             for o, e in zip(outs, eager[k]):
                 assert torch.equal(o, e), (kind, rep, k)
+
+
+@pytest.mark.parametrize("fp", ["tile8x8", "self", "square3x3"])
+def test_graph_replays_of_the_adjoint(fp):
+    """stf_backward under capture: every replay (outputs cleared by a fill
+    kernel, eager work in between) equals the eager adjoint to FP32 rounding
+    (its global atomics sum in no fixed order)."""
+    uv, texs = _inputs()
+    H, W = uv.shape[:2]
+    rng = np.random.default_rng(5)
+    g = [torch.from_numpy(rng.standard_normal((H, W, int(t.shape[2]))).astype(np.float32)).cuda() for t in texs]
+    dtex = [torch.zeros(t.shape[:2] + (int(t.shape[2]),), device="cuda") for t in texs]
+    stf.backward(texs, uv, g, fp, "bicubic", 3, 1, dtex=dtex)
+    torch.cuda.synchronize()
+    eager = [d.clone() for d in dtex]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        stf.backward(texs, uv, g, fp, "bicubic", 3, 1, dtex=dtex)
+    other = [torch.zeros_like(d) for d in dtex]
+    for rep in range(4):
+        for d in dtex:
+            d.zero_()
+        stf.backward(texs, uv, g, fp, "bicubic", 9 + rep, 0, dtex=other)   # eager work between the replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for d, e in zip(dtex, eager):
+            scale = float(e.abs().max())
+            assert scale > 0
+            assert float((d - e).abs().max()) <= 1e-5 * scale, (fp, rep)
