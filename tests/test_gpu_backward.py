@@ -137,6 +137,31 @@ def test_backward_full_frame_sampled_tiles(fp):
         assert np.max(np.abs(gv - want[slot])) <= 1e-5 * scale, (slot, np.max(np.abs(gv - want[slot])) / scale)
 
 
+@pytest.mark.parametrize("fp", ["self", "quad2x2", "square3x3", "lut"])
+def test_backward_positive_gradients_of_wide_range(fp):
+    """Positive dL/dout spread over 2^-40 .. 2^40: every contribution to a
+    texel is positive, so each texel's gradient must match the oracle to FP32
+    rounding relative to itself (the window sums split each total into three
+    BF16 parts; two parts, or a lost remainder, would fail here)."""
+    rng = np.random.default_rng(17)
+    tex = rng.random((64, 64, 4)).astype(np.float32)
+    uv = w.small_screen(48, 40, 64, 2.5, offset_seed=5)
+    g = np.exp2(rng.uniform(-40, 40, uv.shape[:2] + (4,))).astype(np.float32)
+    lut = rng.integers(0, 64, (64, 7)).astype(np.uint8) if fp == "lut" else None
+    H, W = uv.shape[:2]
+    got = stf.backward([dev(tex)], dev(uv), [dev(g)], fp, "bilinear", 2, 0,
+                       lut=dev(lut) if lut is not None else None)[0].cpu().numpy()
+    tiles = o.all_tiles(W, H)
+    px = tiles[:, 0:1] * 8 + (np.arange(64) % 8)[None]
+    py = tiles[:, 1:2] * 8 + (np.arange(64) // 8)[None]
+    valid = (px < W) & (py < H)
+    gt = np.where(valid[..., None], g[np.minimum(py, H - 1), np.minimum(px, W - 1)], 0.0)
+    want = o.stf_adjoint([tex], uv, o.BILINEAR, 2, 0, fp, [gt], lut=lut)[0]
+    assert np.array_equal(got > 0, want > 0)
+    nz = want > 0
+    assert np.max(np.abs(got[nz] - want[nz]) / want[nz]) <= 1e-5
+
+
 def test_backward_central_differences_32x32():
     rng = np.random.default_rng(8)
     tex = rng.random((32, 32, 4)).astype(np.float32)
