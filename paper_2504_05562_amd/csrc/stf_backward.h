@@ -166,14 +166,28 @@ __device__ __forceinline__ uint64_t reverse_members(int fp, int lx, int ly) {
 constexpr int kRevMaxK = 16;
 
 // Where each lane's pick receives contributions from, for the gather of the
-// record footprints: window footprints as a mask of pixels, tables as a list
+// record footprints: square windows as a rectangle of pixels, the other
+// windows as a mask of pixels, tables as a list
 // of coefficient indices m * 64 + p (pixel p's entry m names this pixel) in
 // LDS, ascending, so that the sums have a fixed order.
 struct Reverse {
     uint64_t bits = 0ull;
+    uint32_t rect = 0u;      // square windows: naming pixels x0 | x1 << 4 | y0 << 8 | y1 << 12 (inclusive)
     const uint16_t* list = nullptr;
     int at = 0, n = 0;
 };
+
+// Square windows are separable: the pixels whose window holds this one form
+// a rectangle of tile pixels (origins clamp(p - 1, 0, 8 - n) per axis).
+__device__ __forceinline__ uint32_t reverse_rect(int n, int lx, int ly) {
+    int x0 = 8, x1 = -1, y0 = 8, y1 = -1;
+    for (int p = 0; p < 8; ++p) {
+        const int o = min(max(p - 1, 0), 8 - n);
+        if (o <= lx && lx < o + n) { x0 = min(x0, p); x1 = max(x1, p); }
+        if (o <= ly && ly < o + n) { y0 = min(y0, p); y1 = max(y1, p); }
+    }
+    return (uint32_t)x0 | ((uint32_t)x1 << 4) | ((uint32_t)y0 << 8) | ((uint32_t)y1 << 12);
+}
 
 // The lists of a table footprint for the wave (once per launch): count the
 // entries naming each pixel (LDS integer atomics), prefix sums over the
@@ -412,8 +426,9 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
             wave_lds_sync();
             const int K = footprint_size(fp, a.lut_k);
             float B = 1.0f;
-            for (int m = 0; m < K; ++m) {
-                const int j = member_id(fp, P.lx, P.ly, m, a.lut, a.lut_k, P.q);
+            // member m's coefficient f_p(s_j) r_j (zero for the pixel itself
+            // and for picks off its support)
+            auto member = [&](int m, int j) {
                 float k = 0.0f;
                 if (j != P.q) {
                     const uint2 mj = meta[j];
@@ -423,6 +438,15 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                 }
                 B += k;
                 if (!scatter) coef[m * 64 + P.q] = k;
+            };
+            if (fp == STF_FP_LUT) {
+                for (int m = 0; m < K; ++m) member(m, a.lut[P.q * a.lut_k + m] & 63);
+            } else {
+                // windows: origin and size once, then its rows and columns
+                int ox, oy, n;
+                window_of(fp, P.lx, P.ly, ox, oy, n);
+                for (int wy = 0; wy < n; ++wy)
+                    for (int wx = 0; wx < n; ++wx) member(wy * n + wx, (oy + wy) * 8 + ox + wx);
             }
             const float inv = P.valid ? fast_rcp(B) : 0.0f;
 #pragma unroll
@@ -462,6 +486,23 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                     const float qc[4] = {qp.x, qp.y, qp.z, qp.w};
 #pragma unroll
                     for (int c = 0; c < C; ++c) tot[c] = fmaf(k, qc[c], tot[c]);
+                }
+                if (fp == STF_FP_SQUARE3X3 || fp == STF_FP_SQUARE4X4) {
+                    const int n = fp == STF_FP_SQUARE3X3 ? 3 : 4;
+                    const int x0 = (int)(rev.rect & 15u), x1 = (int)((rev.rect >> 4) & 15u);
+                    const int y0 = (int)((rev.rect >> 8) & 15u), y1 = (int)(rev.rect >> 12);
+                    for (int py = y0; py <= y1; ++py) {
+                        const int row = (P.ly - min(max(py - 1, 0), 8 - n)) * n + P.lx;
+                        for (int px = x0; px <= x1; ++px) {
+                            const int p = py * 8 + px;
+                            if (p == P.q) continue;
+                            const float k = coef[(row - min(max(px - 1, 0), 8 - n)) * 64 + p];
+                            const float4 qp = reinterpret_cast<const float4*>(qrec)[p];
+                            const float qc[4] = {qp.x, qp.y, qp.z, qp.w};
+#pragma unroll
+                            for (int c = 0; c < C; ++c) tot[c] = fmaf(k, qc[c], tot[c]);
+                        }
+                    }
                 }
                 uint64_t bits = rev.bits;
                 while (bits) {
@@ -620,7 +661,9 @@ __global__ __launch_bounds__(kThreads, MODE == kModeRecords ? 4 : kBwdWaves) voi
     __shared__ uint16_t rev_lists[MODE == kModeRecords ? kWavesPerGroup * 64 * kRevMaxK : 1];
     Reverse rev;
     if constexpr (MODE == kModeRecords) {
-        if (a.footprint != STF_FP_LUT)
+        if (a.footprint == STF_FP_SQUARE3X3 || a.footprint == STF_FP_SQUARE4X4)
+            rev.rect = reverse_rect(a.footprint == STF_FP_SQUARE3X3 ? 3 : 4, P.lx, P.ly);
+        else if (a.footprint != STF_FP_LUT)
             rev.bits = reverse_members(a.footprint, P.lx, P.ly);
         else if (a.lut_k <= kRevMaxK)
             build_reverse_table(a, P, reinterpret_cast<int*>(lds), rev_lists + (threadIdx.x >> 6) * 64 * kRevMaxK,

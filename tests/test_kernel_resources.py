@@ -134,8 +134,8 @@ def test_other_kernels_use_no_scratch(kernels):
         # forward kernels: above; the latent Eq. (3) kernel (16 decodes per pixel) is not budgeted
         if "forward_kernel" in name or re.search(r"reference_kernelILi\dELb1E", name):
             continue
-        # the bicubic quad and whole-tile adjoints spill a few registers at their five-wave budget (96 VGPRs)
-        limit = 32 if re.fullmatch(r"_ZN3stf15backward_kernelILi1ELi[13]EEEvNS_4ArgsE", name) else 0
+        # the bicubic exchange adjoints spill a few registers at their budgets (96 VGPRs, 128 for the records)
+        limit = 32 if re.fullmatch(r"_ZN3stf15backward_kernelILi1ELi[123]EEEvNS_4ArgsE", name) else 0
         assert k[".private_segment_fixed_size"] <= limit, name
         assert not k[".uses_dynamic_stack"], name
 
