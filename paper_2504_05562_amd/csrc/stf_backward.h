@@ -39,6 +39,24 @@ static_assert(kBwdNbFloats % 4 == 0 && kBwdRowFloats % 4 == 0 && kBwdWideFloats 
 // rows and columns). The four windows of a workgroup are merged in LDS and
 // flushed with one global atomic per touched texel and channel.
 
+// Workgroup of the launch grid this workgroup works on, renumbered so that
+// each XCD runs one contiguous part of the grid in row-major order. The
+// chip's eight XCDs take the workgroups of a launch round-robin by linear id
+// and each has its own L2; neighbouring workgroups add into the same
+// gradient texels, whose atomics then stay in one L2 (the forward kernels,
+// which only read, measured slower with it). XCD x (linear ids x, x + 8, ...)
+// gets ids x q + min(x, r) onward, with q, r the quotient and remainder of
+// the grid size by 8: a bijection.
+constexpr unsigned kXcds = 8;
+
+__device__ __forceinline__ void xcd_block(int& bx, int& by) {
+    const unsigned total = gridDim.x * gridDim.y, id = blockIdx.y * gridDim.x + blockIdx.x;
+    const unsigned x = id % kXcds, q = total / kXcds, r = total % kXcds;
+    const unsigned v = x * q + min(x, r) + id / kXcds;
+    bx = (int)(v % gridDim.x);
+    by = (int)(v / gridDim.x);
+}
+
 template <int C>
 __device__ __forceinline__ void atomic_texel(float* g, int tw, uint32_t s, const float* v, float scale) {
     float* p = g + ((int64_t)(s >> 16) * tw + (s & 0xFFFFu)) * C;
@@ -652,7 +670,9 @@ __global__ __launch_bounds__(kThreads, MODE == kModeRecords ? 4 : kBwdWaves) voi
     // the workgroup merges behind barriers: a wave whose tile column is off
     // screen stays (every lane off screen, nothing added)
     Pixel P;
-    place_pixel(a, blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6), blockIdx.y, P);
+    int bx, by;
+    xcd_block(bx, by);
+    place_pixel(a, bx * kWavesPerGroup + (threadIdx.x >> 6), by, P);
     const v2f uv = load_uv(a, P.px, P.py);
     P.u = uv.x;
     P.v = uv.y;
