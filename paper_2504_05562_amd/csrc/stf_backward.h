@@ -167,16 +167,20 @@ __device__ __forceinline__ void onehot_window_sum(float* wide, const Pixel& P, u
     wave_lds_sync();                               // read before the merge reuses the area
 }
 
-// Pixels of the wave whose window footprint holds this lane's pixel (lx, ly),
-// itself excluded: bit p for tile pixel p (row-major).
+// Pixels of the wave whose 2x2w window holds this lane's pixel (lx, ly),
+// itself excluded: bit p for tile pixel p (row-major). A 2x2w window starts
+// at most one pixel before its own pixel per axis (its origin is the pixel's
+// coordinate or the one before, clamped to 0..6), so only the pixels within
+// one of (lx, ly) per axis can hold it.
 __device__ __forceinline__ uint64_t reverse_members(int fp, int lx, int ly) {
     uint64_t bits = 0ull;
-    for (int p = 0; p < 64; ++p) {
-        int ox, oy, n;
-        window_of(fp, p & 7, p >> 3, ox, oy, n);
-        if ((uint32_t)(lx - ox) < (uint32_t)n && (uint32_t)(ly - oy) < (uint32_t)n && p != ly * 8 + lx)
-            bits |= 1ull << p;
-    }
+    for (int py = max(ly - 1, 0); py <= min(ly + 1, 7); ++py)
+        for (int px = max(lx - 1, 0); px <= min(lx + 1, 7); ++px) {
+            int ox, oy, n;
+            window_of(fp, px, py, ox, oy, n);
+            if ((uint32_t)(lx - ox) < (uint32_t)n && (uint32_t)(ly - oy) < (uint32_t)n && (px != lx || py != ly))
+                bits |= 1ull << (py * 8 + px);
+        }
     return bits;
 }
 
