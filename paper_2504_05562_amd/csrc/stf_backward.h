@@ -211,14 +211,13 @@ __device__ __forceinline__ uint32_t reverse_rect(int n, int lx, int ly) {
     return (uint32_t)x0 | ((uint32_t)x1 << 4) | ((uint32_t)y0 << 8) | ((uint32_t)y1 << 12);
 }
 
-// The lists of a table footprint for the wave (once per launch): count the
-// entries naming each pixel (LDS integer atomics), prefix sums over the
-// pixels, place the entries, then each pixel sorts its own list. `tmp` holds
-// 128 ints of the wave's LDS.
-__device__ __forceinline__ void build_reverse_table(const Args& a, const Pixel& P, int* tmp, uint16_t* list,
-                                                    Reverse& rev) {
-    const int K = a.lut_k;
-    const uint8_t* row = a.lut + P.q * K;
+// The lists of a table footprint (`lut`, [64][K] in LDS) for the wave (once
+// per launch): count the entries naming each pixel (LDS integer atomics),
+// prefix sums over the pixels, place the entries, then each pixel sorts its
+// own list. `tmp` holds 128 ints of the wave's LDS.
+__device__ __forceinline__ void build_reverse_table(int K, const uint8_t* lut, const Pixel& P, int* tmp,
+                                                    uint16_t* list, Reverse& rev) {
+    const uint8_t* row = lut + P.q * K;
     int* cnt = tmp;
     int* scan = tmp + 64;
     cnt[P.q] = 0;
@@ -265,7 +264,7 @@ __device__ __forceinline__ void build_reverse_table(const Args& a, const Pixel& 
 template <int FILT, int MODE, int C>
 __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pixel& P, const SelCtx<FILT>& ctx,
                                               uint32_t hx, uint32_t hy, const float4& gin, float* lds,
-                                              MergeArea merge, const Reverse& rev) {
+                                              MergeArea merge, const Reverse& rev, const uint8_t* lut_lds) {
     constexpr int N = SelCtx<FILT>::N;
     const TexArg t = a.tex[slot];
     const int lane = lane_id();
@@ -461,8 +460,10 @@ __device__ __forceinline__ void backward_slot(const Args& a, int slot, const Pix
                 B += k;
                 if (!scatter) coef[m * 64 + P.q] = k;
             };
-            if (fp == STF_FP_LUT) {
-                for (int m = 0; m < K; ++m) member(m, a.lut[P.q * a.lut_k + m] & 63);
+            if (fp == STF_FP_LUT && scatter) {
+                for (int m = 0; m < K; ++m) member(m, a.lut[P.q * K + m] & 63);
+            } else if (fp == STF_FP_LUT) {
+                for (int m = 0; m < K; ++m) member(m, lut_lds[P.q * K + m] & 63);     // staged in LDS
             } else {
                 // windows: origin and size once, then its rows and columns
                 int ox, oy, n;
@@ -681,17 +682,24 @@ __global__ __launch_bounds__(kThreads, MODE == kModeRecords ? 4 : kBwdWaves) voi
     P.u = uv.x;
     P.v = uv.y;
     float* lds = lds_all + (threadIdx.x >> 6) * kPerWave;
-    // record footprints: where each pick's contributions come from, for the gather
+    // record footprints: where each pick's contributions come from, for the
+    // gather; tables of at most kRevMaxK entries are staged in LDS (every
+    // thread of the workgroup reaches the barrier)
     __shared__ uint16_t rev_lists[MODE == kModeRecords ? kWavesPerGroup * 64 * kRevMaxK : 1];
+    __shared__ uint8_t lut_lds[MODE == kModeRecords ? 64 * kRevMaxK : 1];
     Reverse rev;
     if constexpr (MODE == kModeRecords) {
+        if (a.footprint == STF_FP_LUT && a.lut_k <= kRevMaxK) {
+            for (int i = threadIdx.x; i < 64 * a.lut_k; i += kThreads) lut_lds[i] = a.lut[i];
+            __syncthreads();
+        }
         if (a.footprint == STF_FP_SQUARE3X3 || a.footprint == STF_FP_SQUARE4X4)
             rev.rect = reverse_rect(a.footprint == STF_FP_SQUARE3X3 ? 3 : 4, P.lx, P.ly);
         else if (a.footprint != STF_FP_LUT)
             rev.bits = reverse_members(a.footprint, P.lx, P.ly);
         else if (a.lut_k <= kRevMaxK)
-            build_reverse_table(a, P, reinterpret_cast<int*>(lds), rev_lists + (threadIdx.x >> 6) * 64 * kRevMaxK,
-                                rev);
+            build_reverse_table(a.lut_k, lut_lds, P, reinterpret_cast<int*>(lds),
+                                rev_lists + (threadIdx.x >> 6) * 64 * kRevMaxK, rev);
     }
     SelCtx<FILT> ctx;
     // dL/dout of the pixel, one vector load per slot, the next slot's
@@ -703,9 +711,9 @@ __global__ __launch_bounds__(kThreads, MODE == kModeRecords ? 4 : kBwdWaves) voi
         keyed_uniforms(a, P, slot, hx, hy);
         ctx.update(P, a.tex[slot].w, a.tex[slot].h);
         const int ch = a.tex[slot].ch;
-        if (ch == 4) backward_slot<FILT, MODE, 4>(a, slot, P, ctx, hx, hy, gcur, lds, merge, rev);
-        else if (ch == 2) backward_slot<FILT, MODE, 2>(a, slot, P, ctx, hx, hy, gcur, lds, merge, rev);
-        else backward_slot<FILT, MODE, 1>(a, slot, P, ctx, hx, hy, gcur, lds, merge, rev);
+        if (ch == 4) backward_slot<FILT, MODE, 4>(a, slot, P, ctx, hx, hy, gcur, lds, merge, rev, lut_lds);
+        else if (ch == 2) backward_slot<FILT, MODE, 2>(a, slot, P, ctx, hx, hy, gcur, lds, merge, rev, lut_lds);
+        else backward_slot<FILT, MODE, 1>(a, slot, P, ctx, hx, hy, gcur, lds, merge, rev, lut_lds);
         gcur = gnext;
     }
 }
