@@ -185,7 +185,7 @@ __device__ __forceinline__ uint64_t reverse_members(int fp, int lx, int ly) {
 }
 
 // Tables of at most kRevMaxK entries per pixel are gathered like the windows.
-constexpr int kRevMaxK = 16;
+constexpr int kRevMaxK = kLutStageMax;
 
 // Where each lane's pick receives contributions from, for the gather of the
 // record footprints: square windows as a rectangle of pixels, the other

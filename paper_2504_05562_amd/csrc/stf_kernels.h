@@ -46,6 +46,8 @@ enum Mode { kModeStf = 0, kModeQuad = 1, kModeRecords = 2, kModeBins = 3 };
 // LDS per wavefront: bins (kBinRecords x 16 B records, or kBinRecords floats
 // of N plus kBinRecords x 16 B of decoded texels) followed by kBinRecords
 // 64-bit fixed-point accumulators, or records (64 x {s, r} + 64 x 16 B).
+// Tables of at most kLutStageMax entries per pixel are staged in LDS.
+constexpr int kLutStageMax = 16;
 constexpr int kAccFloatOffset = kBinRecords * 5;
 constexpr int kLdsFloatsPerWave = kAccFloatOffset + kBinRecords * 2;
 static_assert(kLdsFloatsPerWave % 4 == 0, "16-byte aligned LDS records");
@@ -504,7 +506,8 @@ __device__ __forceinline__ bool wave_same_texel(const Texel<PL>& T, bool valid) 
 template <int FILT, int MODE, int PL, bool LAT = false, bool EF = false>
 __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int slot, const Pixel& P,
                                           const SelCtx<FILT>& ctx, BinGeom<AxisCtx<FILT>::N>& geom,
-                                          const SlotPick& pk, float* lds, const uint8_t* dec = nullptr) {
+                                          const SlotPick& pk, float* lds, const uint8_t* dec = nullptr,
+                                          const uint8_t* lut_lds = nullptr) {
     static_assert(!LAT || PL == kF32x4, "decoded latents are RGBA FP32");
     constexpr int N = SelCtx<FILT>::N;
     constexpr int C = Texel<PL>::C;
@@ -662,6 +665,8 @@ __device__ __forceinline__ void slot_pass(const Args& a, const TexArg& t, int sl
                             if (__uint_as_float(mj.y) != 0.0f) cov.add_pick(ctx, mj.x, Ti, mx, my);
                         }
                     }
+                } else if (a.footprint == STF_FP_LUT && lut_lds != nullptr) {
+                    for (int m = 0; m < a.lut_k; ++m) member(lut_lds[P.q * a.lut_k + m] & 63);   // staged
                 } else if (a.footprint == STF_FP_LUT) {
                     for (int m = 0; m < a.lut_k; ++m) member(a.lut[P.q * a.lut_k + m] & 63);
                 } else {
@@ -780,7 +785,7 @@ constexpr int kForwardRows = DEC ? 2 : 1;
 // requested into uv_next.
 template <int FILT, int MODE, int NT, bool DEC, bool EF>
 __device__ __forceinline__ void forward_tile(const Args& a, Pixel& P, float* lds, const uint8_t* dec, bool more,
-                                             v2f& uv_next) {
+                                             v2f& uv_next, const uint8_t* lut_lds = nullptr) {
     TexArg t[NT];
 #pragma unroll
     for (int i = 0; i < NT; ++i) t[i] = a.tex[i];
@@ -815,13 +820,13 @@ __device__ __forceinline__ void forward_tile(const Args& a, Pixel& P, float* lds
         ctx.update(P, t[i].w, t[i].h);
         if constexpr (MODE == kModeBins) update_geom<FILT>(geom, P, ctx, t[i].w, t[i].h);
         switch (payload_of(t[i].fmt)) {
-        case kF16x4: slot_pass<FILT, MODE, kF16x4, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
-        case kF16x2: slot_pass<FILT, MODE, kF16x2, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
-        case kF32x1: slot_pass<FILT, MODE, kF32x1, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
+        case kF16x4: slot_pass<FILT, MODE, kF16x4, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds, nullptr, lut_lds); break;
+        case kF16x2: slot_pass<FILT, MODE, kF16x2, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds, nullptr, lut_lds); break;
+        case kF32x1: slot_pass<FILT, MODE, kF32x1, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds, nullptr, lut_lds); break;
         case kLatent:
             if constexpr (DEC) slot_pass<FILT, MODE, kF32x4, true, EF>(a, t[i], i, P, ctx, geom, pk[i], lds, dec);
             break;
-        default: slot_pass<FILT, MODE, kF32x4, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds); break;
+        default: slot_pass<FILT, MODE, kF32x4, false, EF>(a, t[i], i, P, ctx, geom, pk[i], lds, nullptr, lut_lds); break;
         }
     }
 }
@@ -890,8 +895,17 @@ __global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, NT, DEC, EF>)) void 
     static_assert(kDedupBytes <= kLdsFloatsPerWave * 4, "decode scratch exceeds the wave's LDS");
     __shared__ __align__(16) float lds_all[kLds ? kWavesPerGroup * kLdsFloatsPerWave : 4];
     __shared__ __align__(16) uint8_t dec[DEC ? kDecBytes : 16];
+    // record footprints without a decoder: a table of at most kLutStageMax
+    // entries per pixel is read from LDS
+    constexpr bool kStageLut = MODE == kModeRecords && !DEC;
+    __shared__ uint8_t lut_lds[kStageLut ? 64 * kLutStageMax : 1];
+    const bool staged = kStageLut && a.footprint == STF_FP_LUT && a.lut_k <= kLutStageMax;
     if constexpr (DEC) {                       // before any wave of the group can leave
         stage_decoder(a.dec, dec);
+        __syncthreads();
+    }
+    if (staged) {                              // uniform over the launch; before any wave can leave
+        for (int i = threadIdx.x; i < 64 * a.lut_k; i += kThreads) lut_lds[i] = a.lut[i];
         __syncthreads();
     }
     if constexpr (kRowLinear<MODE, DEC>) {
@@ -927,7 +941,7 @@ __global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, NT, DEC, EF>)) void 
     if constexpr (kRows == 1) {
         P.u = uv.x;
         P.v = uv.y;
-        forward_tile<FILT, MODE, NT, DEC, EF>(a, P, lds, DEC ? dec : nullptr, false, uv);
+        forward_tile<FILT, MODE, NT, DEC, EF>(a, P, lds, DEC ? dec : nullptr, false, uv, staged ? lut_lds : nullptr);
     } else {
 #pragma unroll 1
         for (int k = 0; k < kRows; ++k) {
@@ -937,7 +951,7 @@ __global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, NT, DEC, EF>)) void 
             P.u = uv.x;
             P.v = uv.y;
             const bool more = k + 1 < kRows && (ty + 1) * kTile < a.sh;
-            forward_tile<FILT, MODE, NT, DEC, EF>(a, P, lds, DEC ? dec : nullptr, more, uv);
+            forward_tile<FILT, MODE, NT, DEC, EF>(a, P, lds, DEC ? dec : nullptr, more, uv, staged ? lut_lds : nullptr);
         }
     }
 }
