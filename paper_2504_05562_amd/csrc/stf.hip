@@ -520,7 +520,7 @@ int stf_backward_decoder(const stf_texture* tex, int32_t ntex, const stf_screen*
         float* g = reinterpret_cast<float*>(wsp + l.g[i]);
         const int64_t texels = (int64_t)tex[i].width * tex[i].height;
         const int64_t n = texels * 4 + ((texels + stf::kDbN - 1) / stf::kDbN + 31) / 32;   // g, then the block mask
-        hipLaunchKernelGGL(stf::zero_fill_kernel, dim3((unsigned)std::min<int64_t>((n / 4 + 255) / 256 + 1, 4096)),
+        hipLaunchKernelGGL(stf::zero_fill_kernel, dim3((unsigned)std::min<int64_t>((n / 4 + 255) / 256 + 1, 1024)),
                            dim3(256), 0, s, g, n);     // g is 256-byte aligned
         a.out[i] = g;
         a.dout[i] = dout[i];

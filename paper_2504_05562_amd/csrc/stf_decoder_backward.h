@@ -374,13 +374,13 @@ __global__ __launch_bounds__(256) void decoder_grad_reduce_kernel(const float* l
 }
 
 // Fills n floats from the 16-byte aligned p with zero (a kernel, not a
-// memset node: safe under graph capture), one 16-byte store per lane and
-// step, then the last n % 4 floats.
+// memset node: safe under graph capture), one non-temporal 16-byte store per
+// lane and step, then the last n % 4 floats.
 __global__ __launch_bounds__(256) void zero_fill_kernel(float* p, int64_t n) {
     const int64_t n4 = n >> 2, stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    float4* p4 = reinterpret_cast<float4*>(p);
-    for (int64_t i = first; i < n4; i += stride) p4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    v4f* p4 = reinterpret_cast<v4f*>(p);
+    for (int64_t i = first; i < n4; i += stride) __builtin_nontemporal_store(v4f{0.0f, 0.0f, 0.0f, 0.0f}, p4 + i);
     for (int64_t i = n4 * 4 + first; i < n; i += stride) p[i] = 0.0f;
 }
 
