@@ -35,6 +35,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 
 #include "stf_device.h"
 #include "stf_decoder.h"
@@ -42,6 +43,16 @@
 namespace stf {
 
 enum Mode { kModeStf = 0, kModeQuad = 1, kModeRecords = 2, kModeBins = 3 };
+
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time.
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, Is...>) {
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // LDS per wavefront: bins (kBinRecords x 16 B records, or kBinRecords floats
 // of N plus kBinRecords x 16 B of decoded texels) followed by kBinRecords
@@ -767,9 +778,9 @@ __device__ __forceinline__ int payload_of(int fmt) {
 // spills), three textures fit 72 (seven waves), four keep 80 (six waves;
 // they spill a few registers, and at 72 more of them, which ran 15 % slower;
 // 96 without spills, five waves, measured no faster); with the latent
-// decoder and one texture it keeps 128 (four waves).
+// decoder it keeps 128 (four waves; its slots run one after another).
 template <int MODE, int NT, bool DEC, bool EF>
-constexpr int kForwardWaves = (MODE == kModeBins && !EF) ? (DEC ? (NT == 1 ? 4 : 1) : NT <= 2 ? 8 : NT == 3 ? 7 : 6) : 1;
+constexpr int kForwardWaves = (MODE == kModeBins && !EF) ? (DEC ? 4 : NT <= 2 ? 8 : NT == 3 ? 7 : 6) : 1;
 
 // Screen tile rows each forward wave filters one after the other (one tile
 // column): the next row's UV is loaded while the current row is filtered,
@@ -789,6 +800,42 @@ __device__ __forceinline__ void forward_tile(const Args& a, Pixel& P, float* lds
     TexArg t[NT];
 #pragma unroll
     for (int i = 0; i < NT; ++i) t[i] = a.tex[i];
+    if constexpr (DEC && MODE != kModeStf) {
+        // With a decoder the exchanging slots run one after another, each
+        // from its pick to its stores: the decode and exchange dominate a
+        // slot, and carrying every slot's pick through the others' passes (as
+        // below) kept them in scratch memory once the compiler left the slot
+        // loop rolled (one-tap STF keeps the overlapped fetches below).
+        SelCtx<FILT> ctx;
+        BinGeom<AxisCtx<FILT>::N> geom;
+        uint4 hq;
+        uint32_t hxs[NT], hys[NT];
+        static_for<NT>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            uint32_t hx, hy;
+            slot_uniforms(a, P, i, hq, hx, hy);
+            ctx.update(P, t[i].w, t[i].h);
+#pragma unroll
+            for (int j = 0; j < i; ++j) {            // shared selection, as below
+                const bool lead = a.leader[i] == j;
+                hx = lead ? hxs[j] : hx;
+                hy = lead ? hys[j] : hy;
+            }
+            hxs[i] = hx;
+            hys[i] = hy;
+            const SlotPick pk = pick_slot<FILT>(t[i], ctx, hx, hy);
+            if (i == 0 && more) uv_next = load_uv(a, P.px, P.py + kTile);
+            if constexpr (MODE == kModeBins) update_geom<FILT>(geom, P, ctx, t[i].w, t[i].h);
+            switch (payload_of(t[i].fmt)) {
+            case kF16x4: slot_pass<FILT, MODE, kF16x4, false, EF>(a, t[i], i, P, ctx, geom, pk, lds); break;
+            case kF16x2: slot_pass<FILT, MODE, kF16x2, false, EF>(a, t[i], i, P, ctx, geom, pk, lds); break;
+            case kF32x1: slot_pass<FILT, MODE, kF32x1, false, EF>(a, t[i], i, P, ctx, geom, pk, lds); break;
+            case kLatent: slot_pass<FILT, MODE, kF32x4, true, EF>(a, t[i], i, P, ctx, geom, pk, lds, dec); break;
+            default: slot_pass<FILT, MODE, kF32x4, false, EF>(a, t[i], i, P, ctx, geom, pk, lds); break;
+            }
+        });
+        return;
+    }
     SelCtx<FILT> ctx;
     SlotPick pk[NT];
     uint4 hq;

@@ -110,8 +110,9 @@ def test_whole_tile_kernels_keep_their_register_budget(kernels, filt):
     for nt, budget in ((1, 64), (2, 64), (3, 72), (4, 80)):
         k = fwd[(filt, "bins", nt, False, False)]
         assert k[".vgpr_count"] + k[".agpr_count"] <= budget, (nt, k[".vgpr_count"])
-    k = fwd[(filt, "bins", 1, True, False)]             # latent decoder, one texture: four waves
-    assert k[".vgpr_count"] + k[".agpr_count"] <= 128
+    for nt in (1, 2, 3, 4):                              # latent decoder: four waves
+        k = fwd[(filt, "bins", nt, True, False)]
+        assert k[".vgpr_count"] + k[".agpr_count"] <= 128, (nt, k[".vgpr_count"])
 
 
 @pytest.mark.parametrize("filt", [0, 1], ids=["bilinear", "bicubic"])
@@ -127,6 +128,13 @@ def test_forward_kernels_keep_per_lane_data_in_registers(kernels, filt):
             assert not k[".uses_dynamic_stack"], (mode, nt)
     # the one-texture latent whole-tile kernel spills a few registers at its 128-VGPR budget
     assert fwd[(filt, "bins", 1, True, False)][".private_segment_fixed_size"] <= 32
+    # with several latent textures the exchanging decoder kernels run their slots one after
+    # another (spilling some registers at 128 VGPRs) instead of keeping every slot's pick in
+    # scratch memory, which took 336-432 bytes per lane
+    for mode in ("quad", "records", "bins"):
+        for nt in (2, 3, 4):
+            k = fwd[(filt, mode, nt, True, False)]
+            assert k[".private_segment_fixed_size"] <= 256, (mode, nt, k[".private_segment_fixed_size"])
 
 
 def test_other_kernels_use_no_scratch(kernels):
