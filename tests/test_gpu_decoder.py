@@ -130,6 +130,37 @@ def test_decoded_parity(kind, filt, fp):
     check(got, image(rv, uv), uv, ftag, decoded, ebound, f"{kind} {filt} {fp}")
 
 
+@pytest.mark.parametrize("fp", [None, "quad2x2", "square3x3", "tile8x8"])
+@pytest.mark.parametrize("nt", [2, 3, 4])
+def test_decoded_parity_several_latent_textures(fp, nt):
+    """Several latent textures in one call (one decoder): the exchanging
+    kernels run their slots one after another. Textures of different sizes
+    and storage kinds; every slot against the oracle."""
+    layers = w.decoder_weights(2)
+    cases = [("bf16", 4, 64), ("fp8", 5, 32), ("f16", 6, 64), ("fp8", 7, 16)][:nt]
+    stored, scales, decoded, bounds = [], [], [], []
+    for kind, seed, size in cases:
+        st, sc, x, u_in = latent_case(kind, seed, size)
+        stored.append(device_latents(st, kind))
+        scales.append(None if sc is None else list(sc))
+        decoded.append(o.mlp_decode(x, layers))
+        bounds.append(bound_decode(x, layers, u_in))
+    uv = w.small_screen(72, 40, 64, 3.0, offset_seed=9)            # ragged: 9 x 5 tiles
+    dec = decoder_on_gpu(layers)
+    duv = torch.from_numpy(uv).cuda()
+    if fp is None:
+        outs, sel = stf.filter(stored, duv, "bicubic", 5, 2, sel=True, scales=scales, decoder=dec)
+        ref = o.stf_filter(decoded, uv, o.BICUBIC, 5, 2)
+    else:
+        outs, sel = stf.filter_reuse(stored, duv, fp, "bicubic", 5, 2, sel=True, scales=scales, decoder=dec)
+        ref = o.stf_filter_reuse(decoded, uv, o.BICUBIC, 5, 2, fp)
+    sel = host(sel)
+    for i in range(nt):
+        rv, rs = ref[i]
+        assert np.array_equal(sel[i], image(rs, uv)), f"slot {i} selection differs"
+        check(host(outs[i]), image(rv, uv), uv, o.BICUBIC, decoded[i], bounds[i], f"slot {i} of {nt}, {fp}")
+
+
 @pytest.mark.parametrize("kind", ["bf16", "fp8"])
 def test_decoded_reference_parity(kind):
     # Eq. (3) over decoded texels: every tap of every pixel is decoded
