@@ -106,9 +106,11 @@ def test_multi_texture_formats(fp):
     run_case(texs, uv, "bicubic", fp, seed=11)
 
 
-def test_lut_footprint():
+@pytest.mark.parametrize("k", [9, 16, 17, 40])
+def test_lut_footprint(k):
+    """Tables of up to 16 entries are read from LDS, longer ones from global memory."""
     rng = np.random.default_rng(5)
-    lut = rng.integers(0, 64, (64, 9))
+    lut = rng.integers(0, 64, (64, k))
     lut[::3, 0] = np.arange(64)[::3]          # some rows name the pixel itself
     uv = w.small_screen(48, 32, 64, 4.0, offset_seed=2)
     run_case([w.tile_texture_rgba8(1, 64)], uv, "bicubic", "lut", seed=2, lut=lut)
