@@ -214,7 +214,9 @@ __device__ __forceinline__ uint32_t reverse_rect(int n, int lx, int ly) {
 // The lists of a table footprint (`lut`, [64][K] in LDS) for the wave (once
 // per launch): count the entries naming each pixel (LDS integer atomics),
 // prefix sums over the pixels, place the entries, then each pixel sorts its
-// own list. `tmp` holds 128 ints of the wave's LDS.
+// own list (insertion sort: quadratic in the entries naming the pixel, K on
+// average; a table whose entries all name one pixel is slow but exact).
+// `tmp` holds 128 ints of the wave's LDS.
 __device__ __forceinline__ void build_reverse_table(int K, const uint8_t* lut, const Pixel& P, int* tmp,
                                                     uint16_t* list, Reverse& rev) {
     const uint8_t* row = lut + P.q * K;
