@@ -65,13 +65,13 @@ __device__ __forceinline__ void atomic_texel(float* g, int tw, uint32_t s, const
 }
 
 // Workgroup merge of the adjoint windows: the four tiles of a workgroup sit
-// side by side, so their bin windows overlap (fully at high magnification). Each wave adds its window's sums into one kMergeW x
-// kMergeH texel area in LDS covering all four, and the workgroup flushes that
-// area with one global atomic per touched texel and channel, instead of each
-// wave flushing its own window: the global FP32 atomics, which bound this
-// kernel, drop by the overlap. A workgroup whose windows do not fit the area
-// flushes per wave; waves whose supports leave their window send their
-// gradients with global atomics and take no part.
+// side by side, so their bin windows overlap (fully at high magnification).
+// Each wave adds its window's sums into one kMergeW x kMergeH texel area in
+// LDS covering all four, and the workgroup flushes that area with one global
+// atomic per touched texel and channel, instead of each wave flushing its
+// own window: the global FP32 atomics drop by the overlap. A workgroup whose
+// windows do not fit the area flushes per wave; waves whose supports leave
+// their window send their gradients with global atomics and take no part.
 constexpr int kMergeW = 32, kMergeH = 16;
 
 struct MergeArea {
@@ -658,14 +658,15 @@ __device__ __forceinline__ float4 load_dout(const Args& a, int slot, const Pixel
     return g;
 }
 
-// The adjoint kernels are budgeted for kBwdWaves waves per SIMD.
+// The adjoint kernels are budgeted for kBwdWaves waves per SIMD (the record
+// footprints' kernel for four: its gathers take more registers).
 constexpr int kBwdWaves = 5;
 
 template <int FILT, int MODE>
 __global__ __launch_bounds__(kThreads, MODE == kModeRecords ? 4 : kBwdWaves) void backward_kernel(Args a) {
     // per wave: bin sums of 1/p or 64 {s, r} records, then the wide area
-    // (window bins, row records); the wide areas of the workgroup together
-    // form the merge area
+    // (u64 sums, row records, member coefficients, one-hot operands); the
+    // wide areas of the workgroup together form the merge area
     constexpr int kPerWave = kBwdNbFloats;
     static_assert(kPerWave >= 128, "64 {s, r} records fit");
     static_assert(kMergeW * kMergeH * 4 <= kWavesPerGroup * kBwdWideFloats, "merge area fits");
