@@ -73,6 +73,29 @@ def test_exact_filtering_parity(filt, fp, texkind):
     assert not bad.any(), f"{bad.sum()} values beyond tolerance"
 
 
+@pytest.mark.parametrize("fp", ["quad2x2", "square3x3", "tile8x8"])
+@pytest.mark.parametrize("nt", [2, 3, 4])
+def test_exact_filtering_several_textures(fp, nt):
+    """Exact filtering with two to four textures of different formats and
+    sizes in one call (with three or more the slots run one after another)."""
+    rng = np.random.default_rng(9)
+    texs = [w.small_texture(3, 64), rng.random((64, 64, 4)).astype(np.float16),
+            (rng.random((32, 32, 2)) * 2 - 1).astype(np.float16),
+            rng.integers(0, 256, (16, 16, 1), dtype=np.uint8)][:nt]
+    uv = rotated_screen(90, 50, 64, 6.0, 0.4, (3.1, 7.3))
+    outs, sel = stf.filter_reuse([dev(t) for t in texs], dev(uv), fp, "bicubic", 6, 1, sel=True,
+                                 exact_filtering=True)
+    ref = o.stf_filter_reuse(texs, uv, o.BICUBIC, 6, 1, fp, exact_filtering=True)
+    sel = host(sel)
+    for i, (tex, (rv, rs)) in enumerate(zip(texs, ref)):
+        assert np.array_equal(sel[i], image(rs, uv)), f"slot {i} selection"
+        got = host(outs[i]).astype(np.float64)
+        want = image(rv, uv)
+        tol = REL * np.maximum(np.abs(want), support_scale(tex, uv, o.BICUBIC)) + 1e-30
+        bad = np.abs(got - want) > tol
+        assert not bad.any(), f"slot {i}: {bad.sum()} values beyond tolerance"
+
+
 @pytest.mark.parametrize("texkind", ["rgba16f", "rgba32f", "r8"])
 def test_covered_pixels_equal_gpu_reference_bitwise(texkind):
     rng = np.random.default_rng(2)

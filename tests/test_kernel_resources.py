@@ -135,6 +135,10 @@ def test_forward_kernels_keep_per_lane_data_in_registers(kernels, filt):
         for nt in (2, 3, 4):
             k = fwd[(filt, mode, nt, True, False)]
             assert k[".private_segment_fixed_size"] <= 256, (mode, nt, k[".private_segment_fixed_size"])
+    # exact filtering with three or four textures runs its slots one after another: no scratch
+    for mode in ("quad", "records", "bins"):
+        for nt in (3, 4):
+            assert fwd[(filt, mode, nt, False, True)][".private_segment_fixed_size"] == 0, (mode, nt)
 
 
 def test_other_kernels_use_no_scratch(kernels):
