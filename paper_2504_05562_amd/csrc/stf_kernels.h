@@ -770,6 +770,116 @@ __device__ __forceinline__ int payload_of(int fmt) {
     }
 }
 
+// The picked texel of one slot as four floats (channels past the payload's
+// are zero).
+template <int PL>
+__device__ __forceinline__ void texel_floats(const TexArg& t, const SlotPick& pk, uint32_t sx, float (&v)[4]) {
+    const Texel<PL> T = decode<PL>(block_texel(pk.raw, sx, format_bytes(t.fmt)), t.fmt);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < Texel<PL>::C; ++c) v[c] = T.ch(c);
+}
+
+// Record footprints under shared selection, every slot led by slot 0 (one
+// texture size, Sec. 4.5): all slots pick the same texel, so the support
+// test and weight w_i = f_c(x_i) / p_i of a member are formed once and
+// applied to every slot's texel. Per slot the sums are the ones slot_pass
+// forms, operation for operation, so the outputs are the same bits. LDS:
+// {s, r}[64], then one float4 texel per lane and slot.
+template <int FILT, int NT>
+__device__ __forceinline__ void shared_records_pass(const Args& a, const TexArg (&t)[NT], const Pixel& P,
+                                                    const SelCtx<FILT>& ctx, const SlotPick (&pk)[NT], float* lds,
+                                                    const uint8_t* lut_lds) {
+    static_assert(NT >= 2 && 128 + NT * 256 <= kLdsFloatsPerWave, "every slot's records fit the wave's LDS");
+    constexpr int N = SelCtx<FILT>::N;
+    const uint32_t mx = (uint32_t)t[0].w - 1u, my = (uint32_t)t[0].h - 1u;
+    const int kx = pk[0].kx, ky = pk[0].ky;
+    const uint32_t sx = (uint32_t)(ctx.x.base + kx) & mx;
+    const uint32_t sy = (uint32_t)(ctx.y.base + ky) & my;
+    const int64_t pix = (int64_t)P.py * a.sw + P.px;
+    float Tv[NT][4];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        switch (payload_of(t[i].fmt)) {
+        case kF16x4: texel_floats<kF16x4>(t[i], pk[i], sx, Tv[i]); break;
+        case kF16x2: texel_floats<kF16x2>(t[i], pk[i], sx, Tv[i]); break;
+        case kF32x1: texel_floats<kF32x1>(t[i], pk[i], sx, Tv[i]); break;
+        case kLatent: Tv[i][0] = Tv[i][1] = Tv[i][2] = Tv[i][3] = 0.0f; break;   // the decoder kernels' case
+        default: texel_floats<kF32x4>(t[i], pk[i], sx, Tv[i]); break;
+        }
+        if (a.sel != nullptr && P.valid)
+            reinterpret_cast<int2*>(a.sel)[(int64_t)i * a.sh * a.sw + pix] = make_int2((int)sx, (int)sy);
+    }
+    // 1/p of the own pick; off-screen pixels share a pick of weight zero
+    const float pc = ctx.x.wsel(kx) * ctx.y.wsel(ky);
+    const float r = P.valid ? fast_rcp(pc) : 0.0f;
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Tv[i][c] = P.valid ? Tv[i][c] : 0.0f;
+    uint2* meta = reinterpret_cast<uint2*>(lds);          // [64] {s, r}
+    float4* val = reinterpret_cast<float4*>(lds + 128);   // [NT][64] texel
+    meta[P.q] = make_uint2(sx | (sy << 16), __float_as_uint(r));
+#pragma unroll
+    for (int i = 0; i < NT; ++i) val[i * 64 + P.q] = make_float4(Tv[i][0], Tv[i][1], Tv[i][2], Tv[i][3]);
+    wave_lds_sync();
+    float B = 1.0f;            // own pick: w_c = 1
+    float acc[NT][4];
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[i][c] = 0.0f;
+    auto member = [&](int j) {
+        if (j == P.q) return;                // the own pick is already counted
+        const uint2 mj = meta[j];
+        float4 vj[NT];
+#pragma unroll
+        for (int i = 0; i < NT; ++i) vj[i] = val[i * 64 + j];
+        uint32_t dx, dy;
+        if (support_offset<N>(mj.x, ctx.x.base, ctx.y.base, mx, my, dx, dy)) {
+            const float w = ctx.x.wsel(dx) * ctx.y.wsel(dy) * __uint_as_float(mj.y);
+            B += w;
+#pragma unroll
+            for (int i = 0; i < NT; ++i) {
+                const float Ti[4] = {vj[i].x, vj[i].y, vj[i].z, vj[i].w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[i][c] = fmaf(w, Ti[c] - Tv[i][c], acc[i][c]);
+            }
+        }
+    };
+    if (a.footprint == STF_FP_LUT && lut_lds != nullptr) {
+        for (int m = 0; m < a.lut_k; ++m) member(lut_lds[P.q * a.lut_k + m] & 63);   // staged
+    } else if (a.footprint == STF_FP_LUT) {
+        for (int m = 0; m < a.lut_k; ++m) member(a.lut[P.q * a.lut_k + m] & 63);
+    } else {
+        int ox, oy, n;
+        window_of(a.footprint, P.lx, P.ly, ox, oy, n);
+        for (int wy = 0; wy < n; ++wy)
+            for (int wx = 0; wx < n; ++wx) member((oy + wy) * 8 + ox + wx);
+    }
+    wave_lds_sync();                         // reads done before the wave's next tile reuses LDS
+    if (P.valid) {
+        const float inv = fast_rcp(B);
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+            float o[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) o[c] = fmaf(acc[i][c], inv, Tv[i][c]);
+            if (t[i].has_scale) {            // Eq. (14) is linear in the texels
+#pragma unroll
+                for (int c = 0; c < 4; ++c) o[c] *= t[i].scale[c];
+            }
+            switch (payload_of(t[i].fmt)) {
+            case kF16x2: store_out<2>(a.out[i], pix, o); break;
+            case kF32x1: store_out<1>(a.out[i], pix, o); break;
+            case kLatent: break;
+            default: store_out<4>(a.out[i], pix, o); break;
+            }
+        }
+    }
+}
+
 // Waves per SIMD the forward kernels are register-budgeted for (VGPRs per
 // lane: 512 / waves, in steps of 8). The whole-tile kernel issues VALU most
 // of the time and hides its memory and LDS latency with occupancy: with up
@@ -794,7 +904,8 @@ constexpr int kForwardRows = DEC ? 2 : 1;
 // every pick and texel fetch is issued before the first exchange so their
 // latencies overlap; then the UV of the wave's next tile (more = true) is
 // requested into uv_next.
-template <int FILT, int MODE, int NT, bool DEC, bool EF>
+// SHR: record footprints with every slot led by slot 0 (shared_records_pass).
+template <int FILT, int MODE, int NT, bool DEC, bool EF, bool SHR = false>
 __device__ __forceinline__ void forward_tile(const Args& a, Pixel& P, float* lds, const uint8_t* dec, bool more,
                                              v2f& uv_next, const uint8_t* lut_lds = nullptr) {
     TexArg t[NT];
@@ -863,6 +974,11 @@ __device__ __forceinline__ void forward_tile(const Args& a, Pixel& P, float* lds
         pk[i] = pick_slot<FILT>(t[i], ctx, hx, hy);
     }
     if (more) uv_next = load_uv(a, P.px, P.py + kTile);
+    if constexpr (SHR) {
+        static_assert(MODE == kModeRecords && !DEC && !EF, "shared records: record footprints without a decoder");
+        shared_records_pass<FILT, NT>(a, t, P, ctx, pk, lds, lut_lds);   // ctx: slot 0's size, every slot's
+        return;
+    }
     BinGeom<AxisCtx<FILT>::N> geom;
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
@@ -1003,6 +1119,28 @@ __global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, NT, DEC, EF>)) void 
             forward_tile<FILT, MODE, NT, DEC, EF>(a, P, lds, DEC ? dec : nullptr, more, uv, staged ? lut_lds : nullptr);
         }
     }
+}
+
+// Record footprints (2x2w, 3x3, 4x4, tables) over two or three textures of
+// one size under shared selection: one support test and weight per member
+// for every slot. A kernel of its own, so that the independent-selection
+// kernels keep their register counts; one tile per wave, laid out as in
+// forward_kernel.
+template <int FILT, int NT>
+__global__ __launch_bounds__(kThreads) void shared_records_kernel(Args a) {
+    __shared__ __align__(16) float lds_all[kWavesPerGroup * kLdsFloatsPerWave];
+    __shared__ uint8_t lut_lds[64 * kLutStageMax];
+    const bool staged = a.footprint == STF_FP_LUT && a.lut_k <= kLutStageMax;
+    if (staged) {                              // uniform over the launch; before any wave can leave
+        for (int i = threadIdx.x; i < 64 * a.lut_k; i += kThreads) lut_lds[i] = a.lut[i];
+        __syncthreads();
+    }
+    Pixel P;
+    if (!setup_pixel(a, P)) return;
+    float* lds = lds_all + (threadIdx.x >> 6) * kLdsFloatsPerWave;
+    v2f next;                                  // no next tile
+    forward_tile<FILT, kModeRecords, NT, false, false, true>(a, P, lds, nullptr, false, next,
+                                                             staged ? lut_lds : nullptr);
 }
 
 // ---------------------------------------------------------------- comparison estimators
@@ -1300,6 +1438,15 @@ inline dim3 grid_forward(const Args& a) {
 template <int FILT, int MODE, bool DEC, bool EF>
 void launch_nt(const Args& a, hipStream_t s) {
     const dim3 g = grid_forward<MODE, DEC>(a), b(kThreads);
+    if constexpr (MODE == kModeRecords && !DEC && !EF) {
+        bool one_pick = a.ntex == 2 || a.ntex == 3;        // every slot takes slot 0's selection
+        for (int i = 1; i < a.ntex; ++i) one_pick = one_pick && a.leader[i] == 0;
+        if (one_pick) {
+            if (a.ntex == 2) hipLaunchKernelGGL((shared_records_kernel<FILT, 2>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((shared_records_kernel<FILT, 3>), g, b, 0, s, a);
+            return;
+        }
+    }
     switch (a.ntex) {
     case 1: hipLaunchKernelGGL((forward_kernel<FILT, MODE, 1, DEC, EF>), g, b, 0, s, a); break;
     case 2: hipLaunchKernelGGL((forward_kernel<FILT, MODE, 2, DEC, EF>), g, b, 0, s, a); break;

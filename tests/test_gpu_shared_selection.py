@@ -77,3 +77,69 @@ def test_shared_selection_adjoint_and_estimators():
     ref = eo.stf_filter_estimator(texs, uv, o.BICUBIC, 4, 0, "square3x3", "mis", share_selection=True)
     for k in range(2):
         assert close(outs[k].cpu().numpy(), image(ref[k][0], uv), texs[k], uv, o.BICUBIC)
+
+
+def one_size_textures(n):
+    """Two or three textures of one size (64^2), so every slot takes slot 0's
+    picks: the record footprints then run the fused kernel. Three: RGBA16F,
+    RG16F and BF16 RGBA with a per-channel scale; two: RGBA32F and R8."""
+    rng = np.random.default_rng(21)
+    if n == 3:
+        vals = rng.random((64, 64, 4)) * np.array([1.0, 4.0, 0.25, 2.0]) - 0.3
+        scale = np.array([0.5, 2.0, 0.125, 1.0])
+        bf = (w.quantize(vals, "bf16", scale), "bf16", scale)
+        return [rng.random((64, 64, 4)).astype(np.float16), (rng.random((64, 64, 2)) * 2 - 1).astype(np.float16), bf]
+    return [rng.random((64, 64, 4)).astype(np.float32), rng.integers(0, 256, (64, 64, 1), dtype=np.uint8)]
+
+
+def device_inputs(texs):
+    dt, sc = [], []
+    for t in texs:
+        if isinstance(t, tuple):                 # (stored BF16 bits, "bf16", scale)
+            dt.append(dev(t[0]).view(torch.int16).view(torch.bfloat16))
+            sc.append(list(t[2]))
+        else:
+            dt.append(dev(t))
+            sc.append(None)
+    return dt, sc
+
+
+def footprint_case(fp):
+    """(footprint name, LUT or None): tables of 9 (staged in LDS) and 24 entries."""
+    if not fp.startswith("lut"):
+        return fp, None
+    k = int(fp[3:])
+    lut = np.random.default_rng(k).integers(0, 64, (64, k))
+    lut[::3, 0] = np.arange(64)[::3]
+    return "lut", lut
+
+
+@pytest.mark.parametrize("fp", ["wave2x2", "square3x3", "square4x4", "lut9", "lut24"])
+@pytest.mark.parametrize("filt", ["bilinear", "bicubic"])
+@pytest.mark.parametrize("n", [2, 3])
+def test_shared_records_kernel(n, filt, fp):
+    """Record footprints over textures of one size under shared selection:
+    one support test and weight per member serves every slot. Parity with
+    the oracle (selection bit-exact, colours within 1e-5), and the same bits
+    as the per-slot kernel, which a fourth texture of that size selects."""
+    texs = one_size_textures(n)
+    name, lut = footprint_case(fp)
+    uv = w.small_screen(90, 58, 64, 4.0, offset_seed=5)      # ragged tiles
+    ftag = o.BICUBIC if filt == "bicubic" else o.BILINEAR
+    dt, sc = device_inputs(texs)
+    duv = dev(uv)
+    lut_t = dev(lut.astype(np.uint8)) if lut is not None else None
+    outs, sel = stf.filter_reuse(dt, duv, name, filt, 7, 3, lut=lut_t, sel=True, scales=sc, share_selection=True)
+    ref = o.stf_filter_reuse(texs, uv, ftag, 7, 3, name, lut=lut, share_selection=True)
+    s = sel.cpu().numpy()
+    for k, (tex, (rv, rs)) in enumerate(zip(texs, ref)):
+        assert np.array_equal(s[k], image(rs, uv)), k
+        vals = o.texture_values(tex)
+        T = np.abs(vals)
+        tol = REL * np.maximum(np.abs(image(rv, uv)), T.max()) + 1e-30
+        assert np.all(np.abs(outs[k].cpu().numpy().astype(np.float64) - image(rv, uv)) <= tol), k
+    # four textures of the size: the per-slot kernel, same picks, same arithmetic per slot
+    per_slot = stf.filter_reuse(dt + [dt[0]] * (4 - n), duv, name, filt, 7, 3, lut=lut_t,
+                                scales=sc + [sc[0]] * (4 - n), share_selection=True)
+    for k in range(n):
+        assert torch.equal(outs[k], per_slot[k]), k
