@@ -344,7 +344,23 @@ def material_form(torch, stf, w, steps, warmup):
         "bilinear_stf_1sample_us": round(t_one * 1e6, 2), "this_gpu": added,
         "paper_rtx4090": {"2x2": 0.04, "3x3": 0.11, "4x4": 0.14},
         "paper_workload": "3840x2160, every pixel magnified, neural textures (9 channels in 3 textures)"}
-    del outs, uv
+    # closer to that workload: three textures of one size (base colour RGBA8, normal RG16F,
+    # material parameters RGBA8; 2048^2 each) and one pick per pixel for all three, as one
+    # decode per texel gives every channel of a neural material
+    mat = [torch.from_numpy(np.ascontiguousarray(t)).cuda()
+           for t in (w.tile_texture_rgba8(0, 2048), w.plane_normal(0, 2048), w.tile_texture_rgba8(1, 2048))]
+    mouts = [torch.empty((2160, 3840, c), dtype=torch.float32, device=uv.device) for c in (4, 2, 4)]
+    t_one_m = launch_time(torch, lambda: stf.filter(mat, uv, "bilinear", 0, 0, out=mouts, share_selection=True),
+                          steps, warmup, batches=5)
+    added_m = {}
+    for name, fp in (("2x2", "quad2x2"), ("3x3", "square3x3"), ("4x4", "square4x4")):
+        t = launch_time(torch, lambda: stf.filter_reuse(mat, uv, fp, "bilinear", 0, 0, out=mouts, share_selection=True),
+                        steps, warmup, batches=5)
+        added_m[name] = round((t - t_one_m) * 1e3, 4)
+    res["added_cost_of_reuse_ms"]["one_size_shared_selection"] = {
+        "textures": ["RGBA8 2048^2", "RG16F 2048^2", "RGBA8 2048^2"], "channels": 10,
+        "bilinear_stf_1sample_us": round(t_one_m * 1e6, 2), "this_gpu": added_m}
+    del outs, uv, mouts, mat
     mse = {"stf": np.zeros(4), "reuse": np.zeros(4)}
     acc = {k: [None] * 4 for k in ("stf", "reuse", "ref")}
     frames = 16
@@ -629,6 +645,18 @@ def profile_launches(torch, stf, w, which, n=50, footprint="tile8x8"):
             stf.filter_reuse(texs, uv, "tile8x8", "bicubic", 0, 0, out=outs)
             stf.filter_reuse(texs, uv, "tile8x8", "bicubic", 0, 0, out=outs, share_selection=True)
         stf.filter_reference(texs, uv, "bicubic", out=outs)
+    elif which == "material_windows":
+        # three 2048^2 textures (RGBA8, RG16F, RGBA8) at 3840x2160, bilinear: one-tap STF, then
+        # reuse over `footprint` with one pick per pixel for all three textures, then with three
+        mat = [torch.from_numpy(np.ascontiguousarray(t)).to(dev)
+               for t in (w.tile_texture_rgba8(0, 2048), w.plane_normal(0, 2048), w.tile_texture_rgba8(1, 2048))]
+        uv = torch.from_numpy(w.perspective_plane(3840, 2160, 2048, 2.0, 32.0)[0]).to(dev)
+        outs = [torch.empty((2160, 3840, c), device=dev) for c in (4, 2, 4)]
+        for _ in range(n):
+            stf.filter(mat, uv, "bilinear", 0, 0, out=outs, share_selection=True)
+        for share in (True, False):
+            for _ in range(n):
+                stf.filter_reuse(mat, uv, footprint, "bilinear", 0, 0, out=outs, share_selection=share)
     elif which == "decoder_backward":
         uv = torch.from_numpy(w.view_set(1, 1920, 1080, 1024, seed=5)[0]).to(dev)
         rng = np.random.Generator(np.random.PCG64(21))
@@ -665,12 +693,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision, backward and latent-decoder comparisons")
-    ap.add_argument("--profile", choices=["latent", "backward", "materials", "decoder_backward"],
-                    help="only run 50 launches of the latent-decoder, backward, decoder-backward or 4K four-texture workload "
-                         "(for rocprofv3) and exit")
+    ap.add_argument("--profile", choices=["latent", "backward", "materials", "decoder_backward", "material_windows"],
+                    help="only run 50 launches of the latent-decoder, backward, decoder-backward, 4K four-texture or 4K "
+                         "three-texture square-window workload (for rocprofv3) and exit")
     ap.add_argument("--footprint", default="tile8x8",
                     choices=["self", "quad2x2", "wave2x2", "square3x3", "square4x4", "lut_ps9", "tile8x8"],
-                    help="footprint of the --profile backward launches")
+                    help="footprint of the --profile backward and material_windows launches")
     ap.add_argument("--summarize-pmc", nargs="+", metavar="CSV",
                     help="write the per-launch traffic summary from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--summarize-trace", metavar="CSV",
