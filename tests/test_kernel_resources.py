@@ -161,3 +161,13 @@ def test_adjoint_occupancy(kernels):
             k = kernels["_ZN3stf15backward_kernelILi%dELi%dEEEvNS_4ArgsE" % (filt, mode)]
             assert k[".vgpr_count"] + k[".agpr_count"] <= 512 // waves // 8 * 8, (filt, mode)
             assert k[".group_segment_fixed_size"] * waves <= 160 * 1024, (filt, mode)
+
+
+def test_shared_records_kernel_keeps_eight_waves(kernels):
+    """The one-size shared-selection record kernel (two or three textures)
+    fits 64 VGPRs without scratch, so it holds eight waves per SIMD."""
+    for filt in (0, 1):
+        for nt in (2, 3):
+            k = kernels["_ZN3stf21shared_records_kernelILi%dELi%dEEEvNS_4ArgsE" % (filt, nt)]
+            assert k[".vgpr_count"] + k[".agpr_count"] <= 64, (filt, nt)
+            assert k[".private_segment_fixed_size"] == 0, (filt, nt)
