@@ -880,6 +880,97 @@ __device__ __forceinline__ void shared_records_pass(const Args& a, const TexArg 
     }
 }
 
+// One slot's quad sums under shared selection: the partners' weights wq
+// (support test inq) are the slot-independent part; each slot moves its own
+// C channels. Same operations, in the same order, as quad_step.
+template <int C>
+__device__ __forceinline__ void quad_slot_sums(const float (&wq)[3], const bool (&inq)[3], const float (&Tc)[4],
+                                               float (&acc)[4]) {
+    static_for<3>([&](auto X) {
+        constexpr int x = decltype(X)::value + 1;
+        float Ti[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) Ti[c] = quad_xor<x>(Tc[c]);
+        if (inq[x - 1]) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] = fmaf(wq[x - 1], Ti[c] - Tc[c], acc[c]);
+        }
+    });
+}
+
+// 2x2 quads under shared selection, every slot led by slot 0: each
+// partner's pick, reciprocal PMF, support test and weight cross the quad
+// and are formed once for all slots; per slot the sums are quad_step's.
+template <int FILT, int NT>
+__device__ __forceinline__ void shared_quad_pass(const Args& a, const TexArg (&t)[NT], const Pixel& P,
+                                                 const SelCtx<FILT>& ctx, const SlotPick (&pk)[NT]) {
+    constexpr int N = SelCtx<FILT>::N;
+    const uint32_t mx = (uint32_t)t[0].w - 1u, my = (uint32_t)t[0].h - 1u;
+    const int kx = pk[0].kx, ky = pk[0].ky;
+    const uint32_t sx = (uint32_t)(ctx.x.base + kx) & mx;
+    const uint32_t sy = (uint32_t)(ctx.y.base + ky) & my;
+    const int64_t pix = (int64_t)P.py * a.sw + P.px;
+    float Tv[NT][4];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        switch (payload_of(t[i].fmt)) {
+        case kF16x4: texel_floats<kF16x4>(t[i], pk[i], sx, Tv[i]); break;
+        case kF16x2: texel_floats<kF16x2>(t[i], pk[i], sx, Tv[i]); break;
+        case kF32x1: texel_floats<kF32x1>(t[i], pk[i], sx, Tv[i]); break;
+        case kLatent: Tv[i][0] = Tv[i][1] = Tv[i][2] = Tv[i][3] = 0.0f; break;   // the decoder kernels' case
+        default: texel_floats<kF32x4>(t[i], pk[i], sx, Tv[i]); break;
+        }
+        if (a.sel != nullptr && P.valid)
+            reinterpret_cast<int2*>(a.sel)[(int64_t)i * a.sh * a.sw + pix] = make_int2((int)sx, (int)sy);
+    }
+    const float pc = ctx.x.wsel(kx) * ctx.y.wsel(ky);
+    const float r = P.valid ? fast_rcp(pc) : 0.0f;
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Tv[i][c] = P.valid ? Tv[i][c] : 0.0f;
+    const uint32_t s = sx | (sy << 16);
+    float B = 1.0f;            // own pick: w_c = 1
+    float wq[3];
+    bool inq[3];
+    static_for<3>([&](auto X) {
+        constexpr int x = decltype(X)::value + 1;
+        const uint32_t si = quad_xor<x>(s);
+        const float ri = quad_xor<x>(r);
+        uint32_t dx, dy;
+        inq[x - 1] = support_offset<N>(si, ctx.x.base, ctx.y.base, mx, my, dx, dy);
+        wq[x - 1] = 0.0f;
+        if (inq[x - 1]) {
+            wq[x - 1] = ctx.x.wsel(dx) * ctx.y.wsel(dy) * ri;
+            B += wq[x - 1];
+        }
+    });
+    const float inv = fast_rcp(B);
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        const int pl = payload_of(t[i].fmt);
+        if (pl == kF16x2) quad_slot_sums<2>(wq, inq, Tv[i], acc);
+        else if (pl == kF32x1) quad_slot_sums<1>(wq, inq, Tv[i], acc);
+        else quad_slot_sums<4>(wq, inq, Tv[i], acc);
+        if (P.valid) {
+            float o[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) o[c] = fmaf(acc[c], inv, Tv[i][c]);
+            if (t[i].has_scale) {            // Eq. (14) is linear in the texels
+#pragma unroll
+                for (int c = 0; c < 4; ++c) o[c] *= t[i].scale[c];
+            }
+            switch (pl) {
+            case kF16x2: store_out<2>(a.out[i], pix, o); break;
+            case kF32x1: store_out<1>(a.out[i], pix, o); break;
+            case kLatent: break;
+            default: store_out<4>(a.out[i], pix, o); break;
+            }
+        }
+    }
+}
+
 // Waves per SIMD the forward kernels are register-budgeted for (VGPRs per
 // lane: 512 / waves, in steps of 8). The whole-tile kernel issues VALU most
 // of the time and hides its memory and LDS latency with occupancy: with up
@@ -974,9 +1065,10 @@ __device__ __forceinline__ void forward_tile(const Args& a, Pixel& P, float* lds
         pk[i] = pick_slot<FILT>(t[i], ctx, hx, hy);
     }
     if (more) uv_next = load_uv(a, P.px, P.py + kTile);
-    if constexpr (SHR) {
-        static_assert(MODE == kModeRecords && !DEC && !EF, "shared records: record footprints without a decoder");
-        shared_records_pass<FILT, NT>(a, t, P, ctx, pk, lds, lut_lds);   // ctx: slot 0's size, every slot's
+    if constexpr (SHR) {                             // ctx: slot 0's size, every slot's
+        static_assert((MODE == kModeRecords || MODE == kModeQuad) && !DEC && !EF, "shared selection kernels");
+        if constexpr (MODE == kModeQuad) shared_quad_pass<FILT, NT>(a, t, P, ctx, pk);
+        else shared_records_pass<FILT, NT>(a, t, P, ctx, pk, lds, lut_lds);
         return;
     }
     BinGeom<AxisCtx<FILT>::N> geom;
@@ -1141,6 +1233,17 @@ __global__ __launch_bounds__(kThreads) void shared_records_kernel(Args a) {
     v2f next;                                  // no next tile
     forward_tile<FILT, kModeRecords, NT, false, false, true>(a, P, lds, nullptr, false, next,
                                                              staged ? lut_lds : nullptr);
+}
+
+// 2x2 quads over two to four textures of one size under shared selection:
+// one support test and weight per partner for every slot (a kernel of its
+// own for the same reason).
+template <int FILT, int NT>
+__global__ __launch_bounds__(kThreads) void shared_quad_kernel(Args a) {
+    Pixel P;
+    if (!setup_pixel(a, P)) return;
+    v2f next;                                  // no next tile
+    forward_tile<FILT, kModeQuad, NT, false, false, true>(a, P, nullptr, nullptr, false, next);
 }
 
 // ---------------------------------------------------------------- comparison estimators
@@ -1444,6 +1547,16 @@ void launch_nt(const Args& a, hipStream_t s) {
         if (one_pick) {
             if (a.ntex == 2) hipLaunchKernelGGL((shared_records_kernel<FILT, 2>), g, b, 0, s, a);
             else hipLaunchKernelGGL((shared_records_kernel<FILT, 3>), g, b, 0, s, a);
+            return;
+        }
+    }
+    if constexpr (MODE == kModeQuad && !DEC && !EF) {
+        bool one_pick = a.ntex >= 2;
+        for (int i = 1; i < a.ntex; ++i) one_pick = one_pick && a.leader[i] == 0;
+        if (one_pick) {
+            if (a.ntex == 2) hipLaunchKernelGGL((shared_quad_kernel<FILT, 2>), g, b, 0, s, a);
+            else if (a.ntex == 3) hipLaunchKernelGGL((shared_quad_kernel<FILT, 3>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((shared_quad_kernel<FILT, 4>), g, b, 0, s, a);
             return;
         }
     }

@@ -80,15 +80,17 @@ def test_shared_selection_adjoint_and_estimators():
 
 
 def one_size_textures(n):
-    """Two or three textures of one size (64^2), so every slot takes slot 0's
-    picks: the record footprints then run the fused kernel. Three: RGBA16F,
-    RG16F and BF16 RGBA with a per-channel scale; two: RGBA32F and R8."""
+    """Two to four textures of one size (64^2), so every slot takes slot 0's
+    picks: the quad and record footprints then run the one-size kernels.
+    Three: RGBA16F, RG16F and BF16 RGBA with a per-channel scale; four: those
+    and R8; two: RGBA32F and R8."""
     rng = np.random.default_rng(21)
-    if n == 3:
+    if n >= 3:
         vals = rng.random((64, 64, 4)) * np.array([1.0, 4.0, 0.25, 2.0]) - 0.3
         scale = np.array([0.5, 2.0, 0.125, 1.0])
         bf = (w.quantize(vals, "bf16", scale), "bf16", scale)
-        return [rng.random((64, 64, 4)).astype(np.float16), (rng.random((64, 64, 2)) * 2 - 1).astype(np.float16), bf]
+        three = [rng.random((64, 64, 4)).astype(np.float16), (rng.random((64, 64, 2)) * 2 - 1).astype(np.float16), bf]
+        return three + [rng.integers(0, 256, (64, 64, 1), dtype=np.uint8)] * (n - 3)
     return [rng.random((64, 64, 4)).astype(np.float32), rng.integers(0, 256, (64, 64, 1), dtype=np.uint8)]
 
 
@@ -114,14 +116,16 @@ def footprint_case(fp):
     return "lut", lut
 
 
-@pytest.mark.parametrize("fp", ["wave2x2", "square3x3", "square4x4", "lut9", "lut24"])
+@pytest.mark.parametrize("fp", ["quad2x2", "wave2x2", "square3x3", "square4x4", "lut9", "lut24"])
 @pytest.mark.parametrize("filt", ["bilinear", "bicubic"])
-@pytest.mark.parametrize("n", [2, 3])
-def test_shared_records_kernel(n, filt, fp):
-    """Record footprints over textures of one size under shared selection:
-    one support test and weight per member serves every slot. Parity with
-    the oracle (selection bit-exact, colours within 1e-5), and the same bits
-    as the per-slot kernel, which a fourth texture of that size selects."""
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_one_size_shared_selection_kernels(n, filt, fp):
+    """Quads and record footprints over textures of one size under shared
+    selection: one support test and weight per member serves every slot.
+    Parity with the oracle (selection bit-exact, colours within 1e-5), and
+    the same bits as the per-slot kernel, which an added texture of another
+    size selects. Four textures (oracle parity only): the quads' one-size
+    kernel, and the per-slot record kernel, whose records would not fit."""
     texs = one_size_textures(n)
     name, lut = footprint_case(fp)
     uv = w.small_screen(90, 58, 64, 4.0, offset_seed=5)      # ragged tiles
@@ -138,8 +142,11 @@ def test_shared_records_kernel(n, filt, fp):
         T = np.abs(vals)
         tol = REL * np.maximum(np.abs(image(rv, uv)), T.max()) + 1e-30
         assert np.all(np.abs(outs[k].cpu().numpy().astype(np.float64) - image(rv, uv)) <= tol), k
-    # four textures of the size: the per-slot kernel, same picks, same arithmetic per slot
-    per_slot = stf.filter_reuse(dt + [dt[0]] * (4 - n), duv, name, filt, 7, 3, lut=lut_t,
-                                scales=sc + [sc[0]] * (4 - n), share_selection=True)
+    if n == 4:
+        return
+    # a texture of another size added: the per-slot kernel, same picks, same arithmetic per slot
+    other = dev(np.random.default_rng(4).random((32, 32, 4)).astype(np.float16))
+    per_slot = stf.filter_reuse(dt + [other], duv, name, filt, 7, 3, lut=lut_t, scales=sc + [None],
+                                share_selection=True)
     for k in range(n):
         assert torch.equal(outs[k], per_slot[k]), k
