@@ -94,6 +94,15 @@ def one_size_textures(n):
     return [rng.random((64, 64, 4)).astype(np.float32), rng.integers(0, 256, (64, 64, 1), dtype=np.uint8)]
 
 
+def bin_textures(n):
+    """Two to four textures of one size with the bins' half-precision and
+    one-channel payloads (RGBA16F, RG16F, R8, R32F)."""
+    rng = np.random.default_rng(22)
+    ts = [rng.random((64, 64, 4)).astype(np.float16), (rng.random((64, 64, 2)) * 2 - 1).astype(np.float16),
+          rng.integers(0, 256, (64, 64, 1), dtype=np.uint8), rng.random((64, 64, 1)).astype(np.float32)]
+    return ts[:n]
+
+
 def device_inputs(texs):
     dt, sc = [], []
     for t in texs:
@@ -116,7 +125,8 @@ def footprint_case(fp):
     return "lut", lut
 
 
-@pytest.mark.parametrize("fp", ["quad2x2", "wave2x2", "square3x3", "square4x4", "lut9", "lut24"])
+@pytest.mark.parametrize("fp", ["quad2x2", "wave2x2", "square3x3", "square4x4", "lut9", "lut24", "tile8x8", "bins",
+                                "bins_minified"])
 @pytest.mark.parametrize("filt", ["bilinear", "bicubic"])
 @pytest.mark.parametrize("n", [2, 3, 4])
 def test_one_size_shared_selection_kernels(n, filt, fp):
@@ -125,10 +135,14 @@ def test_one_size_shared_selection_kernels(n, filt, fp):
     Parity with the oracle (selection bit-exact, colours within 1e-5), and
     the same bits as the per-slot kernel, which an added texture of another
     size selects. Four textures (oracle parity only): the quads' one-size
-    kernel, and the per-slot record kernel, whose records would not fit."""
-    texs = one_size_textures(n)
-    name, lut = footprint_case(fp)
-    uv = w.small_screen(90, 58, 64, 4.0, offset_seed=5)      # ragged tiles
+    kernel, and the per-slot record kernel, whose records would not fit.
+    The whole tile keeps its per-slot bins ('tile8x8': texels of 16 bytes;
+    'bins': RGBA16F, RG16F, R8 and R32F; 'bins_minified': waves whose
+    supports leave the bin window take the records)."""
+    texs = bin_textures(n) if fp.startswith("bins") else one_size_textures(n)
+    name, lut = footprint_case("tile8x8" if fp.startswith("bins") else fp)
+    mag = 1 / 1.5 if fp == "bins_minified" else 4.0
+    uv = w.small_screen(90, 58, 64, mag, offset_seed=5)      # ragged tiles
     ftag = o.BICUBIC if filt == "bicubic" else o.BILINEAR
     dt, sc = device_inputs(texs)
     duv = dev(uv)
