@@ -781,6 +781,11 @@ __device__ __forceinline__ void texel_floats(const TexArg& t, const SlotPick& pk
     for (int c = 0; c < Texel<PL>::C; ++c) v[c] = T.ch(c);
 }
 
+// LDS floats per wave of the one-size record kernel: {s, r}[64], then one
+// float4 texel per lane and slot.
+template <int NT>
+constexpr int kSharedRecordFloats = 128 + NT * 256;
+
 // Record footprints under shared selection, every slot led by slot 0 (one
 // texture size, Sec. 4.5): all slots pick the same texel, so the support
 // test and weight w_i = f_c(x_i) / p_i of a member are formed once and
@@ -791,7 +796,7 @@ template <int FILT, int NT>
 __device__ __forceinline__ void shared_records_pass(const Args& a, const TexArg (&t)[NT], const Pixel& P,
                                                     const SelCtx<FILT>& ctx, const SlotPick (&pk)[NT], float* lds,
                                                     const uint8_t* lut_lds) {
-    static_assert(NT >= 2 && 128 + NT * 256 <= kLdsFloatsPerWave, "every slot's records fit the wave's LDS");
+    static_assert(NT >= 2 && NT <= 4, "two to four slots");
     constexpr int N = SelCtx<FILT>::N;
     const uint32_t mx = (uint32_t)t[0].w - 1u, my = (uint32_t)t[0].h - 1u;
     const int kx = pk[0].kx, ky = pk[0].ky;
@@ -1089,15 +1094,19 @@ __device__ __forceinline__ void forward_tile(const Args& a, Pixel& P, float* lds
 }
 
 // One-tap STF without a decoder exchanges nothing between lanes, so it does
-// not need 8x8 tiles: its waves take kOneTapPixels runs of 64 consecutive
+// not need 8x8 tiles: its waves take kOneTapPixels<NT> runs of 64 consecutive
 // pixels of one screen row, whose UV reads and output writes are contiguous
 // (whole cache lines, where an 8x8 tile writes 8-pixel row pieces: half lines
 // of RG32F). Each lane carries its pixels through the phases together --
 // every UV, then every pick and texel request, then every decode and store
 // -- so that a wave has that many times the loads of one pixel in flight.
+// Two pixels per lane, one with four textures, whose picks already keep four
+// texel requests per pixel in flight (3840x2160: 124 instead of 128 us).
 template <int MODE, bool DEC>
 constexpr bool kRowLinear = MODE == kModeStf && !DEC;
-constexpr int kOneTapPixels = 2;
+template <int NT>
+constexpr int kOneTapPixels = NT >= 4 ? 1 : 2;
+inline int onetap_pixels(int ntex) { return ntex >= 4 ? 1 : 2; }
 
 template <int FILT, int NT, int K>
 __device__ __forceinline__ void onetap_pixels(const Args& a, const Pixel (&P)[K]) {
@@ -1144,7 +1153,7 @@ __device__ __forceinline__ void onetap_pixels(const Args& a, const Pixel (&P)[K]
 
 // Workgroup (x, y) filters tile columns 4x .. 4x+3 (one per wave) over tile
 // rows kForwardRows<DEC> * y onward; row-linear kernels: pixels
-// 256 K x .. 256 K (x + 1) - 1 of screen row y (K = kOneTapPixels).
+// 256 K x .. 256 K (x + 1) - 1 of screen row y (K = kOneTapPixels<NT>).
 template <int FILT, int MODE, int NT, bool DEC, bool EF>
 __global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, NT, DEC, EF>)) void forward_kernel(Args a) {
     // per-wave LDS: records or bins; with a decoder also the deduplicating decode's scratch
@@ -1166,7 +1175,7 @@ __global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, NT, DEC, EF>)) void 
         __syncthreads();
     }
     if constexpr (kRowLinear<MODE, DEC>) {
-        constexpr int K = kOneTapPixels;
+        constexpr int K = kOneTapPixels<NT>;
         const int x0 = (blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6)) * (64 * K);
         if (x0 >= a.sw) return;                // whole wave off screen
         Pixel P[K];
@@ -1213,14 +1222,14 @@ __global__ __launch_bounds__(kThreads, (kForwardWaves<MODE, NT, DEC, EF>)) void 
     }
 }
 
-// Record footprints (2x2w, 3x3, 4x4, tables) over two or three textures of
+// Record footprints (2x2w, 3x3, 4x4, tables) over two to four textures of
 // one size under shared selection: one support test and weight per member
 // for every slot. A kernel of its own, so that the independent-selection
-// kernels keep their register counts; one tile per wave, laid out as in
-// forward_kernel.
+// kernels keep their register counts, with its own LDS share per wave; one
+// tile per wave, laid out as in forward_kernel.
 template <int FILT, int NT>
 __global__ __launch_bounds__(kThreads) void shared_records_kernel(Args a) {
-    __shared__ __align__(16) float lds_all[kWavesPerGroup * kLdsFloatsPerWave];
+    __shared__ __align__(16) float lds_all[kWavesPerGroup * kSharedRecordFloats<NT>];
     __shared__ uint8_t lut_lds[64 * kLutStageMax];
     const bool staged = a.footprint == STF_FP_LUT && a.lut_k <= kLutStageMax;
     if (staged) {                              // uniform over the launch; before any wave can leave
@@ -1229,7 +1238,7 @@ __global__ __launch_bounds__(kThreads) void shared_records_kernel(Args a) {
     }
     Pixel P;
     if (!setup_pixel(a, P)) return;
-    float* lds = lds_all + (threadIdx.x >> 6) * kLdsFloatsPerWave;
+    float* lds = lds_all + (threadIdx.x >> 6) * kSharedRecordFloats<NT>;
     v2f next;                                  // no next tile
     forward_tile<FILT, kModeRecords, NT, false, false, true>(a, P, lds, nullptr, false, next,
                                                              staged ? lut_lds : nullptr);
@@ -1528,11 +1537,13 @@ inline dim3 grid_of(const Args& a) {
 }
 
 // Forward kernels: kForwardRows<DEC> tile rows per workgroup, or 256
-// kOneTapPixels pixels of one screen row.
+// kOneTapPixels<NT> pixels of one screen row.
 template <int MODE, bool DEC>
 inline dim3 grid_forward(const Args& a) {
-    if constexpr (kRowLinear<MODE, DEC>)
-        return dim3((unsigned)((a.sw + kThreads * kOneTapPixels - 1) / (kThreads * kOneTapPixels)), (unsigned)a.sh);
+    if constexpr (kRowLinear<MODE, DEC>) {
+        const int k = onetap_pixels(a.ntex);
+        return dim3((unsigned)((a.sw + kThreads * k - 1) / (kThreads * k)), (unsigned)a.sh);
+    }
     const int rows = (a.sh + kTile - 1) / kTile;
     return dim3((unsigned)((a.sw + kTile * kWavesPerGroup - 1) / (kTile * kWavesPerGroup)),
                 (unsigned)((rows + kForwardRows<DEC> - 1) / kForwardRows<DEC>));
@@ -1542,11 +1553,12 @@ template <int FILT, int MODE, bool DEC, bool EF>
 void launch_nt(const Args& a, hipStream_t s) {
     const dim3 g = grid_forward<MODE, DEC>(a), b(kThreads);
     if constexpr (MODE == kModeRecords && !DEC && !EF) {
-        bool one_pick = a.ntex == 2 || a.ntex == 3;        // every slot takes slot 0's selection
+        bool one_pick = a.ntex >= 2;                      // every slot takes slot 0's selection
         for (int i = 1; i < a.ntex; ++i) one_pick = one_pick && a.leader[i] == 0;
         if (one_pick) {
             if (a.ntex == 2) hipLaunchKernelGGL((shared_records_kernel<FILT, 2>), g, b, 0, s, a);
-            else hipLaunchKernelGGL((shared_records_kernel<FILT, 3>), g, b, 0, s, a);
+            else if (a.ntex == 3) hipLaunchKernelGGL((shared_records_kernel<FILT, 3>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((shared_records_kernel<FILT, 4>), g, b, 0, s, a);
             return;
         }
     }

@@ -134,8 +134,7 @@ def test_one_size_shared_selection_kernels(n, filt, fp):
     selection: one support test and weight per member serves every slot.
     Parity with the oracle (selection bit-exact, colours within 1e-5), and
     the same bits as the per-slot kernel, which an added texture of another
-    size selects. Four textures (oracle parity only): the quads' one-size
-    kernel, and the per-slot record kernel, whose records would not fit.
+    size selects (four textures: oracle parity only).
     The whole tile keeps its per-slot bins ('tile8x8': texels of 16 bytes;
     'bins': RGBA16F, RG16F, R8 and R32F; 'bins_minified': waves whose
     supports leave the bin window take the records)."""
