@@ -26,13 +26,17 @@ def _call(kind, texs, uv, outs, seed):
         stf.filter_reuse(texs, uv, "tile8x8", "bicubic", seed, 0, out=outs)
     elif kind == "quad":
         stf.filter_reuse(texs, uv, "quad2x2", "bilinear", seed, 1, out=outs)
+    elif kind == "quad_shared":                    # both textures 256^2: the one-size quad kernel
+        stf.filter_reuse(texs, uv, "quad2x2", "bilinear", seed, 1, out=outs, share_selection=True)
+    elif kind == "records_shared":                 # the one-size record kernel
+        stf.filter_reuse(texs, uv, "square3x3", "bicubic", seed, 1, out=outs, share_selection=True)
     elif kind == "stf":
         stf.filter(texs, uv, "bicubic", seed, 0, out=outs)
     else:
         stf.filter_reference(texs, uv, "bicubic", out=outs)
 
 
-@pytest.mark.parametrize("kind", ["reuse", "quad", "stf", "reference"])
+@pytest.mark.parametrize("kind", ["reuse", "quad", "stf", "reference", "quad_shared", "records_shared"])
 def test_graph_replays_equal_eager(kind):
     uv, texs = _inputs()
     H, W = uv.shape[:2]
